@@ -1,0 +1,129 @@
+"""Seeded synthetic input generators shared by the tests, the oracle checks and the benchmark.
+
+This module produces *coordinates and values only*: per-entry mode coordinates (an
+``(nnz, order)`` uint64 array, unsorted) and FP64 values.  It holds none of the
+method's arithmetic -- no linearisation, no sorting by linearised index, no
+products -- so both the oracle and the HIP path start from exactly the same raw
+input and each does its own linearisation.
+
+Workloads (all synthetic, seeded, shaped like the paper's benchmark operators):
+
+* ``fd_laplacian(side, dim)`` -- the finite-difference Laplacian on a ``side**dim``
+  grid with Dirichlet boundary (neighbours outside the grid are dropped), as a
+  tensor of order ``2*dim``: the first ``dim`` modes are the output grid point,
+  the last ``dim`` modes the input grid point.  Centre value ``-2*dim``, each
+  in-grid neighbour ``1``.  This is the high-order differential operator of the
+  paper's Section 2 (the combinatorial Laplacian built from FD matrices),
+  in its standard 5-point (2-D) / 7-point (3-D) form.
+* ``kronecker_hypersparse(bits, draws, seed)`` -- a 4-mode Kronecker (R-MAT style)
+  tensor with ``2**bits`` per mode: each draw picks, for every bit level and each
+  mode pair (0,1), (2,3), one of four quadrants with probabilities
+  ``[0.57, 0.19, 0.19, 0.05]``; values uniform(-1, 1).  Duplicated coordinates
+  are left in (the consumer sums them on construction).  This is the recursive
+  quadrant model that the paper's R-TENSOR generalises (Section 5.2.1).
+* ``random_sparse(rng, dims, nnz)`` -- distinct uniformly random coordinates.
+* ``diagonal(order, n)`` -- the purely diagonal tensor of the paper's Figure on
+  hyper-sparsity of matricised tensors (all-zero except i=j=...).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "fd_laplacian",
+    "kronecker_hypersparse",
+    "random_sparse",
+    "diagonal",
+    "KRON_PROBS",
+]
+
+KRON_PROBS = (0.57, 0.19, 0.19, 0.05)
+
+
+def fd_laplacian(side: int, dim: int):
+    """Coordinates and values of the ``dim``-D FD Laplacian on a ``side**dim`` grid.
+
+    Returns ``(coords, vals)`` with ``coords`` of shape ``(nnz, 2*dim)`` (uint64):
+    modes ``0..dim-1`` are the row grid point (x, y[, z]) and modes
+    ``dim..2*dim-1`` the column grid point.  ``nnz = (2*dim+1)*side**dim -
+    2*dim*side**(dim-1)``.
+    """
+    if side < 1 or dim < 1:
+        raise ValueError("side and dim must be >= 1")
+    axes = np.meshgrid(*[np.arange(side, dtype=np.int64)] * dim, indexing="ij")
+    pts = np.stack([a.reshape(-1) for a in axes], axis=1)  # (side**dim, dim)
+    coords = [np.concatenate([pts, pts], axis=1)]
+    vals = [np.full(pts.shape[0], -2.0 * dim)]
+    for ax in range(dim):
+        for step in (-1, 1):
+            nb = pts.copy()
+            nb[:, ax] += step
+            keep = (nb[:, ax] >= 0) & (nb[:, ax] < side)
+            coords.append(np.concatenate([pts[keep], nb[keep]], axis=1))
+            vals.append(np.ones(int(keep.sum())))
+    return (np.ascontiguousarray(np.concatenate(coords).astype(np.uint64)),
+            np.concatenate(vals).astype(np.float64))
+
+
+def kronecker_hypersparse(bits: int, draws: int, seed: int, probs=KRON_PROBS):
+    """Order-4 Kronecker tensor, ``2**bits`` per mode, ``draws`` quadrant draws.
+
+    For each bit level ``b`` (low to high) and each mode pair ((0,1), then (2,3)) a
+    uniform number picks quadrant ``q`` from the cumulative probabilities; the
+    pair's first mode gets bit ``q >> 1`` and the second bit ``q & 1`` at level
+    ``b``.  Values are drawn afterwards, uniform in (-1, 1).  Duplicate
+    coordinates are kept.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cum = np.cumsum(np.asarray(probs, dtype=np.float64))
+    coords = np.zeros((draws, 4), dtype=np.uint64)
+    for b in range(bits):
+        for (m0, m1) in ((0, 1), (2, 3)):
+            u = rng.random(draws)
+            q = np.searchsorted(cum, u, side="right").astype(np.uint64)
+            coords[:, m0] |= (q >> np.uint64(1)) << np.uint64(b)
+            coords[:, m1] |= (q & np.uint64(1)) << np.uint64(b)
+    vals = rng.uniform(-1.0, 1.0, draws)
+    return coords, vals
+
+
+def random_sparse(rng: np.random.Generator, dims, nnz: int, integer_values: bool = False):
+    """``nnz`` distinct uniformly random coordinates in ``dims`` (fewer if the space is smaller).
+
+    Values are uniform(-1, 1), or small integers in [-4, 4] \\ {0} when
+    ``integer_values`` (useful where exact sums are wanted).
+    """
+    dims = [int(d) for d in dims]
+    order = len(dims)
+    if order == 0:
+        n = min(nnz, 1)
+        coords = np.zeros((n, 0), dtype=np.uint64)
+    else:
+        total = 1
+        for d in dims:
+            total *= d
+        nnz = min(nnz, total)
+        if nnz == 0:
+            coords = np.zeros((0, order), dtype=np.uint64)
+        else:
+            got = np.zeros((0, order), dtype=np.uint64)
+            while got.shape[0] < nnz:
+                need = (nnz - got.shape[0]) * 2 + 8
+                cand = np.stack([rng.integers(0, d, need, dtype=np.uint64) for d in dims], axis=1)
+                got = np.unique(np.concatenate([got, cand]), axis=0)
+            pick = rng.permutation(got.shape[0])[:nnz]
+            coords = np.ascontiguousarray(got[pick])
+    n = coords.shape[0]
+    if integer_values:
+        v = rng.integers(1, 5, n).astype(np.float64) * rng.choice([-1.0, 1.0], n)
+    else:
+        v = rng.uniform(-1.0, 1.0, n)
+    return coords, v
+
+
+def diagonal(order: int, n: int, values=None):
+    """The diagonal tensor of order ``order`` with ``n`` per mode (entries where all coordinates agree)."""
+    c = np.arange(n, dtype=np.uint64)
+    coords = np.ascontiguousarray(np.stack([c] * order, axis=1))
+    vals = np.arange(1, n + 1, dtype=np.float64) if values is None else np.asarray(values, dtype=np.float64)
+    return coords, vals

@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: the worked LIV
+example printed in the paper, dense brute force (numpy transpose / einsum /
+matmul on tiny tensors), closed-form finite-difference stencils, involutions and
+exhaustively enumerated index matchings.  None of them calls the HIP library.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import lco_inputs as L
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_of(t):
+    """Dense array of an oracle tensor, decoding LIVs with plain numpy div/mod."""
+    dims = [int(d) for d in t.dims]
+    out = np.zeros(dims if dims else (), dtype=np.float64)
+    rem = t.livs.copy()
+    idx = []
+    for d in dims:
+        idx.append((rem % np.uint64(d)).astype(np.int64))
+        rem = rem // np.uint64(d)
+    if dims:
+        out[tuple(idx)] = t.vals
+    elif t.nnz:
+        out[()] = t.vals[0]
+    return out
+
+
+def dense_from_coords(dims, coords, vals):
+    out = np.zeros([int(d) for d in dims], dtype=np.float64)
+    np.add.at(out, tuple(coords[:, r].astype(np.int64) for r in range(len(dims))), vals)
+    return out
+
+
+# ---------------------------------------------------------------- LIV codec
+def test_table_sparse_formats_example(oracle_mod):
+    """Section 3.1, Table on CO vs LCO formats: 4x4x4 example LIVs 1, 18, 20, 43, 49, 58."""
+    rows = []
+    dims = None
+    for line in open(os.path.join(GOLDEN, "table_sparse_formats.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        if line.startswith("dims"):
+            dims = [int(x) for x in line.split()[1:]]
+            continue
+        rows.append([int(x) for x in line.split()])
+    rows = np.array(rows, dtype=np.uint64)
+    livs = oracle_mod.linearise(dims, rows[:, :3])
+    assert livs.tolist() == rows[:, 3].tolist()
+    back = oracle_mod.delinearise(dims, livs)
+    assert np.array_equal(back, rows[:, :3])
+
+
+def test_liv_full_64bit_range(oracle_mod):
+    """Unsigned LIVs cover a product of dims of exactly 2^64 (dims (2^16)^4)."""
+    dims = [1 << 16] * 4
+    c = np.array([[65535] * 4, [0, 0, 0, 1], [1, 0, 0, 0], [12345, 54321, 7, 65535]], dtype=np.uint64)
+    livs = oracle_mod.linearise(dims, c)
+    expect = [sum(int(x) << (16 * r) for r, x in enumerate(row)) for row in c]
+    assert [int(v) for v in livs] == expect
+    assert int(livs[0]) == 2**64 - 1
+    assert np.array_equal(oracle_mod.delinearise(dims, livs), c)
+
+
+def test_overflow_rejected(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.linearise([1 << 32, (1 << 32) + 1], [[0, 0]])
+    assert e.value.code == 2
+    oracle_mod.linearise([1 << 32, 1 << 32], [[0, 0]])
+
+
+# ---------------------------------------------------------------- construction
+def test_create_sums_duplicates_in_input_order(oracle_mod):
+    rng = np.random.default_rng(7)
+    dims = [3, 4, 2]
+    coords = np.stack([rng.integers(0, d, 200) for d in dims], axis=1).astype(np.uint64)
+    vals = rng.uniform(-1, 1, 200)
+    t = oracle_mod.create(dims, coords, vals, sum_duplicates=True)
+    # brute force: python dict in input order, keys ordered by (k, j, i)
+    acc = {}
+    for c, v in zip(coords.tolist(), vals.tolist()):
+        key = (c[2], c[1], c[0])
+        acc[key] = acc[key] + v if key in acc else v
+    keys = sorted(acc)
+    assert t.nnz == len(keys)
+    assert t.livs.tolist() == [k[2] + 3 * (k[1] + 4 * k[0]) for k in keys]
+    assert t.vals.tolist() == [acc[k] for k in keys]  # bit-exact: same order of addition
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.create(dims, coords, vals, sum_duplicates=False)
+    assert e.value.code == 5
+
+
+def test_create_rejects_out_of_range(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.create([2, 2], np.array([[0, 2]], np.uint64), [1.0])
+
+
+# ---------------------------------------------------------------- permutation
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_permute_vs_dense_transpose_all_perms(oracle_mod, order):
+    rng = np.random.default_rng(100 + order)
+    dims = [int(x) for x in rng.integers(1, 6, order)]
+    coords, vals = L.random_sparse(rng, dims, 40)
+    t = oracle_mod.create(dims, coords, vals)
+    dense = dense_from_coords(dims, coords, vals)
+    for perm in itertools.permutations(range(order)):
+        p = oracle_mod.permute(t, perm)
+        assert p.dims.tolist() == [dims[q] for q in perm]
+        assert p.nnz == t.nnz
+        assert np.all(np.diff(p.livs.astype(np.float64)) > 0) or p.nnz < 2
+        assert np.array_equal(dense_of(p), np.transpose(dense, perm))
+
+
+def test_permute_involution_and_inverse(oracle_mod):
+    rng = np.random.default_rng(5)
+    dims = [5, 3, 4, 6]
+    coords, vals = L.random_sparse(rng, dims, 150)
+    t = oracle_mod.create(dims, coords, vals)
+    swap = [2, 3, 0, 1]
+    p = oracle_mod.permute(oracle_mod.permute(t, swap), swap)
+    assert np.array_equal(p.livs, t.livs) and np.array_equal(p.vals, t.vals)
+    for perm in itertools.permutations(range(4)):
+        inv = list(np.argsort(perm))
+        q = oracle_mod.permute(oracle_mod.permute(t, perm), inv)
+        assert np.array_equal(q.livs, t.livs) and np.array_equal(q.vals, t.vals)
+
+
+def test_permute_symmetric_fd_operator_is_fixed_point(oracle_mod):
+    """The FD Laplacian is symmetric, so swapping row and column modes reproduces it exactly."""
+    c, v = L.fd_laplacian(6, 3)
+    t = oracle_mod.create([6] * 6, c, v)
+    p = oracle_mod.permute(t, [3, 4, 5, 0, 1, 2])
+    assert np.array_equal(p.livs, t.livs) and np.array_equal(p.vals, t.vals)
+
+
+# ---------------------------------------------------------------- contraction
+def partial_permutation_count(n):
+    """Section 3.1: number of inner/outer index matchings of two order-n tensors."""
+    return sum(math.factorial(i) * math.comb(n, i) ** 2 for i in range(n + 1))
+
+
+def matchings(n):
+    """All partial bijections between the modes of two order-n tensors."""
+    out = []
+    for i in range(n + 1):
+        for sa in itertools.combinations(range(n), i):
+            for sb in itertools.permutations(range(n), i):
+                out.append(list(zip(sa, sb)))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_all_matchings_vs_einsum(oracle_mod, n):
+    assert len(matchings(n)) == partial_permutation_count(n)
+    assert [partial_permutation_count(k) for k in (1, 2, 3, 4)] == [2, 7, 34, 209]
+    rng = np.random.default_rng(10 + n)
+    letters = "abcdefghij"
+    for mi, match in enumerate(matchings(n)):
+        dims_a = [int(x) for x in rng.integers(1, 5, n)]
+        dims_b = [int(x) for x in rng.integers(1, 5, n)]
+        for (ia, ib) in match:
+            dims_b[ib] = dims_a[ia]
+        ca, va = L.random_sparse(rng, dims_a, 12, integer_values=True)
+        cb, vb = L.random_sparse(rng, dims_b, 12, integer_values=True)
+        a = oracle_mod.create(dims_a, ca, va)
+        b = oracle_mod.create(dims_b, cb, vb)
+        la = list(range(n))
+        lb = [n + j for j in range(n)]
+        for (ia, ib) in match:
+            lb[ib] = la[ia]
+        matched_a = {ia for ia, _ in match}
+        matched_b = {ib for _, ib in match}
+        lc = [la[i] for i in range(n) if i not in matched_a] + [lb[j] for j in range(n) if j not in matched_b]
+        if mi % 2:
+            lc = lc[::-1]  # exercise a non-default output order too
+        c = oracle_mod.contract(a, la, b, lb, lc)
+        spec = "".join(letters[x] for x in la) + "," + "".join(letters[x] for x in lb) + "->" + \
+            "".join(letters[x] for x in lc)
+        Da = dense_from_coords(dims_a, ca, va)
+        Db = dense_from_coords(dims_b, cb, vb)
+        expect = np.einsum(spec, Da, Db)
+        got = dense_of(c)
+        assert np.array_equal(got, expect), (match, lc)
+        # structural pattern: positions reached by at least one product
+        patt = np.einsum(spec, (Da != 0).astype(np.float64), (Db != 0).astype(np.float64)) > 0
+        got_patt = np.zeros_like(patt)
+        if c.nnz and patt.ndim:
+            got_patt[np.unravel_index(c.livs.astype(np.int64), patt.shape, order="F")] = True
+        elif c.nnz:
+            got_patt[()] = True
+        assert np.array_equal(got_patt, patt)
+
+
+def test_map_and_sort_modes_agree(oracle_mod):
+    rng = np.random.default_rng(3)
+    dims = [7, 5, 6]
+    ca, va = L.random_sparse(rng, dims, 120)
+    cb, vb = L.random_sparse(rng, [6, 5, 4], 90)
+    a = oracle_mod.create(dims, ca, va)
+    b = oracle_mod.create([6, 5, 4], cb, vb)
+    m = oracle_mod.contract(a, [0, 1, 2], b, [2, 1, 3], [3, 0])
+    s = oracle_mod.contract(a, [0, 1, 2], b, [2, 1, 3], [3, 0], mode="sort")
+    assert np.array_equal(m.livs, s.livs) and np.array_equal(m.vals, s.vals)
+    assert np.array_equal(m.absum, s.absum)
+
+
+def test_contract_errors(oracle_mod):
+    a = oracle_mod.create([3, 4], np.array([[0, 0]], np.uint64), [1.0])
+    b = oracle_mod.create([5, 2], np.array([[0, 0]], np.uint64), [1.0])
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.contract(a, [0, 1], b, [1, 2], [0, 2])
+    assert e.value.code == 3  # contracted dims 4 vs 5
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.contract(a, [0, 1], b, [0, 2], [0, 1, 2])
+    assert e.value.code == 7  # entrywise label
+
+
+def test_diagonal_products(oracle_mod):
+    """Diagonal tensors (Section 5.1 hyper-sparsity figure): products stay diagonal."""
+    n = 10
+    c, v = L.diagonal(4, n)
+    a = oracle_mod.create([n] * 4, c, v)
+    # a_ijkl a_klmn (2+2 split: index-sparse) -> diagonal with squared values
+    r = oracle_mod.contract(a, [0, 1, 2, 3], a, [2, 3, 4, 5], [0, 1, 4, 5])
+    assert r.nnz == n
+    assert np.array_equal(r.vals, v * v)
+    assert np.array_equal(oracle_mod.delinearise(r.dims, r.livs), np.stack([np.arange(n)] * 4, 1).astype(np.uint64))
+    # a_ijkl a_jklm (1+3 / 3+1 splits: column- and row-sparse)
+    r = oracle_mod.contract(a, [0, 1, 2, 3], a, [1, 2, 3, 4], [0, 4])
+    assert r.nnz == n and np.array_equal(r.vals, v * v)
+
+
+# ------------------------------------------------- closed-form FD compositions
+def _squared_laplacian_check(t, side, dim):
+    """Closed form of (Dirichlet FD Laplacian)^2 entries.
+
+    With L = -2d on the diagonal and 1 for in-grid neighbours:
+    diagonal = 4d^2 + deg(p); |q-p| = 1 -> -4d; two unit steps on different
+    axes -> 2; two unit steps on one axis -> 1.
+    """
+    co = np.stack(np.unravel_index(t.livs.astype(np.int64), [side] * (2 * dim), order="F"), 1)
+    p, q = co[:, :dim], co[:, dim:]
+    d = q - p
+    l1 = np.abs(d).sum(1)
+    deg = np.zeros(len(p), np.int64)
+    for ax in range(dim):
+        deg += (p[:, ax] > 0).astype(np.int64) + (p[:, ax] < side - 1).astype(np.int64)
+    expect = np.where(l1 == 0, 4 * dim * dim + deg,
+                      np.where(l1 == 1, -4 * dim,
+                               np.where(np.abs(d).max(1) == 2, 1, 2))).astype(np.float64)
+    assert np.all(l1 <= 2)
+    assert np.array_equal(t.vals, expect)
+
+
+def biharmonic_nnz(s):
+    return s * s + 4 * s * (s - 1) + 4 * (s - 1) ** 2 + 4 * s * (s - 2)
+
+
+def squared_laplacian_3d_nnz(s):
+    return s**3 + 6 * s * s * (s - 1) + 12 * s * (s - 1) ** 2 + 6 * s * s * (s - 2)
+
+
+@pytest.mark.parametrize("side", [2, 3, 5, 32])
+def test_biharmonic_closed_form(oracle_mod, side):
+    c, v = L.fd_laplacian(side, 2)
+    assert len(v) == 5 * side * side - 4 * side
+    t = oracle_mod.create([side] * 4, c, v)
+    r = oracle_mod.contract(t, [0, 1, 2, 3], t, [2, 3, 4, 5], [0, 1, 4, 5])
+    assert r.nnz == biharmonic_nnz(side)
+    _squared_laplacian_check(r, side, 2)
+    if side >= 3:
+        # interior rows carry the 13-point biharmonic stencil 20 / -8 / 2 / 1
+        assert set(np.unique(r.vals)) >= {20.0, -8.0, 2.0, 1.0}
+
+
+@pytest.mark.parametrize("side", [2, 4, 7])
+def test_squared_3d_laplacian_closed_form(oracle_mod, side):
+    c, v = L.fd_laplacian(side, 3)
+    assert len(v) == 7 * side**3 - 6 * side**2
+    t = oracle_mod.create([side] * 6, c, v)
+    r = oracle_mod.contract(t, [0, 1, 2, 3, 4, 5], t, [3, 4, 5, 6, 7, 8], [0, 1, 2, 6, 7, 8])
+    assert r.nnz == squared_laplacian_3d_nnz(side)
+    _squared_laplacian_check(r, side, 3)
+
+
+def test_small_fd_config_equals_dense_product(oracle_mod):
+    """32x32 grid: the composed operator equals the dense 1024x1024 matrix product exactly."""
+    s = 32
+    c, v = L.fd_laplacian(s, 2)
+    M = np.zeros((s * s, s * s))
+    rows = (c[:, 0] + s * c[:, 1]).astype(np.int64)
+    cols = (c[:, 2] + s * c[:, 3]).astype(np.int64)
+    M[rows, cols] = v
+    t = oracle_mod.create([s] * 4, c, v)
+    p = oracle_mod.permute(t, [2, 3, 0, 1])
+    Mp = np.zeros_like(M)
+    Mp[(p.livs % (s * s)).astype(np.int64), (p.livs // (s * s)).astype(np.int64)] = p.vals
+    assert np.array_equal(Mp, M.T)
+    r = oracle_mod.contract(t, [0, 1, 2, 3], t, [2, 3, 4, 5], [0, 1, 4, 5])
+    D = np.zeros_like(M)
+    D[(r.livs % (s * s)).astype(np.int64), (r.livs // (s * s)).astype(np.int64)] = r.vals
+    assert np.array_equal(D, M @ M)
+    assert r.nnz == int(np.count_nonzero((M != 0).astype(float) @ (M != 0).astype(float)))
+    assert r.nnz == 12676
+
+
+def test_kronecker_generator_recipe(oracle_mod):
+    """Small Kronecker instance: duplicates summed, values bounded, order-4 outer structure."""
+    coords, vals = L.kronecker_hypersparse(6, 4096, seed=1)
+    assert coords.max() < 64
+    t = oracle_mod.create([64] * 4, coords, vals, sum_duplicates=True)
+    assert 0 < t.nnz <= 4096
+    assert np.isclose(t.vals.sum(), vals.sum())
+    dense = dense_from_coords([64] * 4, coords, vals)
+    assert np.array_equal(np.count_nonzero(dense != 0) <= t.nnz, True)
