@@ -1,0 +1,246 @@
+/*
+ * lco.h -- C-ABI of the MI355X (gfx950) library for sparse tensors in the
+ * linearised-coordinate (LCO) format: construction, mode permutation by radix
+ * permutation, and contraction by the multiplication poly-algorithm.
+ *
+ * The operations follow Harrison & Joseph, "High Performance Rearrangement and
+ * Multiplication Routines for Sparse Tensor Arithmetic":
+ *   - LCO tensor (Section 3.1): a list of linearised index values (LIVs), one
+ *     unsigned 64-bit integer per non-zero, strictly increasing, with a parallel
+ *     list of FP64 values.  Default lexicographical order: the first mode is the
+ *     least significant, LIV = c0 + n0*(c1 + n1*(c2 + ...)).
+ *   - Permutation (Section 4): re-sorting already-sorted data into another
+ *     lexicographical order, done here by radix permutation (RP).
+ *   - Contraction (Sections 2 and 5): Einstein-notation products of two
+ *     tensors, executed as matricise -> convert to a multiplication datatype
+ *     and multiply -> map back, with the algorithm chosen from the paper's
+ *     table of sparsity combinations (Section 5.2, Table "Multiplication
+ *     possibilities based on sparse characteristics of operands").
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an lco_status; no exception crosses the ABI.  On
+ *     error no output handle is produced (the out-pointer is set to NULL),
+ *     scratch memory is released, and lco_last_error() describes the cause.
+ *     Argument errors are detected on the host before any device work.
+ *   - "device" pointers address HIP device memory of the context's device;
+ *     "host" pointers address ordinary host memory.
+ *   - All device work is enqueued on the context's stream.  Entry points that
+ *     must learn a data-dependent size (lco_create, lco_contract) synchronise
+ *     that stream before returning; lco_permute does not.
+ *   - Tensors are owned by the caller and released with lco_destroy, which must
+ *     happen before the context that made them is destroyed.  Inputs are never
+ *     modified.
+ *   - LIVs are unsigned: the product of a tensor's dimensions may be anything up
+ *     to and including 2^64 (the paper limits itself to signed 63-bit LIVs).
+ *   - At most LCO_MAX_ORDER modes per tensor; at most 2^32-1 non-zeros per
+ *     tensor and per intermediate product list.
+ */
+#ifndef LCO_H
+#define LCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LCO_MAX_ORDER 16
+
+typedef enum {
+  LCO_OK = 0,
+  LCO_E_ARG = 1,         /* malformed argument: NULL pointer, bad permutation, bad labels, coordinate out of range */
+  LCO_E_OVERFLOW = 2,    /* product of dimensions exceeds 2^64 */
+  LCO_E_SHAPE = 3,       /* contracted modes of different dimension */
+  LCO_E_UNSORTED = 4,    /* LCO_SORTED input whose LIVs are not strictly increasing */
+  LCO_E_DUPLICATE = 5,   /* repeated coordinate without LCO_SUM_DUPLICATES */
+  LCO_E_OOM = 6,         /* the allocator returned NULL */
+  LCO_E_UNSUPPORTED = 7, /* valid request outside what this library implements (see each call) */
+  LCO_E_HIP = 8          /* a HIP runtime call failed */
+} lco_status;
+
+typedef struct lco_ctx_s* lco_ctx;
+typedef struct lco_tensor_s* lco_tensor;
+
+/* Device allocator callbacks.  alloc returns device memory of at least `bytes`
+ * bytes usable in stream order on `stream` (NULL on failure); free releases it
+ * in stream order.  `user` is passed through unchanged. */
+typedef void* (*lco_alloc_fn)(void* user, size_t bytes, void* stream);
+typedef void (*lco_free_fn)(void* user, void* ptr, size_t bytes, void* stream);
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  If alloc/free are NULL the library
+ * uses stream-ordered hipMallocAsync/hipFreeAsync.  *out receives the handle. */
+lco_status lco_ctx_create(int device, void* hip_stream, lco_alloc_fn alloc, lco_free_fn free_fn, void* user,
+                          lco_ctx* out);
+/* Destroy a context (waits for its stream first). */
+lco_status lco_ctx_destroy(lco_ctx ctx);
+/* Redirect subsequent work of the context to another stream of the same device. */
+lco_status lco_ctx_set_stream(lco_ctx ctx, void* hip_stream);
+/* Block until all work enqueued by the context has finished. */
+lco_status lco_ctx_synchronize(lco_ctx ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the library's kernels (off by default; costs two events per
+ * launch).  lco_timing_query sums over all launches of kernels whose name
+ * equals `kernel` since the last reset: *launches, *total_ms.  Timing of a
+ * launch is collected lazily at query time. */
+lco_status lco_timing_enable(lco_ctx ctx, int on);
+lco_status lco_timing_reset(lco_ctx ctx);
+lco_status lco_timing_query(lco_ctx ctx, const char* kernel, int64_t* launches, double* total_ms);
+/* Name of the i-th distinct kernel seen by the timer (NULL past the end). */
+const char* lco_timing_kernel_name(lco_ctx ctx, int i);
+
+/* ------------------------------------------------------------------ tensors */
+
+#define LCO_SORTED 0x1u          /* d_idx holds LIVs, claimed strictly increasing (verified: LCO_E_UNSORTED) */
+#define LCO_COORDS 0x2u          /* d_idx holds nnz*order coordinates, entry-major (entry i: d_idx[i*order + r]) */
+#define LCO_SUM_DUPLICATES 0x4u  /* repeated coordinates are summed, in input order; else LCO_E_DUPLICATE */
+
+/* Build an LCO tensor (Section 3.1) of order `order` (0..LCO_MAX_ORDER) and
+ * dimensions `dims` (host, `order` entries, each >= 1, product <= 2^64) from
+ * `nnz` entries.  `d_idx` (device) holds either LIVs in the default order
+ * (default) or coordinates (LCO_COORDS); `d_vals` (device) holds nnz FP64
+ * values.  Unsorted input is sorted (stable LSD radix sort on the full LIV);
+ * explicit zeros are kept.  The tensor copies the data (the caller keeps
+ * ownership of d_idx/d_vals).  Errors: LCO_E_ARG (coordinate or LIV out of
+ * range, bad order), LCO_E_OVERFLOW, LCO_E_UNSORTED, LCO_E_DUPLICATE, LCO_E_OOM. */
+lco_status lco_create(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz, const uint64_t* d_idx,
+                      const double* d_vals, uint32_t flags, lco_tensor* out);
+
+/* Release a tensor's device memory (stream-ordered) and its handle. */
+lco_status lco_destroy(lco_tensor t);
+
+int64_t lco_nnz(lco_tensor t);
+int lco_order(lco_tensor t);
+/* Host array of `order` dimensions, owned by the tensor. */
+const uint64_t* lco_dims(lco_tensor t);
+/* Device arrays of nnz LIVs / values, owned by the tensor (NULL when nnz == 0). */
+const uint64_t* lco_livs(lco_tensor t);
+const double* lco_vals(lco_tensor t);
+
+/* -------------------------------------------------------------- permutation */
+
+/* Radix permutation (Section 4.1).  Output mode r is input mode perm[r]
+ * (host array of `order` distinct indices); the output has dimensions
+ * dims[perm[r]] and is sorted in its default order -- identical to re-sorting
+ * the input into the lexicographical order that makes input mode perm[r] the
+ * r-th least significant.  Only the digit groups the permutation disturbs are
+ * sorted (stable LSD passes over the truncated key between the shared leading
+ * resting modes and the trailing resting modes).  Values are copied
+ * bit-exactly.  No host synchronisation except on the segmented path (a
+ * common leading resting mode), which reads back the largest segment size.
+ * Errors: LCO_E_ARG (not a permutation), LCO_E_OOM. */
+lco_status lco_permute(lco_ctx ctx, lco_tensor in, const int* perm, lco_tensor* out);
+
+/* -------------------------------------------------------------- contraction */
+
+/* Sparsity classes of a matricised operand (Section 5.1): a dimension is
+ * "hyper-sparse" when it exceeds three times the number of non-zeros
+ * (Sections 5.2.3-5.2.5 use the ratio dimension/nnz > 3). */
+typedef enum { LCO_SPARSE = 0, LCO_ROW_SPARSE = 1, LCO_COL_SPARSE = 2, LCO_INDEX_SPARSE = 3 } lco_sparsity;
+
+/* Multiplication algorithms (Section 5.2); the value is also the "force"
+ * field of lco_contract's flags. */
+typedef enum {
+  LCO_ALG_AUTO = 0,
+  LCO_ALG_CSC = 1,   /* column-by-column with accumulator, A compressed by columns */
+  LCO_ALG_CSR = 2,   /* row-by-row with accumulator, B compressed by rows */
+  LCO_ALG_DCSC = 3,  /* as CSC with A doubly compressed (only non-empty columns) */
+  LCO_ALG_DCSR = 4,  /* as CSR with B doubly compressed (only non-empty rows) */
+  LCO_ALG_CSCNA = 5, /* column-by-column, no accumulator: products sorted and summed */
+  LCO_ALG_CSRNA = 6, /* row-by-row, no accumulator */
+  LCO_ALG_SOP = 7    /* simple outer product: all rank-1 products sorted and summed */
+} lco_algo;
+
+#define LCO_FORCE_MASK 0xFu  /* flags & LCO_FORCE_MASK = lco_algo to force (0 = choose by the table) */
+
+typedef struct {
+  uint64_t m, k, n;                 /* A is m x k, B is k x n after matricisation */
+  int64_t nnz_a, nnz_b;
+  int a_class, b_class;             /* lco_sparsity of A and B */
+  int algo;                         /* lco_algo that runs */
+  int permute_a, permute_b;         /* 1 if that operand is rearranged before multiplying */
+  int permute_c;                    /* 1 if the product is rearranged into c_labels order */
+  int num_contracted;               /* number of contracted labels */
+} lco_plan;
+
+/* Einstein-notation product (Section 2; Section 5.2's three steps).
+ * `a_labels` / `b_labels` (host) name the modes of a and b; `c_labels` (host,
+ * c_order entries, 0 <= c_order) name the output modes in output order.  A
+ * label in both inputs and not in the output is contracted; a label in exactly
+ * one input and in the output is free.  Each output entry sums its products in
+ * ascending order of the contracted index (contracted modes linearised in the
+ * order they occur in a), starting from 0.0; every structural non-zero is kept.
+ * flags & LCO_FORCE_MASK forces an lco_algo instead of the table's choice.
+ * Synchronises the stream once per data-dependent size (output nnz; product
+ * count for the outer-product and long-row paths).
+ * Errors: LCO_E_ARG (labels malformed, label repeated within an operand or in
+ * the output), LCO_E_SHAPE, LCO_E_OVERFLOW (output dimension product > 2^64),
+ * LCO_E_UNSUPPORTED (a label in both inputs and the output -- entrywise
+ * product --, a free label absent from the output, or a matricised side of
+ * exactly 2^64), LCO_E_OOM. */
+lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
+                        int c_order, const int* c_labels, uint32_t flags, lco_tensor* out);
+
+/* The plan lco_contract would run for these operands, without running it. */
+lco_status lco_plan_info(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
+                         int c_order, const int* c_labels, uint32_t flags, lco_plan* out);
+
+/* ------------------------------------------------- host-only planning logic */
+
+/* Classify an m x k matricised operand with nnz non-zeros (Section 5.2: row-
+ * sparse iff rows/nnz > 3, column-sparse iff cols/nnz > 3, index-sparse iff both). */
+lco_status lco_classify(uint64_t rows, uint64_t cols, int64_t nnz, int* cls);
+
+/* The cell of the paper's multiplication table for operand classes
+ * (a_class, b_class): *first and *second receive the algorithm(s) named in the
+ * cell (equal when the cell names one; CSC-family first when it names two). */
+lco_status lco_select(int a_class, int b_class, int* first, int* second);
+
+/* The same plan as lco_plan_info from shapes alone (host arrays; no device). */
+lco_status lco_plan_contract(int a_order, const uint64_t* a_dims, const int* a_labels, int64_t a_nnz, int b_order,
+                             const uint64_t* b_dims, const int* b_labels, int64_t b_nnz, int c_order,
+                             const int* c_labels, uint32_t flags, lco_plan* out);
+
+/* Radix-permutation plan (Section 4.1): classification of the modes into
+ * rearrangement and resting indices and the truncated key that must be sorted. */
+typedef struct {
+  int identity;            /* 1: the permutation leaves every LIV order unchanged (plain copy + LIV shuffle) */
+  int prefix;              /* leading (most significant) modes shared by the old and new orders: segments */
+  int suffix;              /* trailing (least significant) new-order modes left out of the key */
+  uint32_t rearrangement;  /* bit q set iff input mode q is a rearrangement index */
+  int key_bits;            /* bits of the truncated key (the modes between prefix and suffix) */
+  int seg_bits;            /* bits of the segment id (prefix modes) */
+  int full_bits;           /* bits of the whole LIV range */
+  int method;              /* 0 copy, 1 single-tile LDS sort, 2 global LSD on the key, 3 segmented LDS sort,
+                              4 global LSD on segment and key */
+  int passes;              /* radix passes of the chosen method */
+  int digit_bits;          /* bits per radix pass */
+  uint64_t key_div;        /* new-LIV divisor removing the suffix modes */
+  uint64_t key_range;      /* number of distinct key values (product of the keyed dimensions) */
+  uint64_t seg_div;        /* old-LIV divisor whose quotient is the segment id */
+} lco_rp_plan;
+
+lco_status lco_plan_permute(int order, const uint64_t* dims, const int* perm, int64_t nnz, lco_rp_plan* out);
+
+/* Host run of the library's invariant-divisor division (Granlund & Montgomery,
+ * 1994, "Division by invariant integers using multiplication", Fig. 4.1) used
+ * by the kernels for LIV decoding: quot[i] = num[i] / d, rem[i] = num[i] % d. */
+lco_status lco_fastdiv_host(uint64_t d, int64_t count, const uint64_t* num, uint64_t* quot, uint64_t* rem);
+
+/* --------------------------------------------------------------- diagnostics */
+
+const char* lco_status_str(lco_status s);
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* lco_last_error(void);
+/* Library version string. */
+const char* lco_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCO_H */

@@ -1,0 +1,382 @@
+"""ctypes binding of ``liblco.so`` (the C-ABI of ``include/lco.h``).
+
+Marshalling only.  Device arrays are torch CUDA (HIP) tensors; the library's
+allocations go through the torch caching allocator on the context's stream, so
+the LIV / value arrays of a result can be viewed as torch tensors without a copy.
+
+If the compiled library is missing this module raises ImportError: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
+    "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
+    "lco_contract", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
+    "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
+    "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
+    "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
+    "LCO_ALG_CSRNA", "LCO_ALG_SOP", "LCO_SPARSE", "LCO_ROW_SPARSE", "LCO_COL_SPARSE", "LCO_INDEX_SPARSE",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblco.so")
+
+LCO_SORTED = 0x1
+LCO_COORDS = 0x2
+LCO_SUM_DUPLICATES = 0x4
+
+LCO_ALG_AUTO, LCO_ALG_CSC, LCO_ALG_CSR, LCO_ALG_DCSC, LCO_ALG_DCSR, LCO_ALG_CSCNA, LCO_ALG_CSRNA, LCO_ALG_SOP = range(8)
+ALGOS = {0: "auto", 1: "CSC", 2: "CSR", 3: "DCSC", 4: "DCSR", 5: "CSCNA", 6: "CSRNA", 7: "SOP"}
+ALGO_IDS = {v: k for k, v in ALGOS.items()}
+LCO_SPARSE, LCO_ROW_SPARSE, LCO_COL_SPARSE, LCO_INDEX_SPARSE = range(4)
+CLASSES = {0: "sparse", 1: "row-sparse", 2: "column-sparse", 3: "index-sparse"}
+
+_STATUS = {0: "ok", 1: "bad argument", 2: "index overflow", 3: "shape mismatch", 4: "unsorted input",
+           5: "duplicate entry", 6: "out of memory", 7: "unsupported", 8: "HIP runtime error"}
+
+
+class LcoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_uint64), ("k", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("nnz_a", ctypes.c_int64), ("nnz_b", ctypes.c_int64),
+                ("a_class", ctypes.c_int), ("b_class", ctypes.c_int), ("algo", ctypes.c_int),
+                ("permute_a", ctypes.c_int), ("permute_b", ctypes.c_int), ("permute_c", ctypes.c_int),
+                ("num_contracted", ctypes.c_int)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["algo_name"] = ALGOS[self.algo]
+        d["a_class_name"] = CLASSES[self.a_class]
+        d["b_class_name"] = CLASSES[self.b_class]
+        return d
+
+
+class RpPlan(ctypes.Structure):
+    _fields_ = [("identity", ctypes.c_int), ("prefix", ctypes.c_int), ("suffix", ctypes.c_int),
+                ("rearrangement", ctypes.c_uint32), ("key_bits", ctypes.c_int), ("seg_bits", ctypes.c_int),
+                ("full_bits", ctypes.c_int), ("method", ctypes.c_int), ("passes", ctypes.c_int),
+                ("digit_bits", ctypes.c_int), ("key_div", ctypes.c_uint64), ("key_range", ctypes.c_uint64),
+                ("seg_div", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+_lib = None
+_lock = threading.Lock()
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load liblco.so (ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1802_02619_amd/build.py "
+                              "(or __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+        pi32 = ctypes.POINTER(ctypes.c_int)
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        pvp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "lco_ctx_create": (i32, [i32, vp, _ALLOC_FN, _FREE_FN, vp, pvp]),
+            "lco_ctx_destroy": (i32, [vp]),
+            "lco_ctx_set_stream": (i32, [vp, vp]),
+            "lco_ctx_synchronize": (i32, [vp]),
+            "lco_timing_enable": (i32, [vp, i32]),
+            "lco_timing_reset": (i32, [vp]),
+            "lco_timing_query": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
+            "lco_timing_kernel_name": (ctypes.c_char_p, [vp, i32]),
+            "lco_create": (i32, [vp, i32, pu64, i64, vp, vp, u32, pvp]),
+            "lco_destroy": (i32, [vp]),
+            "lco_nnz": (i64, [vp]),
+            "lco_order": (i32, [vp]),
+            "lco_dims": (pu64, [vp]),
+            "lco_livs": (vp, [vp]),
+            "lco_vals": (vp, [vp]),
+            "lco_permute": (i32, [vp, vp, pi32, pvp]),
+            "lco_contract": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, pvp]),
+            "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
+            "lco_classify": (i32, [u64, u64, i64, ctypes.POINTER(i32)]),
+            "lco_select": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "lco_plan_contract": (i32, [i32, pu64, pi32, i64, i32, pu64, pi32, i64, i32, pi32, u32,
+                                        ctypes.POINTER(Plan)]),
+            "lco_plan_permute": (i32, [i32, pu64, pi32, i64, ctypes.POINTER(RpPlan)]),
+            "lco_fastdiv_host": (i32, [u64, i64, pu64, pu64, pu64]),
+            "lco_status_str": (ctypes.c_char_p, [i32]),
+            "lco_last_error": (ctypes.c_char_p, []),
+            "lco_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise LcoError(st, load_library().lco_last_error().decode())
+
+
+def _u64arr(xs):
+    xs = [int(x) for x in xs]
+    return (ctypes.c_uint64 * max(1, len(xs)))(*xs)
+
+
+def _i32arr(xs):
+    xs = [int(x) for x in xs]
+    return (ctypes.c_int * max(1, len(xs)))(*xs)
+
+
+def lco_version() -> str:
+    return load_library().lco_version().decode()
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """A library context on one device and stream, allocating through torch."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = load_library()
+        self._torch = torch
+        self.device = int(device)
+        self._dev = torch.device("cuda", self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self._dev)
+        self.stream = stream
+        self._allocs = {}
+
+        def _alloc(user, nbytes, strm):
+            try:
+                with torch.cuda.stream(self.stream):
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=self._dev)
+                p = t.data_ptr()
+                self._allocs[p] = t
+                return p
+            except Exception:  # reported to the caller as LCO_E_OOM
+                return None
+
+        def _free(user, ptr, nbytes, strm):
+            self._allocs.pop(ptr, None)
+
+        self._alloc_cb = _ALLOC_FN(_alloc)
+        self._free_cb = _FREE_FN(_free)
+        h = ctypes.c_void_p()
+        _check(L.lco_ctx_create(self.device, ctypes.c_void_p(stream.cuda_stream), self._alloc_cb, self._free_cb,
+                                None, ctypes.byref(h)))
+        self.handle = h
+
+    def synchronize(self):
+        _check(load_library().lco_ctx_synchronize(self.handle))
+
+    def destroy(self):
+        if self.handle:
+            _check(load_library().lco_ctx_destroy(self.handle))
+            self.handle = None
+
+    def view(self, ptr: int, nbytes: int, dtype):
+        """torch view of `nbytes` at device pointer `ptr` inside one of this context's allocations."""
+        t = self._allocs.get(ptr)
+        if t is None:
+            raise KeyError("pointer is not the start of a library allocation")
+        return t[:nbytes].view(dtype)
+
+
+def lco_ctx_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def lco_ctx_destroy(ctx: Context):
+    ctx.destroy()
+
+
+def lco_ctx_synchronize(ctx: Context):
+    ctx.synchronize()
+
+
+# ------------------------------------------------------------------ tensors
+class Tensor:
+    """Handle of an LCO tensor owned by the library (release with destroy())."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    @property
+    def nnz(self) -> int:
+        return int(load_library().lco_nnz(self.handle))
+
+    @property
+    def order(self) -> int:
+        return int(load_library().lco_order(self.handle))
+
+    @property
+    def dims(self):
+        L = load_library()
+        p = L.lco_dims(self.handle)
+        return [int(p[i]) for i in range(self.order)]
+
+    def livs(self):
+        """torch int64 view (bit pattern of the unsigned LIVs) on the device; no copy."""
+        import torch
+        n = self.nnz
+        if n == 0:
+            return torch.zeros(0, dtype=torch.int64, device=self.ctx._dev)
+        p = load_library().lco_livs(self.handle)
+        return self.ctx.view(p, n * 16, torch.uint8)[: n * 8].view(torch.int64)
+
+    def vals(self):
+        import torch
+        n = self.nnz
+        if n == 0:
+            return torch.zeros(0, dtype=torch.float64, device=self.ctx._dev)
+        p = load_library().lco_livs(self.handle)
+        return self.ctx.view(p, n * 16, torch.uint8)[n * 8: n * 16].view(torch.float64)
+
+    def to_numpy(self):
+        """(dims, livs uint64, vals float64) copied to the host."""
+        import numpy as np
+        self.ctx.synchronize()
+        livs = self.livs().cpu().numpy().view(np.uint64)
+        vals = self.vals().cpu().numpy()
+        return np.array(self.dims, dtype=np.uint64), livs.copy(), vals.copy()
+
+    def destroy(self):
+        if self.handle:
+            _check(load_library().lco_destroy(self.handle))
+            self.handle = None
+
+
+def lco_create(ctx: Context, dims, idx, vals, flags: int = 0) -> Tensor:
+    """Build a tensor from device arrays: `idx` (int64/uint64 torch tensor of LIVs, or of
+    nnz*order coordinates with LCO_COORDS) and `vals` (float64)."""
+    import torch
+    L = load_library()
+    nnz = int(vals.numel())
+    if idx.dtype not in (torch.int64, torch.uint64) or vals.dtype != torch.float64:
+        raise TypeError("idx must be int64/uint64 and vals float64")
+    idx = idx.contiguous()
+    vals = vals.contiguous()
+    h = ctypes.c_void_p()
+    _check(L.lco_create(ctx.handle, len(dims), _u64arr(dims), nnz, ctypes.c_void_p(idx.data_ptr() if nnz else 0),
+                        ctypes.c_void_p(vals.data_ptr() if nnz else 0), int(flags), ctypes.byref(h)))
+    return Tensor(ctx, h)
+
+
+def lco_destroy(t: Tensor):
+    t.destroy()
+
+
+def lco_permute(ctx: Context, t: Tensor, perm) -> Tensor:
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(L.lco_permute(ctx.handle, t.handle, _i32arr(perm), ctypes.byref(h)))
+    return Tensor(ctx, h)
+
+
+def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Tensor:
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(L.lco_contract(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
+                          _i32arr(c_labels), int(flags), ctypes.byref(h)))
+    return Tensor(ctx, h)
+
+
+def lco_plan_info(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Plan:
+    L = load_library()
+    p = Plan()
+    _check(L.lco_plan_info(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
+                           _i32arr(c_labels), int(flags), ctypes.byref(p)))
+    return p
+
+
+# ------------------------------------------------------------------ host-only planning
+def lco_plan_contract(a_dims, a_labels, a_nnz, b_dims, b_labels, b_nnz, c_labels, flags: int = 0) -> Plan:
+    L = load_library()
+    p = Plan()
+    _check(L.lco_plan_contract(len(a_dims), _u64arr(a_dims), _i32arr(a_labels), int(a_nnz), len(b_dims),
+                               _u64arr(b_dims), _i32arr(b_labels), int(b_nnz), len(c_labels), _i32arr(c_labels),
+                               int(flags), ctypes.byref(p)))
+    return p
+
+
+def lco_plan_permute(dims, perm, nnz: int) -> RpPlan:
+    L = load_library()
+    p = RpPlan()
+    _check(L.lco_plan_permute(len(dims), _u64arr(dims), _i32arr(perm), int(nnz), ctypes.byref(p)))
+    return p
+
+
+def lco_classify(rows: int, cols: int, nnz: int) -> int:
+    c = ctypes.c_int()
+    _check(load_library().lco_classify(int(rows), int(cols), int(nnz), ctypes.byref(c)))
+    return c.value
+
+
+def lco_select(a_class: int, b_class: int):
+    f, s = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lco_select(int(a_class), int(b_class), ctypes.byref(f), ctypes.byref(s)))
+    return f.value, s.value
+
+
+def lco_fastdiv_host(d: int, nums):
+    import numpy as np
+    nums = np.ascontiguousarray(np.asarray(nums, dtype=np.uint64))
+    q = np.zeros_like(nums)
+    r = np.zeros_like(nums)
+    p = ctypes.POINTER(ctypes.c_uint64)
+    _check(load_library().lco_fastdiv_host(int(d), nums.shape[0], nums.ctypes.data_as(p), q.ctypes.data_as(p),
+                                           r.ctypes.data_as(p)))
+    return q, r
+
+
+# ------------------------------------------------------------------ timing
+def lco_timing_enable(ctx: Context, on: bool = True):
+    _check(load_library().lco_timing_enable(ctx.handle, int(on)))
+
+
+def lco_timing_reset(ctx: Context):
+    _check(load_library().lco_timing_reset(ctx.handle))
+
+
+def lco_timing_query(ctx: Context, kernel: str):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load_library().lco_timing_query(ctx.handle, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def lco_timing_kernels(ctx: Context):
+    L = load_library()
+    out = []
+    i = 0
+    while True:
+        s = L.lco_timing_kernel_name(ctx.handle, i)
+        if not s:
+            return out
+        out.append(s.decode())
+        i += 1

@@ -1,0 +1,467 @@
+// Radix permutation engine (Section 4.1) and the stable LSD radix sort it is built on.
+//
+// The paper's RP sorts, stably, only the digit groups a permutation disturbs.
+// Here every pass is a stable least-significant-digit pass over a tile of
+// (LIV, value) pairs: each wave ranks its elements per digit with ballot
+// matching (all lanes holding the same digit are found with one ballot per
+// digit bit), waves are combined with per-digit counters in LDS, the tile is
+// reordered by digit in LDS, and then written out in digit runs so that
+// consecutive lanes store consecutive addresses.  Tile bucket offsets come from
+// a device-wide scan of per-tile digit counts (reduce-then-scan).  The LIV
+// shuffle (recomputing LIVs in the new lexicographical order) is fused into the
+// first pass's loads.
+#include <algorithm>
+#include <cstdlib>
+
+#include "device_common.h"
+
+namespace lco {
+
+namespace {
+
+constexpr int kRxWaves = 4;
+constexpr int kRxThreads = kRxWaves * kWave;
+constexpr int kRxItems = 16;
+constexpr int kRxTile = kRxThreads * kRxItems;  // 4096
+constexpr int kRxBins = 256;                    // digits of at most 8 bits
+
+constexpr int kLdsWaves = 8;
+constexpr int kLdsThreads = kLdsWaves * kWave;
+constexpr int kLdsItems = 16;
+constexpr int kLdsTile = kLdsThreads * kLdsItems;  // 8192: single-tile and segmented sorts
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t mask) {
+  return (uint32_t)(key >> shift) & mask;
+}
+
+// Peers: lanes of this wave holding the same digit (one ballot per digit bit).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits) {
+  uint64_t peers = ~0ull;
+  for (int b = 0; b < dbits; ++b) {
+    const int bit = (d >> b) & 1;
+    const uint64_t bal = __ballot(bit);
+    peers &= bit ? bal : ~bal;
+  }
+  return peers;
+}
+
+// Stable rank of ITEMS elements per lane within the block, by digit.  Element
+// order is (wave, item, lane).  On return pos[it] is the element's position in
+// the tile sorted by digit; dstart[d] is the first position of digit d.
+template <int WAVES, int ITEMS>
+__device__ __forceinline__ void block_rank(const uint32_t (&dg)[ITEMS], uint32_t (&pos)[ITEMS], int dbits,
+                                           uint32_t (*cnt)[kRxBins], uint32_t* dstart, uint32_t* wsum) {
+  const int wave = threadIdx.x / kWave;
+  const uint32_t bins = 1u << dbits;
+  for (int i = threadIdx.x; i < WAVES * kRxBins; i += WAVES * kWave) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t peers = match_digit(dg[it], dbits);
+    const uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
+    const uint32_t c = cnt[wave][dg[it]];
+    pos[it] = c + before;
+    if (before == 0) cnt[wave][dg[it]] = c + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  uint32_t tot = 0;
+  for (uint32_t d = threadIdx.x; d < (uint32_t)kRxBins; d += WAVES * kWave) {
+    // only threads d < bins hold digits; WAVES*64 >= 256 so each thread has at most one digit
+    if (d < bins) {
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = cnt[w][d];
+        cnt[w][d] = run;
+        run += c;
+      }
+      tot = run;
+    }
+  }
+  uint32_t all;
+  const uint32_t ex = block_exclusive_scan<uint32_t>(tot, wsum, all);
+  if (threadIdx.x < bins) dstart[threadIdx.x] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) pos[it] += dstart[dg[it]] + cnt[wave][dg[it]];
+}
+
+// ---------------------------------------------------------------- global passes
+
+template <bool SHUF>
+__global__ __launch_bounds__(kRxThreads) void rx_count_kernel(const uint64_t* __restrict__ livs, int64_t n,
+                                                              ShuffleParams sp, KeyParams kp, int shift,
+                                                              uint32_t mask, uint32_t* __restrict__ counts,
+                                                              int64_t num_tiles) {
+  __shared__ uint32_t hist[kRxWaves][kRxBins];
+  for (int i = threadIdx.x; i < kRxWaves * kRxBins; i += kRxThreads) (&hist[0][0])[i] = 0;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int64_t base = (int64_t)blockIdx.x * kRxTile + (int64_t)wave * kRxItems * kWave + lane;
+  uint64_t x[kRxItems];
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    const int64_t e = base + it * kWave;
+    x[it] = e < n ? livs[e] : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    const int64_t e = base + it * kWave;
+    if (e < n) {
+      uint64_t v = x[it];
+      if (SHUF) v = shuffle_liv(sp, v);
+      const uint64_t key = fd_div(kp.key_div, v) - kp.key_base;
+      atomicAdd(&hist[wave][digit_of(key, shift, mask)], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d <= mask; d += kRxThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kRxWaves; ++w) s += hist[w][d];
+    counts[(int64_t)d * num_tiles + blockIdx.x] = s;
+  }
+}
+
+template <bool SHUF>
+__global__ __launch_bounds__(kRxThreads) void rx_scatter_kernel(
+    const uint64_t* __restrict__ livs, const double* __restrict__ vals, int64_t n, ShuffleParams sp, KeyParams kp,
+    int shift, int dbits, const uint32_t* __restrict__ offsets, int64_t num_tiles, uint64_t* __restrict__ out_livs,
+    double* __restrict__ out_vals) {
+  __shared__ uint32_t cnt[kRxWaves][kRxBins];
+  __shared__ uint32_t dstart[kRxBins];
+  __shared__ uint32_t gbase[kRxBins];
+  __shared__ uint32_t wsum[kRxWaves + 1];
+  __shared__ uint64_t s_liv[kRxTile];
+  __shared__ double s_val[kRxTile];
+  __shared__ uint8_t s_dig[kRxTile];
+  const uint32_t mask = (1u << dbits) - 1u;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int64_t tile0 = (int64_t)blockIdx.x * kRxTile;
+  const int64_t base = tile0 + (int64_t)wave * kRxItems * kWave + lane;
+  for (uint32_t d = threadIdx.x; d <= mask; d += kRxThreads) gbase[d] = offsets[(int64_t)d * num_tiles + blockIdx.x];
+  uint64_t lv[kRxItems];
+  double vv[kRxItems];
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    const int64_t e = base + it * kWave;
+    lv[it] = e < n ? livs[e] : 0;
+  }
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    const int64_t e = base + it * kWave;
+    vv[it] = e < n ? vals[e] : 0.0;
+  }
+  uint32_t dg[kRxItems], pos[kRxItems];
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    const int64_t e = base + it * kWave;
+    if (SHUF) lv[it] = shuffle_liv(sp, lv[it]);
+    dg[it] = e < n ? digit_of(fd_div(kp.key_div, lv[it]) - kp.key_base, shift, mask) : mask;
+  }
+  block_rank<kRxWaves, kRxItems>(dg, pos, dbits, cnt, dstart, wsum);
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) {
+    s_liv[pos[it]] = lv[it];
+    s_val[pos[it]] = vv[it];
+    s_dig[pos[it]] = (uint8_t)dg[it];
+  }
+  __syncthreads();
+  const int valid = (int)((n - tile0) < kRxTile ? (n - tile0) : kRxTile);
+  for (int i = threadIdx.x; i < valid; i += kRxThreads) {
+    const uint32_t d = s_dig[i];
+    const uint64_t dst = (uint64_t)gbase[d] + (uint32_t)(i - (int)dstart[d]);
+    out_livs[dst] = s_liv[i];
+    out_vals[dst] = s_val[i];
+  }
+}
+
+// ---------------------------------------------------------------- LDS-resident sorts
+
+// Sorts up to kLdsTile elements held in registers (element order (wave, item,
+// lane)) by bits [0, bits) of key(x) = x / key_div - key_base, stably, leaving
+// the result in s_liv / s_val positions [0, valid).
+__device__ __forceinline__ void lds_sort(uint64_t (&lv)[kLdsItems], double (&vv)[kLdsItems], int valid, int bits,
+                                         int digit_cap, const FastDiv& key_div, uint64_t key_base,
+                                         uint32_t (*cnt)[kRxBins], uint32_t* dstart, uint32_t* wsum,
+                                         uint64_t* s_liv, double* s_val) {
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int passes = bits > 0 ? (bits + digit_cap - 1) / digit_cap : 0;
+  const int dbits = passes ? (bits + passes - 1) / passes : 1;
+  const uint32_t mask = (1u << dbits) - 1u;
+  const int ebase = wave * kLdsItems * kWave + lane;
+  if (passes == 0) {
+#pragma unroll
+    for (int it = 0; it < kLdsItems; ++it) {
+      const int e = ebase + it * kWave;
+      s_liv[e] = lv[it];
+      s_val[e] = vv[it];
+    }
+    __syncthreads();
+    return;
+  }
+  for (int p = 0; p < passes; ++p) {
+    uint32_t dg[kLdsItems], pos[kLdsItems];
+#pragma unroll
+    for (int it = 0; it < kLdsItems; ++it) {
+      const int e = ebase + it * kWave;
+      dg[it] = e < valid ? digit_of(fd_div(key_div, lv[it]) - key_base, p * dbits, mask) : mask;
+    }
+    block_rank<kLdsWaves, kLdsItems>(dg, pos, dbits, cnt, dstart, wsum);
+#pragma unroll
+    for (int it = 0; it < kLdsItems; ++it) {
+      s_liv[pos[it]] = lv[it];
+      s_val[pos[it]] = vv[it];
+    }
+    __syncthreads();
+    if (p + 1 < passes) {
+#pragma unroll
+      for (int it = 0; it < kLdsItems; ++it) {
+        const int e = ebase + it * kWave;
+        lv[it] = s_liv[e];
+        vv[it] = s_val[e];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <bool SHUF>
+__global__ __launch_bounds__(kLdsThreads) void rx_single_kernel(const uint64_t* __restrict__ livs,
+                                                                const double* __restrict__ vals, int n,
+                                                                ShuffleParams sp, KeyParams kp, int bits,
+                                                                int digit_cap, uint64_t* __restrict__ out_livs,
+                                                                double* __restrict__ out_vals) {
+  __shared__ uint32_t cnt[kLdsWaves][kRxBins];
+  __shared__ uint32_t dstart[kRxBins];
+  __shared__ uint32_t wsum[kLdsWaves + 1];
+  __shared__ uint64_t s_liv[kLdsTile];
+  __shared__ double s_val[kLdsTile];
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int ebase = wave * kLdsItems * kWave + lane;
+  uint64_t lv[kLdsItems];
+  double vv[kLdsItems];
+#pragma unroll
+  for (int it = 0; it < kLdsItems; ++it) {
+    const int e = ebase + it * kWave;
+    lv[it] = e < n ? livs[e] : 0;
+    vv[it] = e < n ? vals[e] : 0.0;
+    if (SHUF && e < n) lv[it] = shuffle_liv(sp, lv[it]);
+  }
+  lds_sort(lv, vv, n, bits, digit_cap, kp.key_div, kp.key_base, cnt, dstart, wsum, s_liv, s_val);
+  for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+    out_livs[i] = s_liv[i];
+    out_vals[i] = s_val[i];
+  }
+}
+
+// First index >= x that starts a segment (segment id = old LIV / seg_div), or n.
+__device__ int64_t seg_start_at_or_after(const uint64_t* __restrict__ livs, int64_t n, const FastDiv& seg_div,
+                                         int64_t x) {
+  if (x >= n) return n;
+  const uint64_t s = fd_div(seg_div, livs[x]);
+  if (x == 0 || fd_div(seg_div, livs[x - 1]) != s) return x;
+  int64_t lo = x, hi = n;  // livs[lo] lies in segment s; the answer lies in (lo, hi]
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (fd_div(seg_div, livs[mid]) == s) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
+// Segmented radix permutation: tiles hold whole segments of constant leading
+// resting modes (Section 4.1: such regions sort independently), each sorted in
+// LDS by the tile-relative key.  Sets *overflow if a tile exceeds capacity.
+__global__ __launch_bounds__(kLdsThreads) void rx_segmented_kernel(
+    const uint64_t* __restrict__ livs, const double* __restrict__ vals, int64_t n, ShuffleParams sp,
+    FastDiv seg_div, FastDiv key_div, uint64_t key_range, int64_t nominal, int digit_cap,
+    uint64_t* __restrict__ out_livs, double* __restrict__ out_vals, uint32_t* __restrict__ overflow) {
+  __shared__ uint32_t cnt[kLdsWaves][kRxBins];
+  __shared__ uint32_t dstart[kRxBins];
+  __shared__ uint32_t wsum[kLdsWaves + 1];
+  __shared__ uint64_t s_liv[kLdsTile];
+  __shared__ double s_val[kLdsTile];
+  __shared__ int64_t bounds[2];
+  if (threadIdx.x < 2) bounds[threadIdx.x] = seg_start_at_or_after(livs, n, seg_div, ((int64_t)blockIdx.x + threadIdx.x) * nominal);
+  __syncthreads();
+  const int64_t s0 = bounds[0], s1 = bounds[1];
+  const int64_t len = s1 - s0;
+  if (len <= 0) return;
+  if (len > kLdsTile) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  const int valid = (int)len;
+  const uint64_t seg_first = fd_div(seg_div, livs[s0]);
+  const uint64_t seg_last = fd_div(seg_div, livs[s1 - 1]);
+  const uint64_t key_base = seg_first * key_range;
+  const uint64_t range_max = (seg_last - seg_first + 1) * key_range - 1;
+  const int bits = range_max ? 64 - __builtin_clzll(range_max) : 0;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int ebase = wave * kLdsItems * kWave + lane;
+  uint64_t lv[kLdsItems];
+  double vv[kLdsItems];
+#pragma unroll
+  for (int it = 0; it < kLdsItems; ++it) {
+    const int e = ebase + it * kWave;
+    lv[it] = e < valid ? shuffle_liv(sp, livs[s0 + e]) : 0;
+    vv[it] = e < valid ? vals[s0 + e] : 0.0;
+  }
+  lds_sort(lv, vv, valid, bits, digit_cap, key_div, key_base, cnt, dstart, wsum, s_liv, s_val);
+  for (int i = threadIdx.x; i < valid; i += kLdsThreads) {
+    out_livs[s0 + i] = s_liv[i];
+    out_vals[s0 + i] = s_val[i];
+  }
+}
+
+template <bool SHUF>
+__global__ void shuffle_copy_kernel(const uint64_t* __restrict__ livs, const double* __restrict__ vals, int64_t n,
+                                    ShuffleParams sp, uint64_t* __restrict__ out_livs,
+                                    double* __restrict__ out_vals) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = livs[i];
+    out_livs[i] = SHUF ? shuffle_liv(sp, x) : x;
+    out_vals[i] = vals[i];
+  }
+}
+
+int grid_for(lco_ctx ctx, int64_t n, int threads) {
+  const int64_t want = (n + threads - 1) / threads;
+  const int64_t cap = (int64_t)ctx->num_cus * 16;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+}
+
+}  // namespace
+
+int default_digit_cap() {
+  static int cap = [] {
+    const char* e = std::getenv("LCO_DIGIT_BITS");
+    int v = e ? std::atoi(e) : 8;
+    return std::min(8, std::max(1, v));
+  }();
+  return cap;
+}
+
+void shuffle_copy(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                  double* out_vals, int64_t n, const ShuffleParams* shuffle) {
+  if (n <= 0) return;
+  if (shuffle) {
+    LCO_LAUNCH(ctx, "shuffle_copy", shuffle_copy_kernel<true>, grid_for(ctx, n, 256), 256, 0, in_livs, in_vals, n,
+               *shuffle, out_livs, out_vals);
+  } else {
+    LCO_LAUNCH(ctx, "shuffle_copy", shuffle_copy_kernel<false>, grid_for(ctx, n, 256), 256, 0, in_livs, in_vals, n,
+               ShuffleParams{}, out_livs, out_vals);
+  }
+}
+
+void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                      double* out_vals, int64_t n, const ShuffleParams* shuffle, const KeyParams& key, int bits,
+                      int digit_cap) {
+  if (n <= 0) return;
+  if (bits <= 0) {
+    shuffle_copy(ctx, in_livs, in_vals, out_livs, out_vals, n, shuffle);
+    return;
+  }
+  if (n > (int64_t)UINT32_MAX) fail(LCO_E_UNSUPPORTED, "radix sort: more than 2^32-1 elements");
+  if (digit_cap < 1 || digit_cap > 8) digit_cap = default_digit_cap();
+  const ShuffleParams sp = shuffle ? *shuffle : ShuffleParams{};
+  if (n <= kLdsTile) {
+    if (shuffle) {
+      LCO_LAUNCH(ctx, "rx_single", rx_single_kernel<true>, 1, kLdsThreads, 0, in_livs, in_vals, (int)n, sp, key, bits,
+                 digit_cap, out_livs, out_vals);
+    } else {
+      LCO_LAUNCH(ctx, "rx_single", rx_single_kernel<false>, 1, kLdsThreads, 0, in_livs, in_vals, (int)n, sp, key,
+                 bits, digit_cap, out_livs, out_vals);
+    }
+    return;
+  }
+  const int passes = (bits + digit_cap - 1) / digit_cap;
+  const int dbits = (bits + passes - 1) / passes;
+  const uint32_t bins = 1u << dbits;
+  const int64_t num_tiles = (n + kRxTile - 1) / kRxTile;
+  Scratch s(ctx);
+  uint32_t* counts = s.get<uint32_t>((size_t)bins * num_tiles);
+  uint32_t* offs = s.get<uint32_t>((size_t)bins * num_tiles);
+  uint64_t* tl = nullptr;
+  double* tv = nullptr;
+  if (passes >= 2) {
+    tl = s.get<uint64_t>(n);
+    tv = s.get<double>(n);
+  }
+  const uint64_t* src_l = in_livs;
+  const double* src_v = in_vals;
+  for (int p = 0; p < passes; ++p) {
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint64_t* dl = to_out ? out_livs : tl;
+    double* dv = to_out ? out_vals : tv;
+    const int shift = p * dbits;
+    if (p == 0 && shuffle) {
+      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<true>, num_tiles, kRxThreads, 0, src_l, n, sp, key, shift,
+                 bins - 1, counts, num_tiles);
+      scan_u32(ctx, counts, offs, (int64_t)bins * num_tiles, nullptr);
+      LCO_LAUNCH(ctx, "rx_scatter", rx_scatter_kernel<true>, num_tiles, kRxThreads, 0, src_l, src_v, n, sp, key,
+                 shift, dbits, offs, num_tiles, dl, dv);
+    } else {
+      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<false>, num_tiles, kRxThreads, 0, src_l, n, sp, key, shift,
+                 bins - 1, counts, num_tiles);
+      scan_u32(ctx, counts, offs, (int64_t)bins * num_tiles, nullptr);
+      LCO_LAUNCH(ctx, "rx_scatter", rx_scatter_kernel<false>, num_tiles, kRxThreads, 0, src_l, src_v, n, sp, key,
+                 shift, dbits, offs, num_tiles, dl, dv);
+    }
+    src_l = dl;
+    src_v = dv;
+  }
+}
+
+bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                       double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
+                       const FastDiv& key_div, uint64_t key_range) {
+  if (n <= 0) return true;
+  Scratch s(ctx);
+  uint64_t* word = s.get<uint64_t>(1);  // the kernel ORs its flag into the low half
+  memset_async(ctx, word, 0, sizeof(uint64_t));
+  const int64_t nominal = kLdsTile / 2;
+  const int64_t tiles = (n + nominal - 1) / nominal;
+  LCO_LAUNCH(ctx, "rx_segmented", rx_segmented_kernel, tiles, kLdsThreads, 0, in_livs, in_vals, n, shuffle,
+             seg_div, key_div, key_range, nominal, default_digit_cap(), out_livs, out_vals, (uint32_t*)word);
+  const uint64_t* words[1] = {word};
+  const uint64_t* r = readback(ctx, words, 1);
+  return r[0] == 0;
+}
+
+void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, uint64_t* out_livs,
+                     double* out_vals) {
+  const int64_t n = in->nnz;
+  if (n == 0) return;
+  ShuffleParams sp;
+  sp.order = in->order;
+  for (int q = 0; q < in->order; ++q) {
+    sp.dim[q] = make_fastdiv(in->dims[q]);
+    sp.new_weight[q] = plan.new_weight_of_input_mode[q];
+  }
+  KeyParams kp;
+  kp.key_div = make_fastdiv(plan.pub.key_div);
+  kp.key_base = 0;
+  const int cap = default_digit_cap();
+  switch (plan.pub.method) {
+    case 0:
+      shuffle_copy(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp);
+      return;
+    case 1:
+    case 2:
+    case 4:
+      radix_sort_pairs(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp, kp, plan.sort_bits, cap);
+      return;
+    case 3:
+      if (segmented_permute(ctx, in->livs, in->vals, out_livs, out_vals, n, sp, make_fastdiv(plan.pub.seg_div),
+                            kp.key_div, plan.pub.key_range))
+        return;
+      radix_sort_pairs(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp, kp, plan.sort_bits, cap);
+      return;
+    default:
+      fail(LCO_E_ARG, "permute: unknown method");
+  }
+}
+
+}  // namespace lco

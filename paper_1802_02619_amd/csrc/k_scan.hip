@@ -1,0 +1,97 @@
+// Device-wide exclusive prefix sums (reduce -> scan partials -> scan tiles).
+// Used for radix bucket offsets, compaction positions and per-row output offsets.
+#include "device_common.h"
+
+namespace lco {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <class T>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __restrict__ in, int64_t n,
+                                                                   T* __restrict__ partials) {
+  __shared__ T wsum[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T s = 0;
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const int64_t i = base + it * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  T total;
+  block_exclusive_scan<T>(s, wsum, total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Scans one tile per block; `offsets` (optional) gives each tile's starting value.
+template <class T>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                 int64_t n, const T* __restrict__ offsets,
+                                                                 T* __restrict__ total_out) {
+  __shared__ T tile[kScanTile];
+  __shared__ T wsum[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const int64_t i = base + it * kScanThreads + threadIdx.x;
+    tile[it * kScanThreads + threadIdx.x] = i < n ? in[i] : T(0);
+  }
+  __syncthreads();
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    v[it] = tile[threadIdx.x * kScanItems + it];
+    s += v[it];
+  }
+  T total;
+  T run = block_exclusive_scan<T>(s, wsum, total);
+  const T off = offsets ? offsets[blockIdx.x] : T(0);
+  run += off;
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    tile[threadIdx.x * kScanItems + it] = run;
+    run += v[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const int64_t i = base + it * kScanThreads + threadIdx.x;
+    if (i < n) out[i] = tile[it * kScanThreads + threadIdx.x];
+  }
+  if (total_out && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total_out = off + total;
+}
+
+template <class T>
+void scan_impl(lco_ctx ctx, const T* in, T* out, int64_t n, T* total, const char* name) {
+  if (n <= 0) {
+    if (total) memset_async(ctx, total, 0, sizeof(T));
+    return;
+  }
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    LCO_LAUNCH(ctx, name, (scan_tile_kernel<T>), 1, kScanThreads, 0, in, out, n, (const T*)nullptr, total);
+    return;
+  }
+  Scratch s(ctx);
+  T* partials = s.get<T>(tiles);
+  T* poff = s.get<T>(tiles);
+  LCO_LAUNCH(ctx, "scan_reduce", (scan_reduce_kernel<T>), tiles, kScanThreads, 0, in, n, partials);
+  scan_impl<T>(ctx, partials, poff, tiles, (T*)nullptr, name);
+  LCO_LAUNCH(ctx, name, (scan_tile_kernel<T>), tiles, kScanThreads, 0, in, out, n, (const T*)poff, total);
+}
+
+}  // namespace
+
+void scan_u32(lco_ctx ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total) {
+  scan_impl<uint32_t>(ctx, in, out, n, total, "scan_u32");
+}
+
+void scan_u64(lco_ctx ctx, const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total) {
+  scan_impl<uint64_t>(ctx, in, out, n, total, "scan_u64");
+}
+
+}  // namespace lco

@@ -1,0 +1,195 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lco.h"
+#include "fastdiv.h"
+
+namespace lco {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  lco_status code;
+  Error(lco_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(lco_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define LCO_HIP(x) ::lco::hip_check((x), #x)
+
+// ------------------------------------------------------------------ timing
+struct Timer {
+  bool on = false;
+  struct Rec { int name; hipEvent_t a, b; };
+  std::vector<std::string> names;
+  std::map<std::string, int> name_idx;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<int64_t> launches;
+  std::vector<double> total_ms;
+  int idx(const char* n);
+  hipEvent_t get_event();
+  void collect();  // synchronises pending events and accumulates
+  void reset();
+  ~Timer();
+};
+
+// ------------------------------------------------------------------ context
+struct Arena {
+  struct Chunk { char* p; size_t cap; };
+  std::vector<Chunk> chunks;  // chunks[0] is the main chunk
+  size_t used = 0;            // bytes used in the current (last) chunk
+  size_t high_water = 0;      // total bytes in use at the peak of the current op
+  size_t in_use = 0;
+};
+
+}  // namespace lco
+
+struct lco_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  lco_alloc_fn alloc = nullptr;
+  lco_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  int num_cus = 256;
+  size_t max_lds = 65536;
+  lco::Arena arena;
+  int scratch_depth = 0;
+  uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words)
+  lco::Timer timer;
+};
+
+struct lco_tensor_s {
+  lco_ctx ctx = nullptr;
+  int order = 0;
+  uint64_t dims[LCO_MAX_ORDER] = {};
+  int64_t nnz = 0;
+  uint64_t* livs = nullptr;  // device
+  double* vals = nullptr;    // device
+  void* base = nullptr;      // single allocation holding livs then vals
+  size_t bytes = 0;
+};
+
+namespace lco {
+
+// device memory through the context's allocator
+void* dev_alloc(lco_ctx ctx, size_t bytes);
+void dev_free(lco_ctx ctx, void* p, size_t bytes);
+
+// An LCO tensor whose storage is allocated (not yet filled).
+lco_tensor new_tensor(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz);
+
+// Per-operation scratch space carved from the context's arena (256-byte aligned).
+// Scopes nest; memory is reclaimed when the outermost scope of an op ends.
+class Scratch {
+ public:
+  explicit Scratch(lco_ctx ctx);
+  ~Scratch();
+  void* raw(size_t bytes);
+  template <class T> T* get(size_t count) { return static_cast<T*>(raw(count * sizeof(T) + 1)); }
+ private:
+  lco_ctx ctx_;
+  size_t mark_chunk_, mark_used_, mark_in_use_;
+};
+
+// small host<->device helpers on the context stream
+void memset_async(lco_ctx ctx, void* p, int v, size_t bytes);
+void copy_d2d(lco_ctx ctx, void* dst, const void* src, size_t bytes);
+// copies `count` 64-bit words from device to the pinned buffer and synchronises
+const uint64_t* readback(lco_ctx ctx, const uint64_t* const* dev_words, int count);
+void sync(lco_ctx ctx);
+
+// timing scope around one kernel launch
+struct LaunchScope {
+  lco_ctx ctx; int name; hipEvent_t b = nullptr;
+  LaunchScope(lco_ctx c, const char* n);
+  ~LaunchScope();
+};
+
+#define LCO_LAUNCH(ctx, name, kernel, grid, block, shmem, ...)                                   \
+  do {                                                                                           \
+    ::lco::LaunchScope _ls((ctx), (name));                                                       \
+    hipLaunchKernelGGL((kernel), dim3(grid), dim3(block), (shmem), (ctx)->stream, __VA_ARGS__);  \
+    ::lco::hip_check(hipGetLastError(), name);                                                   \
+  } while (0)
+
+inline int bits_for(uint64_t max_value) {  // bits needed to represent max_value (0 -> 0)
+  return max_value ? 64 - __builtin_clzll(max_value) : 0;
+}
+
+// ------------------------------------------------------------------ planning
+struct RpDetail {
+  lco_rp_plan pub;
+  int order;
+  uint64_t new_dims[LCO_MAX_ORDER];
+  uint64_t new_weight_of_input_mode[LCO_MAX_ORDER];  // W'_{perm^-1[q]}
+  int sort_bits;                                     // bits sorted by the chosen method
+};
+RpDetail plan_permute(int order, const uint64_t* dims, const int* perm, int64_t nnz, int digit_cap);
+
+struct ContractDetail {
+  lco_plan pub;
+  bool empty = false;          // an operand has no non-zeros
+  // operand layouts: output mode r of the rearranged operand is input mode perm[r]
+  int perm_a[LCO_MAX_ORDER], perm_b[LCO_MAX_ORDER];
+  int order_a, order_b, order_c;
+  // natural product layout -> c_labels: output mode r is natural mode perm_c[r]
+  int perm_c[LCO_MAX_ORDER];
+  uint64_t natural_dims[LCO_MAX_ORDER];
+  uint64_t c_dims[LCO_MAX_ORDER];
+  // SOP output key: modes of the rearranged A (free part) and B (free part)
+  int n_free_a, n_free_b, n_contracted;
+  uint64_t free_a_dims[LCO_MAX_ORDER], free_b_dims[LCO_MAX_ORDER];
+  uint64_t free_a_cweight[LCO_MAX_ORDER], free_b_cweight[LCO_MAX_ORDER];  // weight in the C LIV
+  bool sop_simple_key = false;  // C LIV == i + m * j
+};
+ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
+                             const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags);
+
+// ------------------------------------------------------------------ kernels (launchers)
+constexpr int kMaxOrder = LCO_MAX_ORDER;
+
+// Parameters for recomputing LIVs in a new lexicographical order (the LIV shuffle).
+struct ShuffleParams {
+  int order = 0;
+  FastDiv dim[kMaxOrder];        // old dimensions, least significant first
+  uint64_t new_weight[kMaxOrder];  // weight of old mode q in the new LIV
+};
+
+// Key of an element for the radix passes: key = (x / key_div) - key_base.
+struct KeyParams {
+  FastDiv key_div;
+  uint64_t key_base = 0;
+};
+
+// exclusive scans; `total` (device, may be null) receives the sum
+void scan_u32(lco_ctx ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
+void scan_u64(lco_ctx ctx, const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total);
+
+// Stable LSD radix sort of (livs, vals) pairs by bits [0, bits) of the element key.
+// If `shuffle` is non-null, the input LIVs are first recomputed (pass 1 reads old
+// LIVs and writes new ones).  Output goes to (out_livs, out_vals); input is untouched.
+void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                      double* out_vals, int64_t n, const ShuffleParams* shuffle, const KeyParams& key, int bits,
+                      int digit_cap);
+// LIV shuffle without reordering (identity order or single-valued key).
+void shuffle_copy(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                  double* out_vals, int64_t n, const ShuffleParams* shuffle);
+// Segmented permutation: returns false (and does nothing) if a segment exceeds the tile capacity.
+bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
+                       double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
+                       const FastDiv& key_div, uint64_t key_range);
+int default_digit_cap();
+
+// permutation of a tensor's storage according to a plan
+void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, uint64_t* out_livs,
+                     double* out_vals);
+
+}  // namespace lco

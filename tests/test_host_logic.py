@@ -1,0 +1,238 @@
+"""CPU tests of the library's host logic through the C-ABI (no GPU needed).
+
+Covers: every symbol declared in include/lco.h is exported; the invariant-divisor
+division used for LIV decoding; the radix-permutation plan (Section 4.1) against
+the paper's worked example and against brute force; sparsity classification and
+the multiplication table (Section 5.2); operand orientation.
+"""
+import ctypes
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import lco_inputs as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1802_02619_amd as lco
+    lco.load_library()
+    return lco
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lco.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"[\s\*](lco_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.library_path())
+    names = declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings(lib):
+    L_ = lib.load_library()
+    assert b"gfx950" in L_.lco_version()
+    assert L_.lco_status_str(7) == b"unsupported"
+
+
+# ---------------------------------------------------------------- fast division
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 7, 10, 30, 127, 128, 129, 2895, 2896, 2**31 - 1, 2**32 - 1, 2**32,
+                               2**32 + 1, 10**12 + 39, 2**63 - 1, 2**63, 2**63 + 1, 2**64 - 59, 2**64 - 1])
+def test_fastdiv_matches_integer_division(lib, d):
+    rng = np.random.default_rng(d % 1000)
+    nums = np.concatenate([
+        rng.integers(0, 2**63, 3000, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, 3000, dtype=np.uint64),
+        np.array([0, 1, 2, d - 1 if d > 0 else 0, d % 2**64, (d + 1) % 2**64, 2**64 - 1, 2**63, 2**63 - 1],
+                 dtype=np.uint64),
+        (np.arange(1, 200, dtype=np.uint64) * np.uint64(d % 2**64)) if d < 2**56 else np.zeros(0, np.uint64),
+    ])
+    q, r = lib.lco_fastdiv_host(d, nums)
+    qi = [int(x) // d for x in nums.tolist()]
+    ri = [int(x) % d for x in nums.tolist()]
+    assert q.tolist() == qi
+    assert r.tolist() == ri
+
+
+# ---------------------------------------------------------------- RP plan
+def test_rp_plan_worked_example(lib):
+    """Section 4.1 figure: 10x3x2, {0,1,2} -> {1,0,2}: i rearrangement, k leading resting (regions of
+    LIV div 30), key on the new LIV = (LIV mod 30) div 3, j final resting."""
+    p = lib.lco_plan_permute([10, 3, 2], [1, 0, 2], 100000)
+    assert p.rearrangement == 0b001          # only i
+    assert p.prefix == 1                     # k
+    assert p.suffix == 1                     # j
+    assert p.seg_div == 30
+    assert p.key_div == 3
+    assert p.key_range == 10
+    assert p.identity == 0
+
+
+def test_rp_plan_paper_table_permutations(lib):
+    """Section 4.2 table: at N = 2^11.5 (2896) the min-difference permutation {1,0,2,3} only
+    re-sorts by one index; the max/median ones {3,1,2,0}, {2,1,3,0} keep one trailing resting index."""
+    dims = [2896] * 4
+    mn = lib.lco_plan_permute(dims, [1, 0, 2, 3], 10**7)
+    assert (mn.prefix, mn.key_bits, mn.full_bits) == (2, 12, 46)
+    for perm in ([3, 1, 2, 0], [2, 1, 3, 0]):
+        mx = lib.lco_plan_permute(dims, perm, 10**7)
+        assert mx.prefix == 0 and mx.suffix == 1 and mx.key_bits == 35
+    ident = lib.lco_plan_permute(dims, [0, 1, 2, 3], 10**7)
+    assert ident.identity == 1 and ident.method == 0
+
+
+def _rearrangement_brute(dims, perm):
+    order = len(dims)
+    newpos = [perm.index(q) for q in range(order)]
+    mask = 0
+    for x in range(order):
+        if dims[x] <= 1:
+            continue
+        if any(dims[y] > 1 and newpos[y] < newpos[x] for y in range(x + 1, order)):
+            mask |= 1 << x
+    return mask
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_rp_plan_truncated_key_sort_equals_full_sort(lib, oracle_mod, order):
+    """Stable sort of old-sorted data by the plan's truncated key reproduces the oracle's
+    permutation for every permutation (the radix-permutation claim)."""
+    rng = np.random.default_rng(order)
+    for trial in range(2):
+        dims = [int(x) for x in rng.integers(1, 5, order)]
+        if trial == 0:
+            dims[int(rng.integers(0, order))] = 1  # size-1 modes are ignored by the classification
+        coords, vals = L.random_sparse(rng, dims, 60)
+        t = oracle_mod.create(dims, coords, vals)
+        for perm in itertools.permutations(range(order)):
+            perm = list(perm)
+            p = lib.lco_plan_permute(dims, perm, t.nnz)
+            assert p.rearrangement == _rearrangement_brute(dims, perm)
+            ref = oracle_mod.permute(t, perm)
+            nd = [dims[q] for q in perm]
+            newc = oracle_mod.delinearise(dims, t.livs)[:, perm]
+            newliv = oracle_mod.linearise(nd, newc)
+            if p.identity:
+                assert np.array_equal(newliv, ref.livs)
+                continue
+            key = newliv // np.uint64(p.key_div)
+            # segments of the shared leading resting modes are contiguous in the old order
+            seg = t.livs // np.uint64(p.seg_div)
+            assert np.all(np.diff(seg.astype(np.float64)) >= 0)
+            if p.prefix == 0:
+                assert int(key.max()) < p.key_range
+            order_idx = np.argsort(key, kind="stable")
+            assert np.array_equal(newliv[order_idx], ref.livs), (dims, perm)
+            assert np.array_equal(t.vals[order_idx], ref.vals)
+
+
+# ---------------------------------------------------------------- selector
+def test_classify_thresholds(lib):
+    # Section 5.2: hyper-sparse when dimension / nnz exceeds 3 (strictly)
+    assert lib.lco_classify(30, 30, 10) == lib.LCO_SPARSE
+    assert lib.lco_classify(31, 30, 10) == lib.LCO_ROW_SPARSE
+    assert lib.lco_classify(30, 31, 10) == lib.LCO_COL_SPARSE
+    assert lib.lco_classify(31, 31, 10) == lib.LCO_INDEX_SPARSE
+    assert lib.lco_classify(2**64 - 1, 1, 2**40) == lib.LCO_ROW_SPARSE
+
+
+def test_multiplication_table_cells(lib):
+    """Section 5.2's table, rows = A in (sparse, column-, row-, index-sparse),
+    columns = B in (sparse, row-, column-, index-sparse)."""
+    S, R, C, I = lib.LCO_SPARSE, lib.LCO_ROW_SPARSE, lib.LCO_COL_SPARSE, lib.LCO_INDEX_SPARSE
+    A = lib.ALGO_IDS
+    table = {
+        (S, S): ("CSC", "CSR"), (S, R): ("CSC",), (S, C): ("CSC",), (S, I): ("CSC",),
+        (C, S): ("CSR",), (C, R): ("DCSC", "DCSR"), (C, C): ("DCSC",), (C, I): ("DCSC",),
+        (R, S): ("CSR",), (R, R): ("DCSR",), (R, C): ("CSCNA", "CSRNA"), (R, I): ("CSCNA",),
+        (I, S): ("CSR",), (I, R): ("DCSR",), (I, C): ("CSRNA",), (I, I): ("SOP",),
+    }
+    for (a, b), algos in table.items():
+        f, s = lib.lco_select(a, b)
+        assert (lib.ALGOS[f], lib.ALGOS[s]) == (algos[0], algos[-1]), (a, b)
+
+
+def test_plan_small_fd_config(lib):
+    """32x32 grid operator composed with itself: sparse x sparse, both operands already column-major
+    after matricisation -> the column-by-column accumulator algorithm with no rearrangement."""
+    p = lib.lco_plan_contract([32] * 4, [0, 1, 2, 3], 4992, [32] * 4, [2, 3, 4, 5], 4992, [0, 1, 4, 5])
+    assert (p.m, p.k, p.n) == (1024, 1024, 1024)
+    assert p.a_class == lib.LCO_SPARSE and p.b_class == lib.LCO_SPARSE
+    assert lib.ALGOS[p.algo] == "CSC"
+    assert (p.permute_a, p.permute_b, p.permute_c) == (0, 0, 0)
+    # output in row-major order: CSR needs no output rearrangement, CSC would
+    q = lib.lco_plan_contract([32] * 4, [0, 1, 2, 3], 4992, [32] * 4, [2, 3, 4, 5], 4992, [4, 5, 0, 1])
+    assert lib.ALGOS[q.algo] in ("CSC", "CSR")
+    assert q.permute_a + q.permute_b + q.permute_c <= 2
+
+
+def test_plan_3d_fd_config(lib):
+    p = lib.lco_plan_contract([128] * 6, [0, 1, 2, 3, 4, 5], 14581760, [128] * 6, [3, 4, 5, 6, 7, 8], 14581760,
+                              [0, 1, 2, 6, 7, 8])
+    assert (p.m, p.k, p.n) == (2**21, 2**21, 2**21)
+    assert lib.ALGOS[p.algo] in ("CSC", "CSR")
+    assert (p.permute_a, p.permute_b, p.permute_c) == (0, 0, 0)
+
+
+def test_plan_hypersparse_kronecker(lib):
+    p = lib.lco_plan_contract([2**16] * 4, [0, 1, 2, 3], 16777201, [2**16] * 4, [2, 3, 4, 5], 16777183,
+                              [0, 1, 4, 5])
+    assert p.a_class == lib.LCO_INDEX_SPARSE and p.b_class == lib.LCO_INDEX_SPARSE
+    assert lib.ALGOS[p.algo] == "SOP"
+    assert (p.permute_a, p.permute_b, p.permute_c) == (0, 1, 0)
+
+
+def test_plan_diagonal_matricisations(lib):
+    """Section 5.1 figure: a 10^4 diagonal tensor is index-sparse in a 2+2 split and column-/row-sparse
+    in 1+3 / 3+1 splits."""
+    p = lib.lco_plan_contract([10] * 4, [0, 1, 2, 3], 10, [10] * 4, [2, 3, 4, 5], 10, [0, 1, 4, 5])
+    assert (p.a_class, p.b_class) == (lib.LCO_INDEX_SPARSE, lib.LCO_INDEX_SPARSE)
+    assert lib.ALGOS[p.algo] == "SOP"
+    q = lib.lco_plan_contract([10] * 4, [0, 1, 2, 3], 10, [10] * 4, [1, 2, 3, 4], 10, [0, 4])
+    assert (q.a_class, q.b_class) == (lib.LCO_COL_SPARSE, lib.LCO_ROW_SPARSE)
+    assert lib.ALGOS[q.algo] in ("DCSC", "DCSR")
+
+
+def test_plan_forced_algorithm_and_errors(lib):
+    for name in ("CSC", "CSR", "DCSC", "DCSR", "CSCNA", "CSRNA", "SOP"):
+        p = lib.lco_plan_contract([5, 6], [0, 1], 10, [6, 7], [1, 2], 10, [0, 2], lib.ALGO_IDS[name])
+        assert lib.ALGOS[p.algo] == name
+    with pytest.raises(lib.LcoError) as e:
+        lib.lco_plan_contract([5, 6], [0, 1], 10, [7, 7], [1, 2], 10, [0, 2])
+    assert e.value.code == 3
+    with pytest.raises(lib.LcoError) as e:
+        lib.lco_plan_contract([5, 6], [0, 1], 10, [6, 7], [1, 2], 10, [0, 1, 2])
+    assert e.value.code == 7
+    with pytest.raises(lib.LcoError) as e:
+        lib.lco_plan_contract([5, 6], [0, 0], 10, [6, 7], [1, 2], 10, [2])
+    assert e.value.code == 1
+    with pytest.raises(lib.LcoError) as e:
+        lib.lco_plan_contract([2**40, 2**30], [0, 1], 10, [2**30, 2**40], [1, 2], 10, [0, 2])
+    assert e.value.code == 2
+    with pytest.raises(lib.LcoError):
+        lib.lco_plan_permute([3, 4], [0, 0], 5)
+
+
+def test_orientation_rule_prefers_fewer_rearrangements(lib):
+    # both operands row-major after matricisation: CSR needs nothing, CSC would rearrange both
+    p = lib.lco_plan_contract([7, 9], [1, 0], 40, [8, 7], [2, 1], 40, [2, 0])
+    # a: modes (k, i) -> row-major; b: modes (j, k) -> row-major; c = (j, i) = CSR's natural layout
+    assert lib.ALGOS[p.algo] == "CSR"
+    assert (p.permute_a, p.permute_b, p.permute_c) == (0, 0, 0)
+    # column-major operands but a row-major output: CSC costs one rearrangement (the output), CSR two
+    q = lib.lco_plan_contract([5, 6], [0, 1], 20, [6, 50], [1, 2], 20, [2, 0])
+    assert lib.ALGOS[q.algo] == "CSC" and (q.permute_a, q.permute_b, q.permute_c) == (0, 0, 1)
+    # ties (one rearrangement either way): column-by-column iff n > m (Section 5.2.2)
+    r = lib.lco_plan_contract([6], [1], 5, [4, 6, 5], [2, 1, 3], 30, [2, 3])      # m = 1, n = 20
+    assert (r.permute_a + r.permute_b + r.permute_c) == 1 and lib.ALGOS[r.algo] == "CSC"
+    r = lib.lco_plan_contract([4, 6, 5], [0, 1, 4], 30, [6], [1], 5, [0, 4])      # m = 20, n = 1
+    assert (r.permute_a + r.permute_b + r.permute_c) == 1 and lib.ALGOS[r.algo] == "CSR"
