@@ -91,6 +91,12 @@ def load_library():
     with _lock:
         if _lib is not None:
             return _lib
+        # One HIP runtime per process: torch ships its own libamdhip64 (same soname); importing torch
+        # first makes the dynamic loader bind liblco.so to that already-loaded runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1802_02619_amd/build.py "
                               "(or __graft_entry__.build()); there is no CPU fallback")

@@ -3,7 +3,9 @@
 Every source under ``csrc/`` is compiled to an object in ``_build/`` (in
 parallel) and linked into ``paper_1802_02619_amd/liblco.so``.  Flags:
 ``-ffp-contract=off`` keeps products and sums separately rounded (no fused
-multiply-add), and packed FP32 instructions are disabled.
+multiply-add), and packed FP32 instructions are disabled.  Code objects are
+version 5 so that the HIP runtime bundled with PyTorch (which the library
+shares when loaded from Python) can load them.
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ LIB = os.path.join(HERE, "liblco.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LCO_OFFLOAD_ARCH", "gfx950")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-mcode-object-version=5", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(os.path.dirname(HERE), "include"), "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unknown-pragmas"]

@@ -1,0 +1,156 @@
+"""GPU parity: construction and radix permutation vs the CPU oracle (bit-exact).
+
+LIVs and values must match the oracle exactly: construction sums duplicates in
+input order on both sides, and permutation moves values without arithmetic.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import lco_inputs as L
+from conftest import gpu_create
+
+pytestmark = pytest.mark.gpu
+
+
+def same(gt, ot):
+    dims, livs, vals = gt.to_numpy()
+    assert dims.tolist() == ot.dims.tolist()
+    assert livs.shape == ot.livs.shape, (livs.shape, ot.livs.shape)
+    assert np.array_equal(livs, ot.livs)
+    assert np.array_equal(vals.view(np.uint64), ot.vals.view(np.uint64))
+
+
+# ---------------------------------------------------------------- construction
+@pytest.mark.parametrize("n", [0, 1, 100, 5000, 8192, 8193, 100000, 300001])
+def test_create_with_duplicates(lco_lib, gpu_ctx, oracle_mod, n):
+    print(f"create n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    dims = [37, 5, 64, 3]
+    coords = np.stack([rng.integers(0, d, n) for d in dims], axis=1).astype(np.uint64)
+    vals = rng.uniform(-1, 1, n)
+    g = gpu_create(lco_lib, gpu_ctx, dims, coords, vals, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES)
+    o = oracle_mod.create(dims, coords, vals, sum_duplicates=True)
+    same(g, o)
+    g.destroy()
+
+
+def test_create_errors(lco_lib, gpu_ctx):
+    import torch
+    dims = [4, 4]
+    with pytest.raises(lco_lib.LcoError) as e:
+        gpu_create(lco_lib, gpu_ctx, dims, [[0, 1], [0, 1]], [1.0, 2.0])
+    assert e.value.code == 5
+    with pytest.raises(lco_lib.LcoError) as e:
+        gpu_create(lco_lib, gpu_ctx, dims, [[0, 4]], [1.0])
+    assert e.value.code == 1
+    livs = torch.tensor([3, 2], dtype=torch.int64, device="cuda")
+    vals = torch.tensor([1.0, 2.0], dtype=torch.float64, device="cuda")
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.lco_create(gpu_ctx, dims, livs, vals, lco_lib.LCO_SORTED)
+    assert e.value.code == 4
+    ok = lco_lib.lco_create(gpu_ctx, dims, livs, vals, 0)  # unsorted LIVs are sorted
+    d, l_, v = ok.to_numpy()
+    assert l_.tolist() == [2, 3] and v.tolist() == [2.0, 1.0]
+    ok.destroy()
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.lco_create(gpu_ctx, [2**40, 2**30], livs, vals, 0)
+    assert e.value.code == 2
+
+
+def test_create_full_64bit_range(lco_lib, gpu_ctx, oracle_mod):
+    rng = np.random.default_rng(64)
+    dims = [2**16] * 4
+    n = 50000
+    coords = np.stack([rng.integers(0, d, n, dtype=np.uint64) for d in dims], axis=1)
+    coords[0] = [2**16 - 1] * 4
+    vals = rng.uniform(-1, 1, n)
+    g = gpu_create(lco_lib, gpu_ctx, dims, coords, vals, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES)
+    o = oracle_mod.create(dims, coords, vals, sum_duplicates=True)
+    same(g, o)
+    assert int(o.livs[-1]) == 2**64 - 1
+    g.destroy()
+
+
+# ---------------------------------------------------------------- permutation
+def _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, perms):
+    g = gpu_create(lco_lib, gpu_ctx, dims, coords, vals)
+    o = oracle_mod.create(dims, coords, vals)
+    for perm in perms:
+        print(f"permute dims={dims} nnz={o.nnz} perm={perm}", flush=True)
+        gp = lco_lib.lco_permute(gpu_ctx, g, list(perm))
+        same(gp, oracle_mod.permute(o, list(perm)))
+        gp.destroy()
+    g.destroy()
+
+
+def test_permute_small_fd_config(lco_lib, gpu_ctx, oracle_mod):
+    """32x32 grid operator, modes (1,2,3,4) -> (3,4,1,2): single-tile LDS path."""
+    c, v = L.fd_laplacian(32, 2)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, [32] * 4, c, v, [(2, 3, 0, 1)])
+
+
+@pytest.mark.parametrize("nnz", [3000, 60000, 250000])
+def test_permute_all_4d_permutations(lco_lib, gpu_ctx, oracle_mod, nnz):
+    """All 24 permutations of an order-4 tensor (the paper's 23 non-identity cases plus identity),
+    on the LDS path and on the multi-tile global path with a ragged last tile."""
+    rng = np.random.default_rng(nnz)
+    dims = [29, 64, 7, 33]
+    coords, vals = L.random_sparse(rng, dims, nnz)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, list(itertools.permutations(range(4))))
+
+
+def test_permute_segmented_paths(lco_lib, gpu_ctx, oracle_mod):
+    """A shared leading resting mode: small regions (segmented LDS path) and large regions
+    (fallback to the global passes)."""
+    rng = np.random.default_rng(11)
+    small = [50, 40, 300, 20]          # regions of constant (mode 2, mode 3) hold <= 2000 entries
+    coords, vals = L.random_sparse(rng, small, 200000)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, small, coords, vals, [(1, 0, 2, 3), (2, 1, 0, 3)])
+    big = [400, 300, 3]                 # regions of constant mode 2 hold ~67k entries
+    coords, vals = L.random_sparse(rng, big, 200000)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, big, coords, vals, [(1, 0, 2)])
+
+
+def test_permute_size_one_modes_and_empty(lco_lib, gpu_ctx, oracle_mod):
+    rng = np.random.default_rng(5)
+    dims = [1, 70, 1, 90]
+    coords, vals = L.random_sparse(rng, dims, 3000)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(1, 0, 2, 3), (2, 3, 0, 1), (3, 1, 0, 2)])
+    e = gpu_create(lco_lib, gpu_ctx, [3, 4], np.zeros((0, 2), np.uint64), np.zeros(0))
+    p = lco_lib.lco_permute(gpu_ctx, e, [1, 0])
+    assert p.nnz == 0 and p.dims == [4, 3]
+
+
+def test_permute_hypersparse_64bit(lco_lib, gpu_ctx, oracle_mod):
+    """Order-4 Kronecker tensor with 2^16 per mode (full 64-bit LIVs): modes (3,4,1,2), 32-bit key."""
+    coords, vals = L.kronecker_hypersparse(16, 1 << 18, seed=2)
+    o = oracle_mod.create([2**16] * 4, coords, vals, sum_duplicates=True)
+    g = gpu_create(lco_lib, gpu_ctx, [2**16] * 4, coords, vals, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES)
+    same(g, o)
+    gp = lco_lib.lco_permute(gpu_ctx, g, [2, 3, 0, 1])
+    same(gp, oracle_mod.permute(o, [2, 3, 0, 1]))
+
+
+def test_permute_3d_fd_operator_order6(lco_lib, gpu_ctx, oracle_mod):
+    c, v = L.fd_laplacian(24, 3)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, [24] * 6, c, v, [(3, 4, 5, 0, 1, 2), (1, 0, 2, 3, 4, 5),
+                                                             (5, 4, 3, 2, 1, 0)])
+
+
+@pytest.mark.slow
+def test_permute_3d_fd_full_size(lco_lib, gpu_ctx, oracle_mod):
+    """128^3 grid operator (14,581,760 entries), modes (1..6) -> (4,5,6,1,2,3): bit-exact vs the oracle;
+    the operator is symmetric, so the result also equals the input."""
+    c, v = L.fd_laplacian(128, 3)
+    o = oracle_mod.create([128] * 6, c, v)
+    assert o.nnz == 14581760
+    g = gpu_create(lco_lib, gpu_ctx, [128] * 6, c, v)
+    same(g, o)
+    gp = lco_lib.lco_permute(gpu_ctx, g, [3, 4, 5, 0, 1, 2])
+    same(gp, oracle_mod.permute(o, [3, 4, 5, 0, 1, 2]))
+    same(gp, o)
+    gp2 = lco_lib.lco_permute(gpu_ctx, g, [3, 4, 5, 0, 1, 2])
+    a1, a2 = gp.to_numpy(), gp2.to_numpy()
+    assert np.array_equal(a1[1], a2[1]) and np.array_equal(a1[2], a2[2])  # deterministic
