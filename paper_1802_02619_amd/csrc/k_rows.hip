@@ -1,0 +1,528 @@
+// Row-by-row sparse products (Section 5.2.2-5.2.4): CSR (accumulator, B
+// compressed by rows), DCSR (accumulator, B doubly compressed), CSRNA (no
+// accumulator: products sorted and summed).  The column-by-column variants
+// (CSC, DCSC, CSCNA) are the same kernels run on the transposed roles: a
+// column-major A is a row-major A^T over the same LIV array, so C = A*B
+// column by column is C^T = B^T * A^T row by row.
+//
+// Layout: A' is m' x k' with LIV = col + k'*row (rows contiguous, cols
+// ascending); B' is k' x n' with LIV = col + n'*row; the product C' gets
+// LIV = col + n'*row.  Each output entry sums its products in ascending order
+// of the contracted index starting from 0.0.
+//
+// Work split: the non-empty rows of A' are binned by their product count f(i).
+//  - f(i) <= 64 and at most 64 A' entries: one wave per row.  CSR/DCSR keep an
+//    LDS hash table (column -> slot) as the sparse accumulator, accumulate in
+//    registers (slot s lives in lane s mod 64) in product order, then sort the
+//    row's distinct columns with a wave bitonic network.  CSRNA sorts the
+//    (column, product index) pairs and sums runs.
+//  - larger rows: products are expanded to global memory keyed by (row rank,
+//    column), sorted with the stable radix engine and summed per run.
+#include <algorithm>
+#include <cstring>
+
+#include "device_common.h"
+#include "rows.h"
+
+namespace lco {
+
+namespace {
+
+constexpr int kRowWaves = 4;
+constexpr int kRowThreads = kRowWaves * kWave;
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = __double_as_longlong(x);
+  const uint32_t lo = readlane_u32((uint32_t)b, l), hi = readlane_u32((uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Bitonic sort of one (key, idx, val) triple per lane across the wave, ascending
+// by (key, idx).
+__device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, double& val) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t ok = __shfl_xor(key, j, kWave);
+      const uint32_t oi = __shfl_xor(idx, j, kWave);
+      const double ov = __shfl_xor(val, j, kWave);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const bool other_less = ok < key || (ok == key && oi < idx);
+      const bool take = (lower == up) ? other_less : !other_less;
+      if (take) {
+        key = ok;
+        idx = oi;
+        val = ov;
+      }
+    }
+  }
+}
+
+template <bool DENSE>
+__device__ __forceinline__ void b_row(const RowArgs& ra, uint64_t j, uint32_t& start, uint32_t& len) {
+  if (DENSE) {
+    start = ra.bptr[j];
+    len = ra.bptr[j + 1] - start;
+  } else {
+    const uint64_t n = *ra.nzr_b;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (ra.brow_id[mid] < j) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < n && ra.brow_id[lo] == j) {
+      start = ra.brow_start[lo];
+      len = ra.brow_start[lo + 1] - start;
+    } else {
+      start = 0;
+      len = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
+  return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
+}
+
+// ---------------------------------------------------------------- setup kernels
+
+__global__ void seg_heads_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv div,
+                                 uint32_t* __restrict__ head) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || fd_div(div, livs[i]) != fd_div(div, livs[i - 1])) ? 1u : 0u;
+}
+
+__global__ void seg_compact_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv div,
+                                   const uint32_t* __restrict__ head, const uint32_t* __restrict__ pos,
+                                   uint64_t* __restrict__ ids, uint32_t* __restrict__ starts) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (head[i]) {
+      ids[pos[i]] = fd_div(div, livs[i]);
+      starts[pos[i]] = (uint32_t)i;
+    }
+    if (i == n - 1) starts[pos[i] + head[i]] = (uint32_t)n;
+  }
+}
+
+// bptr[r] = first B' entry of row r, for r in [0, k'] (bptr[k'] = nnz_b).
+__global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv ndiv, uint64_t kp,
+                                 uint32_t* __restrict__ bptr) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = e == 0 ? 0 : fd_div(ndiv, livs[e - 1]) + 1;
+    const uint64_t hi = e == n ? kp : fd_div(ndiv, livs[e]);
+    for (uint64_t r = lo; r <= hi; ++r) bptr[r] = (uint32_t)e;
+  }
+}
+
+template <bool DENSE>
+__global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ra.nnz_a;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t j;
+    fd_divmod(ra.kdiv, ra.a_livs[e], j);
+    uint32_t s, l;
+    b_row<DENSE>(ra, j, s, l);
+    len[e] = l;
+  }
+}
+
+// Bins non-empty rows of A' by product count.
+__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint32_t* __restrict__ list0,
+                                    uint32_t* __restrict__ list2, uint64_t* __restrict__ counters,
+                                    uint64_t* __restrict__ f2, uint32_t* __restrict__ is2) {
+  const uint64_t nzr = *ra.nzr_a;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
+    if ((uint64_t)r >= nzr) break;
+    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+    const uint64_t f = ra.poff[e1] - ra.poff[e0];
+    if (f == 0) continue;
+    if (f <= (uint64_t)kWave && e1 - e0 <= (uint32_t)kWave) {
+      const uint64_t i = atomicAdd((unsigned long long*)&counters[0], 1ull);
+      list0[i] = (uint32_t)r;
+    } else {
+      const uint64_t i = atomicAdd((unsigned long long*)&counters[1], 1ull);
+      list2[i] = (uint32_t)r;
+      f2[r] = f;
+      is2[r] = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- one wave per row
+
+template <bool DENSE, bool ACC, bool NUMERIC>
+__global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, const uint32_t* __restrict__ list,
+                                                                uint32_t count, uint64_t* __restrict__ cnt,
+                                                                const uint64_t* __restrict__ coff,
+                                                                uint64_t* __restrict__ out_livs,
+                                                                double* __restrict__ out_vals) {
+  __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
+  __shared__ uint64_t s_ocol[kRowWaves][kWave];
+  __shared__ double s_oval[kRowWaves][kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t nw = gridDim.x * kRowWaves;
+  for (uint32_t li = blockIdx.x * kRowWaves + w; li < count; li += nw) {
+    const uint32_t r = list[li];
+    const uint32_t e0 = ra.row_start[r];
+    const int t = (int)(ra.row_start[r + 1] - e0);
+    const uint64_t row = ra.row_id[r];
+    uint64_t j = 0;
+    uint32_t bs = 0, len = 0;
+    double av = 0.0;
+    if (lane < t) {
+      const uint64_t la = ra.a_livs[e0 + lane];
+      j = la - ra.kp * row;
+      b_row<DENSE>(ra, j, bs, len);
+      if (NUMERIC) av = ra.a_vals[e0 + lane];
+    }
+    const uint32_t incl = wave_inclusive_scan<uint32_t>(len);
+    const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
+    // product p = lane: its A' entry is the first lane whose inclusive count exceeds p
+    const uint32_t p = (uint32_t)lane;
+    int lo = 0, hi = t - 1;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const uint32_t v = (uint32_t)__shfl((int)incl, mid, kWave);
+      if (lo < hi) {
+        if (v > p) hi = mid;
+        else lo = mid + 1;
+      }
+    }
+    const uint32_t excl_e = (uint32_t)__shfl((int)(incl - len), lo, kWave);
+    const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
+    const uint64_t j_e = __shfl(j, lo, kWave);
+    const double av_e = __shfl(av, lo, kWave);
+    const bool valid = p < f;
+    uint64_t col = kEmpty;
+    double v = 0.0;
+    if (valid) {
+      const uint32_t q = bs_e + (p - excl_e);
+      col = ra.b_livs[q] - ra.np * j_e;
+      if (NUMERIC) v = av_e * ra.b_vals[q];
+    }
+    if (ACC) {
+      // sparse accumulator: LDS hash table mapping a column to a slot
+      s_hash[w][lane] = kEmpty;
+      s_hash[w][lane + kWave] = kEmpty;
+      wave_lds_sync();
+      uint32_t slot = valid ? hash_slot(col) : 0;
+      bool isnew = false;
+      if (valid) {
+        for (int probe = 0; probe < 2 * kWave; ++probe) {
+          const uint64_t prev = atomicCAS((unsigned long long*)&s_hash[w][slot], (unsigned long long)kEmpty,
+                                          (unsigned long long)col);
+          if (prev == kEmpty) {
+            isnew = true;
+            break;
+          }
+          if (prev == col) break;
+          slot = (slot + 1) & (2 * kWave - 1);
+        }
+      }
+      const uint64_t newmask = __ballot(isnew);
+      const uint32_t distinct = (uint32_t)__popcll(newmask);
+      if (!NUMERIC) {
+        if (lane == 0) cnt[r] = distinct;
+      } else {
+        wave_lds_sync();
+        // accumulate in product order; slot s is held by lane s % 64
+        double acc0 = 0.0, acc1 = 0.0;
+        for (uint32_t s = 0; s < f; ++s) {
+          const uint32_t sl = readlane_u32(slot, (int)s);
+          const double vs = readlane_f64(v, (int)s);
+          if ((int)(sl & (kWave - 1)) == lane) {
+            if (sl < (uint32_t)kWave) acc0 += vs;
+            else acc1 += vs;
+          }
+        }
+        // gather occupied slots, then sort the row's distinct columns
+        const uint64_t c0 = s_hash[w][lane], c1 = s_hash[w][lane + kWave];
+        const uint64_t m0 = __ballot(c0 != kEmpty), m1 = __ballot(c1 != kEmpty);
+        const uint32_t base1 = (uint32_t)__popcll(m0);
+        if (c0 != kEmpty) {
+          const uint32_t pos = (uint32_t)__popcll(m0 & lanemask_lt());
+          s_ocol[w][pos] = c0;
+          s_oval[w][pos] = acc0;
+        }
+        if (c1 != kEmpty) {
+          const uint32_t pos = base1 + (uint32_t)__popcll(m1 & lanemask_lt());
+          s_ocol[w][pos] = c1;
+          s_oval[w][pos] = acc1;
+        }
+        wave_lds_sync();
+        uint64_t key = lane < (int)distinct ? s_ocol[w][lane] : kEmpty;
+        double val = lane < (int)distinct ? s_oval[w][lane] : 0.0;
+        uint32_t idx = 0;
+        wave_bitonic(key, idx, val);
+        if (lane < (int)distinct) {
+          const uint64_t o = coff[r] + lane;
+          out_livs[o] = key + ra.np * row;
+          out_vals[o] = val;
+        }
+        wave_lds_sync();
+      }
+    } else {
+      // no accumulator: sort (column, product index), then each run head sums its run
+      uint64_t key = col;
+      uint32_t idx = p;
+      double val = v;
+      wave_bitonic(key, idx, val);
+      const uint64_t prev = __shfl_up(key, 1, kWave);
+      const bool head = lane < (int)f && (lane == 0 || prev != key);
+      const uint64_t hmask = __ballot(head);
+      if (!NUMERIC) {
+        if (lane == 0) cnt[r] = (uint64_t)__popcll(hmask);
+      } else {
+        double acc = 0.0;
+        bool active = head;
+        if (head) acc += val;
+        for (int s = 1; s < kWave; ++s) {
+          const uint64_t ks = __shfl_down(key, s, kWave);
+          const double vs = __shfl_down(val, s, kWave);
+          if (active) {
+            if (lane + s < (int)f && ks == key) acc += vs;
+            else active = false;
+          }
+          if (!__any(active)) break;
+        }
+        if (head) {
+          const uint64_t o = coff[r] + (uint64_t)__popcll(hmask & lanemask_lt());
+          out_livs[o] = key + ra.np * row;
+          out_vals[o] = acc;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- long rows (global sort)
+
+constexpr int kBigThreads = 256;
+
+template <bool DENSE>
+__global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, const uint32_t* __restrict__ list,
+                                                                 uint32_t count, const uint64_t* __restrict__ off2,
+                                                                 const uint32_t* __restrict__ q2, int colbits,
+                                                                 uint64_t* __restrict__ keys,
+                                                                 double* __restrict__ vals) {
+  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    const uint32_t r = list[li];
+    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+    const uint64_t p0 = ra.poff[e0];
+    const uint64_t f = ra.poff[e1] - p0;
+    const uint64_t row = ra.row_id[r];
+    const uint64_t qk = (uint64_t)q2[r] << colbits;
+    const uint64_t base = off2[r];
+    for (uint64_t p = threadIdx.x; p < f; p += kBigThreads) {
+      // last A' entry e in [e0, e1) with poff[e] <= p0 + p
+      uint32_t lo = e0, hi = e1 - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (ra.poff[mid] <= p0 + p) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint64_t j = ra.a_livs[lo] - ra.kp * row;
+      uint32_t bs, len;
+      b_row<DENSE>(ra, j, bs, len);
+      const uint32_t q = bs + (uint32_t)(p0 + p - ra.poff[lo]);
+      const uint64_t col = ra.b_livs[q] - ra.np * j;
+      keys[base + p] = qk | col;
+      vals[base + p] = ra.a_vals[lo] * ra.b_vals[q];
+    }
+  }
+}
+
+// Distinct keys of each long row (symbolic) or their run sums (numeric).
+template <bool NUMERIC>
+__global__ __launch_bounds__(kBigThreads) void big_reduce_kernel(RowArgs ra, const uint32_t* __restrict__ list,
+                                                                 uint32_t count, const uint64_t* __restrict__ off2,
+                                                                 const uint64_t* __restrict__ keys,
+                                                                 const double* __restrict__ vals,
+                                                                 uint64_t colmask, uint64_t* __restrict__ cnt,
+                                                                 const uint64_t* __restrict__ coff,
+                                                                 uint64_t* __restrict__ out_livs,
+                                                                 double* __restrict__ out_vals) {
+  __shared__ uint32_t wsum[kBigThreads / kWave + 1];
+  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    const uint32_t r = list[li];
+    const uint64_t f = ra.poff[ra.row_start[r + 1]] - ra.poff[ra.row_start[r]];
+    const uint64_t base = off2[r];
+    const uint64_t row = ra.row_id[r];
+    uint64_t run = 0;  // heads seen before this chunk
+    for (uint64_t c0 = 0; c0 < f; c0 += kBigThreads) {
+      const uint64_t p = c0 + threadIdx.x;
+      const bool head = p < f && (p == 0 || keys[base + p] != keys[base + p - 1]);
+      uint32_t total;
+      const uint32_t ex = block_exclusive_scan<uint32_t>(head ? 1u : 0u, wsum, total);
+      if (NUMERIC && head) {
+        const uint64_t key = keys[base + p];
+        double acc = 0.0;
+        for (uint64_t q = p; q < f && keys[base + q] == key; ++q) acc += vals[base + q];
+        const uint64_t o = coff[r] + run + ex;
+        out_livs[o] = (key & colmask) + ra.np * row;
+        out_vals[o] = acc;
+      }
+      run += total;
+    }
+    if (!NUMERIC && threadIdx.x == 0) cnt[r] = run;
+  }
+}
+
+int grid_for(lco_ctx ctx, int64_t n, int threads) {
+  const int64_t want = (n + threads - 1) / threads;
+  const int64_t cap = (int64_t)ctx->num_cus * 16;
+  return (int)(want < 1 ? 1 : (want > cap ? cap : want));
+}
+
+}  // namespace
+
+Segments segment_livs(lco_ctx ctx, Scratch& s, const uint64_t* livs, int64_t n, const FastDiv& div) {
+  Segments sg;
+  sg.count = s.get<uint64_t>(1);
+  memset_async(ctx, sg.count, 0, sizeof(uint64_t));
+  uint32_t* head = s.get<uint32_t>(n);
+  uint32_t* pos = s.get<uint32_t>(n);
+  sg.ids = s.get<uint64_t>(n);
+  sg.starts = s.get<uint32_t>(n + 1);
+  LCO_LAUNCH(ctx, "seg_heads", seg_heads_kernel, grid_for(ctx, n, 256), 256, 0, livs, n, div, head);
+  scan_u32(ctx, head, pos, n, (uint32_t*)sg.count);
+  LCO_LAUNCH(ctx, "seg_compact", seg_compact_kernel, grid_for(ctx, n, 256), 256, 0, livs, n, div, head, pos, sg.ids,
+             sg.starts);
+  return sg;
+}
+
+lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, uint64_t mp, uint64_t kp,
+                      uint64_t np, bool dense, bool acc, int out_order, const uint64_t* out_dims) {
+  (void)mp;
+  const int64_t na = A->nnz, nb = B->nnz;
+  Scratch s(ctx);
+  RowArgs ra;
+  ra.a_livs = A->livs;
+  ra.a_vals = A->vals;
+  ra.nnz_a = na;
+  ra.b_livs = B->livs;
+  ra.b_vals = B->vals;
+  ra.nnz_b = nb;
+  ra.kdiv = make_fastdiv(kp);
+  ra.kp = kp;
+  ra.np = np;
+  const FastDiv ndiv = make_fastdiv(np);
+  // rows of A'
+  Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
+  ra.row_start = arows.starts;
+  ra.row_id = arows.ids;
+  ra.nzr_a = arows.count;
+  // compressed B'
+  if (dense) {
+    if (kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "contract: singly-compressed row pointer of more than 2^34 entries");
+    uint32_t* bptr = s.get<uint32_t>(kp + 1);
+    LCO_LAUNCH(ctx, "dense_ptr", dense_ptr_kernel, grid_for(ctx, nb + 1, 256), 256, 0, B->livs, nb, ndiv, kp, bptr);
+    ra.bptr = bptr;
+  } else {
+    Segments brows = segment_livs(ctx, s, B->livs, nb, ndiv);
+    ra.brow_id = brows.ids;
+    ra.brow_start = brows.starts;
+    ra.nzr_b = brows.count;
+  }
+  // product counts per A' entry and their prefix
+  uint64_t* len = s.get<uint64_t>(na);
+  uint64_t* poff = s.get<uint64_t>(na + 1);
+  if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len);
+  else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len);
+  scan_u64(ctx, len, poff, na, poff + na);
+  ra.poff = poff;
+  // bin rows
+  uint32_t* list0 = s.get<uint32_t>(na);
+  uint32_t* list2 = s.get<uint32_t>(na);
+  uint64_t* counters = s.get<uint64_t>(4);
+  uint64_t* f2 = s.get<uint64_t>(na);
+  uint32_t* is2 = s.get<uint32_t>(na);
+  uint64_t* off2 = s.get<uint64_t>(na + 1);
+  uint32_t* q2 = s.get<uint32_t>(na);
+  memset_async(ctx, counters, 0, 4 * sizeof(uint64_t));
+  memset_async(ctx, f2, 0, na * sizeof(uint64_t));
+  memset_async(ctx, is2, 0, na * sizeof(uint32_t));
+  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, list0, list2,
+             counters, f2, is2);
+  scan_u64(ctx, f2, off2, na, counters + 2);
+  scan_u32(ctx, is2, q2, na, nullptr);
+  const uint64_t* rb1[4] = {arows.count, counters, counters + 1, counters + 2};
+  const uint64_t* h = readback(ctx, rb1, 4);
+  const uint64_t nzr = h[0], n0 = h[1], n2 = h[2], f2_total = h[3];
+  // per-row output counts
+  uint64_t* cnt = s.get<uint64_t>(nzr + 1);
+  uint64_t* coff = s.get<uint64_t>(nzr + 1);
+  memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));
+  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n0 + kRowWaves - 1) / kRowWaves,
+                                                                       (uint64_t)ctx->num_cus * 64));
+#define LCO_ROW_SMALL(NUM, ...)                                                                                 \
+  do {                                                                                                          \
+    if (dense && acc) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<true, true, NUM>), \
+                                 small_grid, kRowThreads, 0, __VA_ARGS__);                                      \
+    else if (dense) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<true, false, NUM>), \
+                               small_grid, kRowThreads, 0, __VA_ARGS__);                                        \
+    else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<false, true, NUM>),          \
+                    small_grid, kRowThreads, 0, __VA_ARGS__);                                                   \
+  } while (0)
+  if (n0) LCO_ROW_SMALL(false, ra, list0, (uint32_t)n0, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                        (double*)nullptr);
+  // long rows: expand, sort by (row rank, column), count distinct
+  uint64_t* keys = nullptr;
+  double* pvals = nullptr;
+  uint64_t colmask = 0;
+  const int big_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(n2, (uint64_t)ctx->num_cus * 8));
+  if (n2) {
+    const int colbits = bits_for(np - 1);
+    const int qbits = bits_for(n2 - 1);
+    if (colbits + qbits > 64) fail(LCO_E_UNSUPPORTED, "contract: long-row sort key exceeds 64 bits");
+    colmask = colbits == 64 ? ~0ull : ((1ull << colbits) - 1);
+    uint64_t* ek = s.get<uint64_t>(f2_total);
+    double* ev = s.get<double>(f2_total);
+    keys = s.get<uint64_t>(f2_total);
+    pvals = s.get<double>(f2_total);
+    if (dense)
+      LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2, off2,
+                 q2, colbits, ek, ev);
+    else
+      LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
+                 off2, q2, colbits, ek, ev);
+    KeyParams kparams;
+    radix_sort_pairs(ctx, ek, ev, keys, pvals, (int64_t)f2_total, nullptr, kparams, colbits + qbits, 0);
+    LCO_LAUNCH(ctx, "big_reduce_sym", big_reduce_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
+               off2, (const uint64_t*)keys, (const double*)pvals, colmask, cnt, (const uint64_t*)nullptr,
+               (uint64_t*)nullptr, (double*)nullptr);
+  }
+  scan_u64(ctx, cnt, coff, nzr, coff + nzr);
+  const uint64_t* rb2[1] = {coff + nzr};
+  const uint64_t nnz_c = readback(ctx, rb2, 1)[0];
+  if (nnz_c > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "contract: more than 2^32-1 output entries");
+  lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
+  try {
+    if (n0) LCO_ROW_SMALL(true, ra, list0, (uint32_t)n0, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    if (n2)
+      LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
+                 off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,
+                 (const uint64_t*)coff, C->livs, C->vals);
+  } catch (...) {
+    lco_destroy(C);
+    throw;
+  }
+#undef LCO_ROW_SMALL
+  return C;
+}
+
+}  // namespace lco

@@ -1,0 +1,45 @@
+// Shared declarations of the multiplication kernels (row-wise engine and outer product).
+#pragma once
+
+#include "lco_internal.h"
+
+namespace lco {
+
+// Non-empty groups of a sorted LIV array, group id = LIV / div (device arrays
+// sized for the worst case; the group count lives on the device).
+struct Segments {
+  uint64_t* ids = nullptr;     // group ids, ascending
+  uint32_t* starts = nullptr;  // first entry of each group, plus a terminal entry
+  uint64_t* count = nullptr;   // device word: number of groups
+};
+Segments segment_livs(lco_ctx ctx, Scratch& s, const uint64_t* livs, int64_t n, const FastDiv& div);
+
+// Arguments of the row-wise product kernels (see k_rows.hip for the layout).
+struct RowArgs {
+  const uint64_t* a_livs = nullptr;
+  const double* a_vals = nullptr;
+  int64_t nnz_a = 0;
+  const uint64_t* b_livs = nullptr;
+  const double* b_vals = nullptr;
+  int64_t nnz_b = 0;
+  FastDiv kdiv;          // k': row of A' = LIV / k'
+  uint64_t kp = 1, np = 1;
+  const uint32_t* bptr = nullptr;        // singly compressed B': k'+1 row starts
+  const uint64_t* brow_id = nullptr;     // doubly compressed B': non-empty row ids
+  const uint32_t* brow_start = nullptr;  //   and their starts (plus terminal)
+  const uint64_t* nzr_b = nullptr;       //   device count of non-empty rows
+  const uint32_t* row_start = nullptr;   // non-empty rows of A': starts (plus terminal)
+  const uint64_t* row_id = nullptr;      //   and ids
+  const uint64_t* nzr_a = nullptr;       //   device count
+  const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
+};
+
+// C' = A' * B' row by row; `dense` selects singly (CSR) or doubly (DCSR)
+// compressed B', `acc` the sparse accumulator (CSR, DCSR) or none (CSRNA).
+lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, uint64_t mp, uint64_t kp,
+                      uint64_t np, bool dense, bool acc, int out_order, const uint64_t* out_dims);
+
+// Simple outer product (Section 5.2.5) of A (column-major) and B (row-major).
+lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, const ContractDetail& d);
+
+}  // namespace lco

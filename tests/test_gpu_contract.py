@@ -1,0 +1,325 @@
+"""GPU parity: contraction (every algorithm of the poly-algorithm) vs the CPU oracle.
+
+Indices and sparsity patterns must be bit-exact.  FP64 values must agree to
+1e-12 relative per entry; where an entry's terms cancel (|c| < 1e-3 * sum|terms|)
+the bound is 1e-12 * sum|terms|.  Integer-valued inputs (the FD operators) must
+be bit-exact, and so must every case where both sides sum in the same order
+(ascending contracted index in the first operand's mode order, from 0.0).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import lco_inputs as L
+from conftest import gpu_create
+
+pytestmark = pytest.mark.gpu
+
+FORCED = ["CSC", "CSR", "DCSC", "DCSR", "CSCNA", "CSRNA", "SOP"]
+TOL = 1e-12
+
+
+def to_np(t):
+    d, livs, vals = t.to_numpy()
+    return d, livs, vals
+
+
+def check(gt, ot, exact=False, what=""):
+    d, livs, vals = to_np(gt)
+    assert d.tolist() == ot.dims.tolist(), what
+    assert livs.shape == ot.livs.shape, (what, livs.shape, ot.livs.shape)
+    assert np.array_equal(livs, ot.livs), what
+    if exact:
+        assert np.array_equal(vals.view(np.uint64), ot.vals.view(np.uint64)), what
+        return
+    err = np.abs(vals - ot.vals)
+    cancel = np.abs(ot.vals) < 1e-3 * ot.absum
+    bound = np.where(cancel, TOL * ot.absum, TOL * np.abs(ot.vals))
+    bad = err > bound
+    assert not bad.any(), (what, int(bad.sum()), float(err.max()))
+
+
+def pair(lco, ctx, ora, dims, coords, vals):
+    return gpu_create(lco, ctx, dims, coords, vals), ora.create(dims, coords, vals)
+
+
+def run_all(lco, ctx, ora, ga, oa, la, gb, ob, lb, lc, exact=False, algos=("auto",) + tuple(FORCED)):
+    ref = ora.contract(oa, la, ob, lb, lc)
+    first = None
+    for name in algos:
+        flags = 0 if name == "auto" else lco.ALGO_IDS[name]
+        print(f"contract {la}x{lb}->{lc} algo={name} nnz={oa.nnz},{ob.nnz}", flush=True)
+        gc = lco.lco_contract(ctx, ga, la, gb, lb, lc, flags)
+        check(gc, ref, exact, f"{name} {la} {lb} {lc}")
+        if first is None:
+            first = to_np(gc)
+        gc.destroy()
+    return ref
+
+
+# ---------------------------------------------------------------- small FD config
+def test_small_fd_config_all_algorithms(lco_lib, gpu_ctx, oracle_mod):
+    """32x32 grid operator composed with itself over modes (3,4)x(1,2): 12,676 entries, exact,
+    and equal to the dense 1024x1024 matrix product."""
+    c, v = L.fd_laplacian(32, 2)
+    g, o = pair(lco_lib, gpu_ctx, oracle_mod, [32] * 4, c, v)
+    plan = lco_lib.lco_plan_info(gpu_ctx, g, [0, 1, 2, 3], g, [2, 3, 4, 5], [0, 1, 4, 5])
+    assert lco_lib.ALGOS[plan.algo] == "CSC" and plan.permute_a + plan.permute_b + plan.permute_c == 0
+    ref = run_all(lco_lib, gpu_ctx, oracle_mod, g, o, [0, 1, 2, 3], g, o, [2, 3, 4, 5], [0, 1, 4, 5], exact=True)
+    assert ref.nnz == 12676
+    M = np.zeros((1024, 1024))
+    M[(c[:, 0] + 32 * c[:, 1]).astype(int), (c[:, 2] + 32 * c[:, 3]).astype(int)] = v
+    gc = lco_lib.lco_contract(gpu_ctx, g, [0, 1, 2, 3], g, [2, 3, 4, 5], [0, 1, 4, 5])
+    _, livs, vals = to_np(gc)
+    D = np.zeros_like(M)
+    D[(livs % 1024).astype(int), (livs // 1024).astype(int)] = vals
+    assert np.array_equal(D, M @ M)
+
+
+# ---------------------------------------------------------------- all index matchings
+def matchings(n):
+    out = []
+    for i in range(n + 1):
+        for sa in itertools.combinations(range(n), i):
+            for sb in itertools.permutations(range(n), i):
+                out.append(list(zip(sa, sb)))
+    return out
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_all_matchings_every_algorithm(lco_lib, gpu_ctx, oracle_mod, n):
+    rng = np.random.default_rng(40 + n)
+    for mi, match in enumerate(matchings(n)):
+        dims_a = [int(x) for x in rng.integers(2, 7, n)]
+        dims_b = [int(x) for x in rng.integers(2, 7, n)]
+        for (ia, ib) in match:
+            dims_b[ib] = dims_a[ia]
+        ca, va = L.random_sparse(rng, dims_a, 30, integer_values=True)
+        cb, vb = L.random_sparse(rng, dims_b, 30, integer_values=True)
+        ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, dims_a, ca, va)
+        gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, dims_b, cb, vb)
+        la = list(range(n))
+        lb = [n + j for j in range(n)]
+        for (ia, ib) in match:
+            lb[ib] = la[ia]
+        lc = [la[i] for i in range(n) if i not in {x for x, _ in match}] + \
+             [lb[j] for j in range(n) if j not in {y for _, y in match}]
+        if mi % 3 == 1:
+            lc = lc[::-1]
+        elif mi % 3 == 2 and len(lc) > 2:
+            lc = lc[1:] + lc[:1]
+        run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
+        ga.destroy()
+        gb.destroy()
+
+
+# ---------------------------------------------------------------- random FP64, multi-tile
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_fp64_every_algorithm(lco_lib, gpu_ctx, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    dims_a, dims_b = [30, 40, 25], [25, 40, 35]
+    ca, va = L.random_sparse(rng, dims_a, 9000)
+    cb, vb = L.random_sparse(rng, dims_b, 9000)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, dims_a, ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, dims_b, cb, vb)
+    # a_ijk b_kjl -> c_il : contracted (j, k) in a's order -> bit-exact against the oracle
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [2, 1, 3], [0, 3], exact=True)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [2, 1, 3], [3, 0], exact=True)
+
+
+def test_long_rows_global_path(lco_lib, gpu_ctx, oracle_mod):
+    """Rows with more than 64 products go through the global sort path."""
+    rng = np.random.default_rng(9)
+    ca, va = L.random_sparse(rng, [60, 300], 6000)
+    cb, vb = L.random_sparse(rng, [300, 200], 9000)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [60, 300], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [300, 200], cb, vb)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [0, 2], exact=True)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [2, 0], exact=True)
+
+
+# ---------------------------------------------------------------- hyper-sparse cells of the table
+def test_rowsparse_times_colsparse_uses_no_accumulator(lco_lib, gpu_ctx, oracle_mod):
+    """a_ijk b_lmk (Section 5.2.4): A row-sparse, B column-sparse -> CSCNA/CSRNA."""
+    rng = np.random.default_rng(21)
+    d = [128, 128, 128]
+    ca, va = L.random_sparse(rng, d, 3000)
+    cb, vb = L.random_sparse(rng, d, 3000)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, d, ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, d, cb, vb)
+    la, lb, lc = [0, 1, 2], [3, 4, 2], [0, 1, 3, 4]
+    p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
+    assert (p.a_class, p.b_class) == (lco_lib.LCO_ROW_SPARSE, lco_lib.LCO_COL_SPARSE)
+    assert lco_lib.ALGOS[p.algo] in ("CSCNA", "CSRNA")
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
+
+
+def test_colsparse_times_rowsparse_uses_doubly_compressed(lco_lib, gpu_ctx, oracle_mod):
+    """a_ijk b_ljk (Section 5.2.3): A column-sparse, B row-sparse -> DCSC/DCSR."""
+    rng = np.random.default_rng(22)
+    d = [128, 128, 128]
+    ca, va = L.random_sparse(rng, d, 3000)
+    cb, vb = L.random_sparse(rng, d, 3000)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, d, ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, d, cb, vb)
+    la, lb, lc = [0, 1, 2], [3, 1, 2], [0, 3]
+    p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
+    assert (p.a_class, p.b_class) == (lco_lib.LCO_COL_SPARSE, lco_lib.LCO_ROW_SPARSE)
+    assert lco_lib.ALGOS[p.algo] in ("DCSC", "DCSR")
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
+
+
+@pytest.mark.parametrize("bits,draws", [(6, 3000), (10, 60000)])
+def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws):
+    """Scaled-down hyper-sparse Kronecker pair contracted over (3,4)x(1,2): index-sparse x
+    index-sparse -> SOP, with the second operand rearranged."""
+    ca, va = L.kronecker_hypersparse(bits, draws, seed=1)
+    cb, vb = L.kronecker_hypersparse(bits, draws, seed=2)
+    dims = [2**bits] * 4
+    flags = lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES
+    ga = gpu_create(lco_lib, gpu_ctx, dims, ca, va, flags)
+    gb = gpu_create(lco_lib, gpu_ctx, dims, cb, vb, flags)
+    oa = oracle_mod.create(dims, ca, va, sum_duplicates=True)
+    ob = oracle_mod.create(dims, cb, vb, sum_duplicates=True)
+    la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
+    p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
+    if bits == 10:
+        assert lco_lib.ALGOS[p.algo] == "SOP" and p.permute_b == 1
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
+
+
+def test_diagonal_tensor_splits(lco_lib, gpu_ctx, oracle_mod):
+    c, v = L.diagonal(4, 10)
+    g, o = pair(lco_lib, gpu_ctx, oracle_mod, [10] * 4, c, v)
+    for lb, lc in (([2, 3, 4, 5], [0, 1, 4, 5]), ([1, 2, 3, 4], [0, 4]), ([4, 0, 1, 2], [3, 4])):
+        ref = run_all(lco_lib, gpu_ctx, oracle_mod, g, o, [0, 1, 2, 3], g, o, lb, lc, exact=True)
+        assert ref.nnz == 10
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_cases(lco_lib, gpu_ctx, oracle_mod):
+    rng = np.random.default_rng(3)
+    ca, va = L.random_sparse(rng, [6, 7], 20)
+    cb, vb = L.random_sparse(rng, [7, 5], 20)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [6, 7], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [7, 5], cb, vb)
+    # full contraction to a scalar (order-0 output)
+    gs, os_ = pair(lco_lib, gpu_ctx, oracle_mod, [7, 5], *L.random_sparse(rng, [7, 5], 15))
+    ref = oracle_mod.contract(ob, [0, 1], os_, [0, 1], [])
+    got = lco_lib.lco_contract(gpu_ctx, gb, [0, 1], gs, [0, 1], [])
+    check(got, ref)
+    # outer product (nothing contracted)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [2, 3], [0, 1, 2, 3], exact=True)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [2, 3], [2, 0, 3, 1], exact=True)
+    # empty operand
+    ge = gpu_create(lco_lib, gpu_ctx, [7, 5], np.zeros((0, 2), np.uint64), np.zeros(0))
+    r = lco_lib.lco_contract(gpu_ctx, ga, [0, 1], ge, [1, 2], [0, 2])
+    assert r.nnz == 0 and r.dims == [6, 5]
+    # products that cancel exactly are kept as explicit zeros
+    a = gpu_create(lco_lib, gpu_ctx, [2, 2], np.array([[0, 0], [0, 1]], np.uint64), np.array([1.0, 1.0]))
+    b = gpu_create(lco_lib, gpu_ctx, [2, 2], np.array([[0, 0], [1, 0]], np.uint64), np.array([1.0, -1.0]))
+    for name in ["auto"] + FORCED:
+        r = lco_lib.lco_contract(gpu_ctx, a, [0, 1], b, [1, 2], [0, 2], 0 if name == "auto" else lco_lib.ALGO_IDS[name])
+        _, l_, v_ = to_np(r)
+        assert l_.tolist() == [0] and v_.tolist() == [0.0], name
+    # errors are reported before any device work
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.lco_contract(gpu_ctx, ga, [0, 1], gb, [0, 2], [0, 1, 2])
+    assert e.value.code == 7
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.lco_contract(gpu_ctx, ga, [0, 1], ga, [1, 2], [0, 2])
+    assert e.value.code == 3
+
+
+def test_deterministic(lco_lib, gpu_ctx, oracle_mod):
+    rng = np.random.default_rng(77)
+    ca, va = L.random_sparse(rng, [40, 50, 40], 20000)
+    g, _ = pair(lco_lib, gpu_ctx, oracle_mod, [40, 50, 40], ca, va)
+    outs = []
+    for _ in range(2):
+        for name in FORCED:
+            r = lco_lib.lco_contract(gpu_ctx, g, [0, 1, 2], g, [2, 1, 3], [0, 3], lco_lib.ALGO_IDS[name])
+            outs.append(to_np(r))
+            r.destroy()
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2].view(np.uint64), outs[0][2].view(np.uint64))
+
+
+# ---------------------------------------------------------------- full-size configurations
+def squared_laplacian_values(livs, side, dim):
+    co = np.stack(np.unravel_index(livs.astype(np.int64), [side] * (2 * dim), order="F"), 1)
+    p, q = co[:, :dim], co[:, dim:]
+    d = q - p
+    l1 = np.abs(d).sum(1)
+    deg = np.zeros(len(p), np.int64)
+    for ax in range(dim):
+        deg += (p[:, ax] > 0).astype(np.int64) + (p[:, ax] < side - 1).astype(np.int64)
+    return np.where(l1 == 0, 4 * dim * dim + deg,
+                    np.where(l1 == 1, -4 * dim, np.where(np.abs(d).max(1) == 2, 1, 2))).astype(np.float64)
+
+
+@pytest.mark.slow
+def test_3d_fd_config_full_size(lco_lib, gpu_ctx, oracle_mod):
+    """128^3 grid (14,581,760 entries): permute (4,5,6,1,2,3), then compose over 3 modes:
+    51,742,208 entries, every value equal to the closed form, sampled rows equal to the oracle."""
+    s = 128
+    c, v = L.fd_laplacian(s, 3)
+    g = gpu_create(lco_lib, gpu_ctx, [s] * 6, c, v)
+    p = lco_lib.lco_permute(gpu_ctx, g, [3, 4, 5, 0, 1, 2])
+    la, lb, lc = [0, 1, 2, 3, 4, 5], [3, 4, 5, 6, 7, 8], [0, 1, 2, 6, 7, 8]
+    for name in ("auto", "CSR", "CSRNA"):
+        flags = 0 if name == "auto" else lco_lib.ALGO_IDS[name]
+        print(f"full 3-D composition algo={name}", flush=True)
+        r = lco_lib.lco_contract(gpu_ctx, p, la, p, lb, lc, flags)
+        _, livs, vals = to_np(r)
+        assert livs.shape[0] == 51742208
+        assert np.all(livs[1:] > livs[:-1])
+        assert np.array_equal(vals, squared_laplacian_values(livs, s, 3))
+        r.destroy()
+    # oracle on sampled rows (output grid points), incl. corners and faces
+    rng = np.random.default_rng(2)
+    rows = np.unique(np.concatenate([rng.integers(0, s**3, 3000), [0, s - 1, s**3 - 1, s * s * 64 + 64 * s]]))
+    o = oracle_mod.create([s] * 6, c, v)
+    keep = np.isin(o.livs % np.uint64(s**3), rows.astype(np.uint64))
+    sub = oracle_mod.Tensor(o.dims, o.livs[keep], o.vals[keep])
+    ref = oracle_mod.contract(sub, la, o, lb, lc, mode="sort")
+    r = lco_lib.lco_contract(gpu_ctx, p, la, p, lb, lc)
+    _, livs, vals = to_np(r)
+    pick = np.isin(livs % np.uint64(s**3), rows.astype(np.uint64))
+    assert np.array_equal(livs[pick], ref.livs)
+    assert np.array_equal(vals[pick], ref.vals)
+
+
+@pytest.mark.slow
+def test_hypersparse_kronecker_full_size(lco_lib, gpu_ctx, oracle_mod):
+    """Order-4 Kronecker pair, 2^16 per mode, 2^24 draws each (seeds 1, 2), contracted over (3,4)x(1,2)
+    by SOP; sampled output rows against the oracle."""
+    bits, draws = 16, 1 << 24
+    ca, va = L.kronecker_hypersparse(bits, draws, seed=1)
+    cb, vb = L.kronecker_hypersparse(bits, draws, seed=2)
+    dims = [2**bits] * 4
+    flags = lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES
+    ga = gpu_create(lco_lib, gpu_ctx, dims, ca, va, flags)
+    gb = gpu_create(lco_lib, gpu_ctx, dims, cb, vb, flags)
+    la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
+    plan = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
+    assert lco_lib.ALGOS[plan.algo] == "SOP"
+    r = lco_lib.lco_contract(gpu_ctx, ga, la, gb, lb, lc)
+    _, livs, vals = to_np(r)
+    assert np.all(livs[1:] > livs[:-1])
+    # sampled rows: output entries whose (mode 0, mode 1) pair lies in a random sample
+    oa = oracle_mod.create(dims, ca, va, sum_duplicates=True)
+    ob = oracle_mod.create(dims, cb, vb, sum_duplicates=True)
+    rng = np.random.default_rng(5)
+    rows = np.unique(oa.livs[rng.integers(0, oa.nnz, 20000)] % np.uint64(2**32))
+    keep = np.isin(oa.livs % np.uint64(2**32), rows)
+    sub = oracle_mod.Tensor(oa.dims, oa.livs[keep], oa.vals[keep])
+    ref = oracle_mod.contract(sub, la, ob, lb, lc, mode="sort")
+    pick = np.isin(livs % np.uint64(2**32), rows)
+    assert np.array_equal(livs[pick], ref.livs)
+    err = np.abs(vals[pick] - ref.vals)
+    cancel = np.abs(ref.vals) < 1e-3 * ref.absum
+    assert np.all(err <= np.where(cancel, TOL * ref.absum, TOL * np.abs(ref.vals)))
+    assert np.array_equal(vals[pick].view(np.uint64), ref.vals.view(np.uint64))
