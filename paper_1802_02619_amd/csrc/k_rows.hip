@@ -70,6 +70,29 @@ __device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, doubl
   }
 }
 
+// Bitonic sort of one (key, val) pair per lane across the wave, ascending by key;
+// keys must be distinct except for the largest value (padding lanes).
+template <class K>
+__device__ __forceinline__ void wave_bitonic_key(K& key, double& val) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const K ok = __shfl_xor(key, j, kWave);
+      const double ov = __shfl_xor(val, j, kWave);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const bool other_less = ok < key;
+      const bool take = (lower == up) ? other_less : (key < ok);
+      if (take) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
+}
+
 template <bool DENSE>
 __device__ __forceinline__ void b_row(const RowArgs& ra, uint64_t j, uint32_t& start, uint32_t& len) {
   if (DENSE) {
@@ -127,8 +150,9 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
   }
 }
 
+// For each A' entry: the start and length of the B' row its column selects.
 template <bool DENSE>
-__global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len) {
+__global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_t* __restrict__ bstart) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ra.nnz_a;
        e += (int64_t)gridDim.x * blockDim.x) {
     uint64_t j;
@@ -136,153 +160,258 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len) {
     uint32_t s, l;
     b_row<DENSE>(ra, j, s, l);
     len[e] = l;
+    bstart[e] = s;
   }
 }
 
-// Bins non-empty rows of A' by product count.
-__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint32_t* __restrict__ list0,
-                                    uint32_t* __restrict__ list2, uint64_t* __restrict__ counters,
-                                    uint64_t* __restrict__ f2, uint32_t* __restrict__ is2) {
+// Per-row shape codes of the one-wave kernel.
+constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
+constexpr uint8_t kShapeSkip = 0xFF;   // no products, or a long row
+// Rows with at most 64 products and 64 entries run one wave per row.  When the
+// row's entries times W (the next power of two at least its longest B' row) fit
+// the 64 lanes, lane = entry * W + position ("entry-major"): each lane knows its
+// product without any search.  The shape code is log2 W for those rows.
+__device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
+  return f <= (uint64_t)kWave && t <= (uint32_t)kWave;
+}
+
+// Flags the long rows of A' (is2, f2) and writes the shape code of every row;
+// the rows keep their natural order.
+__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ f2,
+                                    uint32_t* __restrict__ is2, uint8_t* __restrict__ shape) {
   const uint64_t nzr = *ra.nzr_a;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
-    if ((uint64_t)r >= nzr) break;
-    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
-    const uint64_t f = ra.poff[e1] - ra.poff[e0];
-    if (f == 0) continue;
-    if (f <= (uint64_t)kWave && e1 - e0 <= (uint32_t)kWave) {
-      const uint64_t i = atomicAdd((unsigned long long*)&counters[0], 1ull);
-      list0[i] = (uint32_t)r;
-    } else {
-      const uint64_t i = atomicAdd((unsigned long long*)&counters[1], 1ull);
-      list2[i] = (uint32_t)r;
-      f2[r] = f;
-      is2[r] = 1;
+    uint64_t f = 0;
+    uint32_t big = 0;
+    uint8_t sh = kShapeSkip;
+    if ((uint64_t)r < nzr) {
+      const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+      f = ra.poff[e1] - ra.poff[e0];
+      if (f > 0 && small_row(f, e1 - e0)) {
+        uint64_t mx = 0;
+        for (uint32_t e = e0; e < e1; ++e) {
+          const uint64_t l = ra.poff[e + 1] - ra.poff[e];
+          mx = l > mx ? l : mx;
+        }
+        uint32_t lw = 0;
+        while ((1ull << lw) < mx) ++lw;
+        sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
+      } else if (f > 0) {
+        big = 1;
+      }
     }
+    is2[r] = big;
+    f2[r] = big ? f : 0;
+    shape[r] = sh;
   }
+}
+
+__global__ void list_scatter_kernel(const uint32_t* __restrict__ is2, const uint32_t* __restrict__ q2, int64_t n,
+                                    uint32_t* __restrict__ list2) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    if (is2[r]) list2[q2[r]] = (uint32_t)r;
 }
 
 // ---------------------------------------------------------------- one wave per row
 
+// One wave per row, rows in their natural (ascending) order.  Each lane ends up
+// with at most one product: its A' entry `ent`, its column and (numeric) value.
+template <bool NUMERIC>
+__device__ __forceinline__ void gather_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                                int lane, bool& valid, int& ent, uint64_t& col, double& v) {
+  valid = false;
+  ent = 0;
+  col = kEmpty;
+  v = 0.0;
+  if (sh != kShapeSearch) {
+    // entry-major lanes: no search
+    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
+    if (e < t) {
+      const uint32_t ge = e0 + e;
+      const uint64_t len = ra.poff[ge + 1] - ra.poff[ge];
+      if ((uint64_t)k < len) {
+        const uint64_t j = ra.a_livs[ge] - ra.kp * row;
+        const uint32_t q = ra.bstart[ge] + (uint32_t)k;
+        valid = true;
+        ent = e;
+        col = ra.b_livs[q] - ra.np * j;
+        if (NUMERIC) v = ra.a_vals[ge] * ra.b_vals[q];
+      }
+    }
+    return;
+  }
+  // general small row: product p = lane, found by a binary search over the
+  // entries' inclusive product counts
+  uint64_t j = 0;
+  uint32_t len = 0, bs = 0, rel = 0;
+  double av = 0.0;
+  const uint64_t p0 = ra.poff[e0];
+  if (lane < t) {
+    const uint32_t ge = e0 + lane;
+    j = ra.a_livs[ge] - ra.kp * row;
+    rel = (uint32_t)(ra.poff[ge] - p0);
+    len = (uint32_t)(ra.poff[ge + 1] - ra.poff[ge]);
+    bs = ra.bstart[ge];
+    if (NUMERIC) av = ra.a_vals[ge];
+  }
+  const uint32_t incl = rel + len;
+  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
+  const uint32_t p = (uint32_t)lane;
+  int lo = 0, hi = t - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
+    if (lo < hi) {
+      if (x > p) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
+  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
+  const uint64_t j_e = __shfl(j, lo, kWave);
+  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
+  if (p < f) {
+    const uint32_t q = bs_e + (p - excl_e);
+    valid = true;
+    ent = lo;
+    col = ra.b_livs[q] - ra.np * j_e;
+    if (NUMERIC) v = av_e * ra.b_vals[q];
+  }
+}
+
 template <bool DENSE, bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, const uint32_t* __restrict__ list,
-                                                                uint32_t count, uint64_t* __restrict__ cnt,
+__global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, uint32_t nzr,
+                                                                const uint8_t* __restrict__ shape,
+                                                                uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
                                                                 uint64_t* __restrict__ out_livs,
                                                                 double* __restrict__ out_vals) {
   __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
-  __shared__ uint64_t s_ocol[kRowWaves][kWave];
-  __shared__ double s_oval[kRowWaves][kWave];
+  __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
+  __shared__ double s_acc[kRowWaves][3 * kWave];  // 128 slots + one dummy per lane
+  __shared__ uint32_t s_own[kRowWaves][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const uint32_t nw = gridDim.x * kRowWaves;
-  for (uint32_t li = blockIdx.x * kRowWaves + w; li < count; li += nw) {
-    const uint32_t r = list[li];
+  const bool narrow = ra.np < (1ull << 32);  // columns fit 32 bits below the padding key
+  for (uint32_t r = blockIdx.x * kRowWaves + w; r < nzr; r += nw) {
+    const uint8_t sh = shape[r];
+    if (sh == kShapeSkip) continue;
     const uint32_t e0 = ra.row_start[r];
     const int t = (int)(ra.row_start[r + 1] - e0);
     const uint64_t row = ra.row_id[r];
-    uint64_t j = 0;
-    uint32_t bs = 0, len = 0;
-    double av = 0.0;
-    if (lane < t) {
-      const uint64_t la = ra.a_livs[e0 + lane];
-      j = la - ra.kp * row;
-      b_row<DENSE>(ra, j, bs, len);
-      if (NUMERIC) av = ra.a_vals[e0 + lane];
-    }
-    const uint32_t incl = wave_inclusive_scan<uint32_t>(len);
-    const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
-    // product p = lane: its A' entry is the first lane whose inclusive count exceeds p
-    const uint32_t p = (uint32_t)lane;
-    int lo = 0, hi = t - 1;
-#pragma unroll
-    for (int it = 0; it < 6; ++it) {
-      const int mid = (lo + hi) >> 1;
-      const uint32_t v = (uint32_t)__shfl((int)incl, mid, kWave);
-      if (lo < hi) {
-        if (v > p) hi = mid;
-        else lo = mid + 1;
-      }
-    }
-    const uint32_t excl_e = (uint32_t)__shfl((int)(incl - len), lo, kWave);
-    const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
-    const uint64_t j_e = __shfl(j, lo, kWave);
-    const double av_e = __shfl(av, lo, kWave);
-    const bool valid = p < f;
-    uint64_t col = kEmpty;
-    double v = 0.0;
-    if (valid) {
-      const uint32_t q = bs_e + (p - excl_e);
-      col = ra.b_livs[q] - ra.np * j_e;
-      if (NUMERIC) v = av_e * ra.b_vals[q];
-    }
+    bool valid;
+    int ent;
+    uint64_t col;
+    double v;
+    gather_products<NUMERIC>(ra, e0, t, row, sh, lane, valid, ent, col, v);
     if (ACC) {
-      // sparse accumulator: LDS hash table mapping a column to a slot
-      s_hash[w][lane] = kEmpty;
-      s_hash[w][lane + kWave] = kEmpty;
+      // sparse accumulator: an LDS hash table maps a column to a slot (32-bit
+      // keys when the columns allow), and one FP64 accumulator per slot
+      if (narrow) {
+        s_hash32[w][lane] = 0xFFFFFFFFu;
+        s_hash32[w][lane + kWave] = 0xFFFFFFFFu;
+      } else {
+        s_hash[w][lane] = kEmpty;
+        s_hash[w][lane + kWave] = kEmpty;
+      }
+      if (NUMERIC) {
+        s_acc[w][lane] = 0.0;
+        s_acc[w][lane + kWave] = 0.0;
+      }
       wave_lds_sync();
       uint32_t slot = valid ? hash_slot(col) : 0;
       bool isnew = false;
       if (valid) {
-        for (int probe = 0; probe < 2 * kWave; ++probe) {
-          const uint64_t prev = atomicCAS((unsigned long long*)&s_hash[w][slot], (unsigned long long)kEmpty,
-                                          (unsigned long long)col);
-          if (prev == kEmpty) {
-            isnew = true;
-            break;
+        if (narrow) {
+          const uint32_t c32 = (uint32_t)col;
+          for (int probe = 0; probe < 2 * kWave; ++probe) {
+            const uint32_t prev = atomicCAS(&s_hash32[w][slot], 0xFFFFFFFFu, c32);
+            if (prev == 0xFFFFFFFFu) {
+              isnew = true;
+              break;
+            }
+            if (prev == c32) break;
+            slot = (slot + 1) & (2 * kWave - 1);
           }
-          if (prev == col) break;
-          slot = (slot + 1) & (2 * kWave - 1);
+        } else {
+          for (int probe = 0; probe < 2 * kWave; ++probe) {
+            const uint64_t prev = atomicCAS((unsigned long long*)&s_hash[w][slot], (unsigned long long)kEmpty,
+                                            (unsigned long long)col);
+            if (prev == kEmpty) {
+              isnew = true;
+              break;
+            }
+            if (prev == col) break;
+            slot = (slot + 1) & (2 * kWave - 1);
+          }
         }
       }
       const uint64_t newmask = __ballot(isnew);
-      const uint32_t distinct = (uint32_t)__popcll(newmask);
       if (!NUMERIC) {
-        if (lane == 0) cnt[r] = distinct;
+        if (lane == 0) cnt[r] = (uint64_t)__popcll(newmask);
       } else {
-        wave_lds_sync();
-        // accumulate in product order; slot s is held by lane s % 64
-        double acc0 = 0.0, acc1 = 0.0;
-        for (uint32_t s = 0; s < f; ++s) {
-          const uint32_t sl = readlane_u32(slot, (int)s);
-          const double vs = readlane_f64(v, (int)s);
-          if ((int)(sl & (kWave - 1)) == lane) {
-            if (sl < (uint32_t)kWave) acc0 += vs;
-            else acc1 += vs;
+        // Accumulate in product order, one A' entry (one contracted index) at a
+        // time: the products of one entry come from one row of B' and so have
+        // distinct columns, hence distinct slots, and need no atomics.  Lanes of
+        // other entries update a private dummy slot, so the loop has no branches.
+        // (LDS operations of one wave complete in order, so iteration e+1 reads
+        // what iteration e wrote.)
+        const int dummy = 2 * kWave + lane;
+        if (t <= 8) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int a = (valid && ent == e) ? (int)slot : dummy;
+            s_acc[w][a] += v;
+            __builtin_amdgcn_wave_barrier();
+          }
+        } else {
+          for (int e = 0; e < t; ++e) {
+            const int a = (valid && ent == e) ? (int)slot : dummy;
+            s_acc[w][a] += v;
+            __builtin_amdgcn_wave_barrier();
           }
         }
-        // gather occupied slots, then sort the row's distinct columns
-        const uint64_t c0 = s_hash[w][lane], c1 = s_hash[w][lane + kWave];
-        const uint64_t m0 = __ballot(c0 != kEmpty), m1 = __ballot(c1 != kEmpty);
-        const uint32_t base1 = (uint32_t)__popcll(m0);
-        if (c0 != kEmpty) {
-          const uint32_t pos = (uint32_t)__popcll(m0 & lanemask_lt());
-          s_ocol[w][pos] = c0;
-          s_oval[w][pos] = acc0;
-        }
-        if (c1 != kEmpty) {
-          const uint32_t pos = base1 + (uint32_t)__popcll(m1 & lanemask_lt());
-          s_ocol[w][pos] = c1;
-          s_oval[w][pos] = acc1;
-        }
         wave_lds_sync();
-        uint64_t key = lane < (int)distinct ? s_ocol[w][lane] : kEmpty;
-        double val = lane < (int)distinct ? s_oval[w][lane] : 0.0;
-        uint32_t idx = 0;
-        wave_bitonic(key, idx, val);
-        if (lane < (int)distinct) {
-          const uint64_t o = coff[r] + lane;
-          out_livs[o] = key + ra.np * row;
-          out_vals[o] = val;
+        // the lane that inserted a column owns that output entry; its rank among
+        // the row's distinct columns is its position in the sorted row
+        double mine = 0.0;
+        if (isnew) mine = s_acc[w][slot];
+        const int distinct = __popcll(newmask);
+        uint32_t rank = 0;
+        if (narrow && distinct <= 32) {
+          // owners' columns compacted into lanes [0, distinct), compared with
+          // scalar reads at fixed lane indices (no loop, no branches)
+          if (isnew) s_own[w][__popcll(newmask & lanemask_lt())] = (uint32_t)col;
+          wave_lds_sync();
+          const uint32_t oc = lane < distinct ? s_own[w][lane] : 0xFFFFFFFFu;
+          const uint32_t c32 = (uint32_t)col;
+#pragma unroll
+          for (int b = 0; b < 32; ++b) rank += readlane_u32(oc, b) < c32 ? 1u : 0u;
+        } else {
+          for (uint64_t mm = newmask; mm; mm &= mm - 1) {
+            const int b = __builtin_ctzll(mm);
+            const uint64_t cb = ((uint64_t)readlane_u32((uint32_t)(col >> 32), b) << 32) |
+                                readlane_u32((uint32_t)col, b);
+            rank += cb < col ? 1u : 0u;
+          }
         }
-        wave_lds_sync();
+        if (isnew) {
+          const uint64_t o = coff[r] + rank;
+          out_livs[o] = col + ra.np * row;
+          out_vals[o] = mine;
+        }
       }
+      wave_lds_sync();
     } else {
-      // no accumulator: sort (column, product index), then each run head sums its run
+      // no accumulator: sort (column, product index), then each run head sums
+      // its run (invalid lanes carry the largest key and sort last)
       uint64_t key = col;
-      uint32_t idx = p;
+      uint32_t idx = (uint32_t)lane;
       double val = v;
       wave_bitonic(key, idx, val);
       const uint64_t prev = __shfl_up(key, 1, kWave);
-      const bool head = lane < (int)f && (lane == 0 || prev != key);
+      const bool head = key != kEmpty && (lane == 0 || prev != key);
       const uint64_t hmask = __ballot(head);
       if (!NUMERIC) {
         if (lane == 0) cnt[r] = (uint64_t)__popcll(hmask);
@@ -294,7 +423,7 @@ __global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, cons
           const uint64_t ks = __shfl_down(key, s, kWave);
           const double vs = __shfl_down(val, s, kWave);
           if (active) {
-            if (lane + s < (int)f && ks == key) acc += vs;
+            if (lane + s < kWave && ks == key) acc += vs;
             else active = false;
           }
           if (!__any(active)) break;
@@ -441,33 +570,34 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   // product counts per A' entry and their prefix
   uint64_t* len = s.get<uint64_t>(na);
   uint64_t* poff = s.get<uint64_t>(na + 1);
-  if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len);
-  else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len);
+  uint32_t* bstart = s.get<uint32_t>(na);
+  if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+  else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+  ra.bstart = bstart;
   scan_u64(ctx, len, poff, na, poff + na);
   ra.poff = poff;
-  // bin rows
-  uint32_t* list0 = s.get<uint32_t>(na);
+  // flag long rows (they keep row order), count them and place their products
   uint32_t* list2 = s.get<uint32_t>(na);
-  uint64_t* counters = s.get<uint64_t>(4);
+  uint64_t* counters = s.get<uint64_t>(2);
   uint64_t* f2 = s.get<uint64_t>(na);
   uint32_t* is2 = s.get<uint32_t>(na);
   uint64_t* off2 = s.get<uint64_t>(na + 1);
   uint32_t* q2 = s.get<uint32_t>(na);
-  memset_async(ctx, counters, 0, 4 * sizeof(uint64_t));
-  memset_async(ctx, f2, 0, na * sizeof(uint64_t));
-  memset_async(ctx, is2, 0, na * sizeof(uint32_t));
-  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, list0, list2,
-             counters, f2, is2);
-  scan_u64(ctx, f2, off2, na, counters + 2);
-  scan_u32(ctx, is2, q2, na, nullptr);
-  const uint64_t* rb1[4] = {arows.count, counters, counters + 1, counters + 2};
-  const uint64_t* h = readback(ctx, rb1, 4);
-  const uint64_t nzr = h[0], n0 = h[1], n2 = h[2], f2_total = h[3];
+  memset_async(ctx, counters, 0, 2 * sizeof(uint64_t));
+  uint8_t* shape = s.get<uint8_t>(na);
+  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, f2, is2, shape);
+  scan_u64(ctx, f2, off2, na, counters);
+  scan_u32(ctx, is2, q2, na, (uint32_t*)(counters + 1));
+  const uint64_t* rb1[3] = {arows.count, counters + 1, counters};
+  const uint64_t* h = readback(ctx, rb1, 3);
+  const uint64_t nzr = h[0], n2 = h[1], f2_total = h[2];
+  if (n2) LCO_LAUNCH(ctx, "list_scatter", list_scatter_kernel, grid_for(ctx, nzr, 256), 256, 0, is2, q2, (int64_t)nzr,
+                     list2);
   // per-row output counts
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
   uint64_t* coff = s.get<uint64_t>(nzr + 1);
   memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));
-  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n0 + kRowWaves - 1) / kRowWaves,
+  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + kRowWaves - 1) / kRowWaves,
                                                                        (uint64_t)ctx->num_cus * 64));
 #define LCO_ROW_SMALL(NUM, ...)                                                                                 \
   do {                                                                                                          \
@@ -478,8 +608,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<false, true, NUM>),          \
                     small_grid, kRowThreads, 0, __VA_ARGS__);                                                   \
   } while (0)
-  if (n0) LCO_ROW_SMALL(false, ra, list0, (uint32_t)n0, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                        (double*)nullptr);
+  LCO_ROW_SMALL(false, ra, (uint32_t)nzr, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
   // long rows: expand, sort by (row rank, column), count distinct
   uint64_t* keys = nullptr;
   double* pvals = nullptr;
@@ -512,7 +641,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   if (nnz_c > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "contract: more than 2^32-1 output entries");
   lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
   try {
-    if (n0) LCO_ROW_SMALL(true, ra, list0, (uint32_t)n0, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    LCO_ROW_SMALL(true, ra, (uint32_t)nzr, (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
     if (n2)
       LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
                  off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,

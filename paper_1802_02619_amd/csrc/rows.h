@@ -32,6 +32,7 @@ struct RowArgs {
   const uint64_t* row_id = nullptr;      //   and ids
   const uint64_t* nzr_a = nullptr;       //   device count
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
+  const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
 };
 
 // C' = A' * B' row by row; `dense` selects singly (CSR) or doubly (DCSR)
