@@ -174,14 +174,29 @@ void copy_d2d(lco_ctx ctx, void* dst, const void* src, size_t bytes) {
   if (bytes) LCO_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
 }
 
+static void check_device_error(lco_ctx ctx, uint32_t word) {
+  if (word) {
+    LCO_HIP(hipMemsetAsync(ctx->dev_err, 0, sizeof(uint32_t), ctx->stream));
+    fail(LCO_E_HIP, "a kernel exceeded its bounded wait for another workgroup (results discarded)");
+  }
+}
+
 const uint64_t* readback(lco_ctx ctx, const uint64_t* const* dev_words, int count) {
   for (int i = 0; i < count; ++i)
     LCO_HIP(hipMemcpyAsync(ctx->pinned + i, dev_words[i], sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+  LCO_HIP(hipMemcpyAsync((uint32_t*)(ctx->pinned + 63), ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
   LCO_HIP(hipStreamSynchronize(ctx->stream));
+  check_device_error(ctx, *(uint32_t*)(ctx->pinned + 63));
   return ctx->pinned;
 }
 
-void sync(lco_ctx ctx) { LCO_HIP(hipStreamSynchronize(ctx->stream)); }
+void sync(lco_ctx ctx) {
+  LCO_HIP(hipMemcpyAsync((uint32_t*)(ctx->pinned + 63), ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  LCO_HIP(hipStreamSynchronize(ctx->stream));
+  check_device_error(ctx, *(uint32_t*)(ctx->pinned + 63));
+}
 
 lco_tensor new_tensor(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz) {
   lco_tensor t = new lco_tensor_s;
@@ -277,6 +292,14 @@ lco_status lco_ctx_create(int device, void* hip_stream, lco_alloc_fn alloc, lco_
     delete c;
     hip_check(e, "hipHostMalloc");
   }
+  try {
+    c->dev_err = (uint32_t*)dev_alloc(c, 256);
+    LCO_HIP(hipMemsetAsync(c->dev_err, 0, 256, c->stream));
+  } catch (...) {
+    (void)hipHostFree(c->pinned);
+    delete c;
+    throw;
+  }
   *out = c;
   return LCO_OK;
   LCO_CATCH
@@ -289,6 +312,7 @@ lco_status lco_ctx_destroy(lco_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& c : ctx->arena.chunks) dev_free(ctx, c.p, c.cap);
   ctx->arena.chunks.clear();
+  if (ctx->dev_err) dev_free(ctx, ctx->dev_err, 256);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;

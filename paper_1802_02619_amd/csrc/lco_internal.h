@@ -64,6 +64,7 @@ struct lco_ctx_s {
   int scratch_depth = 0;
   uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words)
   lco::Timer timer;
+  uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
 };
 
 struct lco_tensor_s {
