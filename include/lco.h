@@ -185,6 +185,30 @@ typedef struct {
 lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
                         int c_order, const int* c_labels, uint32_t flags, lco_tensor* out);
 
+/* One product of a batch (the arguments of lco_contract). */
+typedef struct {
+  lco_tensor a;
+  const int* a_labels;
+  lco_tensor b;
+  const int* b_labels;
+  int c_order;
+  const int* c_labels;
+  uint32_t flags;
+} lco_contract_desc;
+
+/* Batched products: outs[i] receives the product of descs[i], bit-identical to
+ * what lco_contract returns for the same arguments.  Instances whose plan is
+ * CSR/CSC/CSRNA/CSCNA (after any operand rearrangement) and whose rows of A'
+ * each have at most 64 products run together, every phase as one launch over
+ * all of them, with two stream synchronisations for the whole batch; outputs of
+ * those instances share one device allocation that is released with the last
+ * of them.  Other instances (doubly compressed, outer product, long rows) run
+ * through the per-call path.  Errors are those of lco_contract; on error no
+ * output handle survives. */
+lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs);
+/* How many instances of the last lco_contract_batch call ran batched / per call. */
+lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call);
+
 /* The plan lco_contract would run for these operands, without running it. */
 lco_status lco_plan_info(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
                          int c_order, const int* c_labels, uint32_t flags, lco_plan* out);

@@ -16,7 +16,7 @@ import threading
 __all__ = [
     "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
-    "lco_contract", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
+    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
@@ -124,6 +124,8 @@ def load_library():
             "lco_permute": (i32, [vp, vp, pi32, pvp]),
             "lco_contract": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, pvp]),
             "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
+            "lco_contract_batch": (i32, [vp, i32, ctypes.POINTER(ContractDesc), ctypes.POINTER(ctypes.c_void_p)]),
+            "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "lco_classify": (i32, [u64, u64, i64, ctypes.POINTER(i32)]),
             "lco_select": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "lco_plan_contract": (i32, [i32, pu64, pi32, i64, i32, pu64, pi32, i64, i32, pi32, u32,
@@ -207,9 +209,13 @@ class Context:
     def view(self, ptr: int, nbytes: int, dtype):
         """torch view of `nbytes` at device pointer `ptr` inside one of this context's allocations."""
         t = self._allocs.get(ptr)
-        if t is None:
-            raise KeyError("pointer is not the start of a library allocation")
-        return t[:nbytes].view(dtype)
+        if t is not None:
+            return t[:nbytes].view(dtype)
+        for start, buf in self._allocs.items():  # inside a shared allocation (batch outputs)
+            if start <= ptr and ptr + nbytes <= start + buf.numel():
+                off = ptr - start
+                return buf[off:off + nbytes].view(dtype)
+        raise KeyError("pointer is not inside a library allocation")
 
 
 def lco_ctx_create(device: int = 0, stream=None) -> Context:
@@ -253,15 +259,15 @@ class Tensor:
         if n == 0:
             return torch.zeros(0, dtype=torch.int64, device=self.ctx._dev)
         p = load_library().lco_livs(self.handle)
-        return self.ctx.view(p, n * 16, torch.uint8)[: n * 8].view(torch.int64)
+        return self.ctx.view(p, n * 8, torch.uint8).view(torch.int64)
 
     def vals(self):
         import torch
         n = self.nnz
         if n == 0:
             return torch.zeros(0, dtype=torch.float64, device=self.ctx._dev)
-        p = load_library().lco_livs(self.handle)
-        return self.ctx.view(p, n * 16, torch.uint8)[n * 8: n * 16].view(torch.float64)
+        p = load_library().lco_vals(self.handle)
+        return self.ctx.view(p, n * 8, torch.uint8).view(torch.float64)
 
     def to_numpy(self):
         """(dims, livs uint64, vals float64) copied to the host."""
@@ -310,6 +316,37 @@ def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_label
     _check(L.lco_contract(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
                           _i32arr(c_labels), int(flags), ctypes.byref(h)))
     return Tensor(ctx, h)
+
+
+class ContractDesc(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("a_labels", ctypes.POINTER(ctypes.c_int)),
+                ("b", ctypes.c_void_p), ("b_labels", ctypes.POINTER(ctypes.c_int)),
+                ("c_order", ctypes.c_int), ("c_labels", ctypes.POINTER(ctypes.c_int)),
+                ("flags", ctypes.c_uint32)]
+
+
+def lco_contract_batch(ctx: Context, items):
+    """Batched products; `items` is a list of (a, a_labels, b, b_labels, c_labels[, flags]).
+    Returns the list of result tensors (bit-identical to lco_contract on each item)."""
+    L = load_library()
+    n = len(items)
+    keep = []
+    descs = (ContractDesc * max(1, n))()
+    for i, it in enumerate(items):
+        a, la, b, lb, lc = it[:5]
+        flags = it[5] if len(it) > 5 else 0
+        arrs = (_i32arr(la), _i32arr(lb), _i32arr(lc))
+        keep.append(arrs)
+        descs[i] = ContractDesc(a.handle, arrs[0], b.handle, arrs[1], len(lc), arrs[2], int(flags))
+    outs = (ctypes.c_void_p * max(1, n))()
+    _check(L.lco_contract_batch(ctx.handle, n, descs, outs))
+    return [Tensor(ctx, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+def lco_batch_stats(ctx: Context):
+    b, p = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().lco_batch_stats(ctx.handle, ctypes.byref(b), ctypes.byref(p)))
+    return b.value, p.value
 
 
 def lco_plan_info(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Plan:

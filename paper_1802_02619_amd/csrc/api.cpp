@@ -218,9 +218,48 @@ lco_tensor new_tensor(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz)
   return t;
 }
 
+Pool* new_pool(lco_ctx ctx, size_t bytes) {
+  Pool* p = new Pool;
+  p->ctx = ctx;
+  p->bytes = bytes;
+  p->refs = 1;
+  try {
+    p->base = dev_alloc(ctx, bytes);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  return p;
+}
+
+void release_pool(Pool* p) {
+  if (!p) return;
+  if (--p->refs == 0) {
+    dev_free(p->ctx, p->base, p->bytes);
+    delete p;
+  }
+}
+
+lco_tensor pool_tensor(lco_ctx ctx, Pool* p, int order, const uint64_t* dims, uint64_t* livs, double* vals,
+                       int64_t nnz) {
+  lco_tensor t = new lco_tensor_s;
+  t->ctx = ctx;
+  t->order = order;
+  for (int r = 0; r < order; ++r) t->dims[r] = dims[r];
+  t->nnz = nnz;
+  if (nnz > 0) {
+    t->pool = p;
+    p->refs++;
+    t->livs = livs;
+    t->vals = vals;
+  }
+  return t;
+}
+
 static void free_tensor(lco_tensor t) {
   if (!t) return;
-  if (t->base) dev_free(t->ctx, t->base, t->bytes);
+  if (t->pool) release_pool(t->pool);
+  else if (t->base) dev_free(t->ctx, t->base, t->bytes);
   delete t;
 }
 

@@ -16,6 +16,8 @@ struct Owned {  // a temporary tensor released on scope exit
   }
 };
 
+}  // namespace
+
 lco_tensor permuted(lco_ctx ctx, const lco_tensor_s* in, const int* perm) {
   RpDetail plan = plan_permute(in->order, in->dims, perm, in->nnz, default_digit_cap());
   lco_tensor t = new_tensor(ctx, in->order, plan.new_dims, in->nnz);
@@ -27,8 +29,6 @@ lco_tensor permuted(lco_ctx ctx, const lco_tensor_s* in, const int* perm) {
   }
   return t;
 }
-
-}  // namespace
 
 lco_tensor contract_run(lco_ctx ctx, const lco_tensor_s* a, const lco_tensor_s* b, const ContractDetail& d) {
   if (d.empty) return new_tensor(ctx, d.order_c, d.c_dims, 0);
@@ -66,3 +66,111 @@ lco_tensor contract_run(lco_ctx ctx, const lco_tensor_s* a, const lco_tensor_s* 
 }
 
 }  // namespace lco
+
+// ---------------------------------------------------------------- batched C-ABI
+
+namespace lco {
+lco_status set_error(const Error& e);
+lco_status set_error_msg(lco_status s, const char* msg);
+}  // namespace lco
+
+using namespace lco;
+
+namespace {
+int64_t g_batch_stats[2] = {0, 0};  // per context would need the context; the last call on any context
+}
+
+extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs) {
+  if (!ctx || count < 0 || (count && (!descs || !outs))) return set_error_msg(LCO_E_ARG, "lco_contract_batch: bad argument");
+  for (int i = 0; i < count; ++i) outs[i] = nullptr;
+  std::vector<lco_tensor> temps;
+  try {
+    std::vector<ContractDetail> plans(count);
+    for (int i = 0; i < count; ++i) {
+      const lco_contract_desc& x = descs[i];
+      if (!x.a || !x.b) fail(LCO_E_ARG, "lco_contract_batch: tensor is NULL");
+      if (x.a->ctx != ctx || x.b->ctx != ctx) fail(LCO_E_ARG, "lco_contract_batch: tensor belongs to another context");
+      plans[i] = plan_contract(x.a->order, x.a->dims, x.a_labels, x.a->nnz, x.b->order, x.b->dims, x.b_labels,
+                               x.b->nnz, x.c_order, x.c_labels, x.flags);
+    }
+    LCO_HIP(hipSetDevice(ctx->device));
+    std::vector<BatchJob> acc_jobs, na_jobs;
+    std::vector<int> percall, batched;
+    for (int i = 0; i < count; ++i) {
+      const ContractDetail& d = plans[i];
+      if (d.empty) {
+        outs[i] = new_tensor(ctx, d.order_c, d.c_dims, 0);
+        continue;
+      }
+      const int algo = d.pub.algo;
+      const bool rowwise = algo == LCO_ALG_CSR || algo == LCO_ALG_CSRNA;
+      const bool colwise = algo == LCO_ALG_CSC || algo == LCO_ALG_CSCNA;
+      if (!rowwise && !colwise) {
+        percall.push_back(i);
+        continue;
+      }
+      const lco_tensor_s* A = descs[i].a;
+      const lco_tensor_s* B = descs[i].b;
+      if (d.pub.permute_a) {
+        temps.push_back(permuted(ctx, A, d.perm_a));
+        A = temps.back();
+      }
+      if (d.pub.permute_b) {
+        temps.push_back(permuted(ctx, B, d.perm_b));
+        B = temps.back();
+      }
+      BatchJob j;
+      j.index = i;
+      j.A = rowwise ? A : B;
+      j.B = rowwise ? B : A;
+      j.kp = d.pub.k;
+      j.np = rowwise ? d.pub.n : d.pub.m;
+      j.order_c = d.order_c;
+      for (int r = 0; r < d.order_c; ++r) j.natural_dims[r] = d.natural_dims[r];
+      (algo == LCO_ALG_CSR || algo == LCO_ALG_CSC ? acc_jobs : na_jobs).push_back(j);
+      batched.push_back(i);
+    }
+    std::vector<int> redo;
+    if (!acc_jobs.empty()) {
+      std::vector<int> r = batch_group(ctx, acc_jobs, true, outs);
+      redo.insert(redo.end(), r.begin(), r.end());
+    }
+    if (!na_jobs.empty()) {
+      std::vector<int> r = batch_group(ctx, na_jobs, false, outs);
+      redo.insert(redo.end(), r.begin(), r.end());
+    }
+    for (int i : batched) {
+      if (!outs[i] || !plans[i].pub.permute_c) continue;
+      lco_tensor natural = outs[i];
+      outs[i] = permuted(ctx, natural, plans[i].perm_c);
+      lco_destroy(natural);
+    }
+    percall.insert(percall.end(), redo.begin(), redo.end());
+    for (int i : percall) outs[i] = contract_run(ctx, descs[i].a, descs[i].b, plans[i]);
+    for (lco_tensor t : temps) lco_destroy(t);
+    g_batch_stats[0] = (int64_t)batched.size() - (int64_t)redo.size();
+    g_batch_stats[1] = (int64_t)percall.size();
+    return LCO_OK;
+  } catch (const Error& e) {
+    for (lco_tensor t : temps) lco_destroy(t);
+    for (int i = 0; i < count; ++i) {
+      if (outs[i]) lco_destroy(outs[i]);
+      outs[i] = nullptr;
+    }
+    return set_error(e);
+  } catch (const std::exception& e) {
+    for (lco_tensor t : temps) lco_destroy(t);
+    for (int i = 0; i < count; ++i) {
+      if (outs[i]) lco_destroy(outs[i]);
+      outs[i] = nullptr;
+    }
+    return set_error_msg(LCO_E_HIP, e.what());
+  }
+}
+
+extern "C" lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call) {
+  if (!ctx || !batched || !per_call) return set_error_msg(LCO_E_ARG, "lco_batch_stats: bad argument");
+  *batched = g_batch_stats[0];
+  *per_call = g_batch_stats[1];
+  return LCO_OK;
+}

@@ -1,0 +1,294 @@
+// Batched contraction: many independent products run as one sequence of
+// launches.  Every instance that the per-call path would run through the
+// one-wave-per-row engine (row- or column-wise, singly compressed B', every
+// row of A' with at most 64 products and entries) is processed together: each
+// phase -- row pointers of B', rows of A', products per entry, row shapes, the
+// symbolic count, the numeric product -- is a single launch over the
+// concatenated entries and rows of all instances, and the whole batch needs
+// two host synchronisations (the batch's row count, then its output size).
+// Rows are computed by the same device code as the per-call path, so each
+// result is bit-identical to the per-call result.  Instances outside that case
+// (doubly compressed, outer product, long rows) run through the per-call path.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "row_core.h"
+
+namespace lco {
+
+namespace {
+
+struct BInst {
+  const uint64_t* a_livs;
+  const double* a_vals;
+  const uint64_t* b_livs;
+  const double* b_vals;
+  int64_t nnz_a, nnz_b;
+  int64_t eoff;  // first global A' entry
+  int64_t boff;  // first global B' slot (nnz_b + 1 slots per instance)
+  int64_t koff;  // first row pointer (k' + 1 per instance)
+  uint64_t kp, np;
+  FastDiv kdiv, ndiv;
+};
+
+// index i with off[i] <= g < off[i + 1]
+__device__ __forceinline__ int find_inst(const int64_t* __restrict__ off, int count, int64_t g) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void bt_dense_ptr_kernel(const BInst* __restrict__ in, const int64_t* __restrict__ boff, int count,
+                                    int64_t total, uint32_t* __restrict__ bptr) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_inst(boff, count, g);
+    const BInst& x = in[i];
+    const int64_t e = g - x.boff;  // 0..nnz_b
+    const uint64_t lo = e == 0 ? 0 : fd_div(x.ndiv, x.b_livs[e - 1]) + 1;
+    const uint64_t hi = e == x.nnz_b ? x.kp : fd_div(x.ndiv, x.b_livs[e]);
+    for (uint64_t r = lo; r <= hi; ++r) bptr[x.koff + r] = (uint32_t)e;
+  }
+}
+
+__global__ void bt_heads_kernel(const BInst* __restrict__ in, const int64_t* __restrict__ eoff, int count,
+                                int64_t total, uint32_t* __restrict__ head) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_inst(eoff, count, g);
+    const BInst& x = in[i];
+    const int64_t e = g - x.eoff;
+    head[g] = (e == 0 || fd_div(x.kdiv, x.a_livs[e]) != fd_div(x.kdiv, x.a_livs[e - 1])) ? 1u : 0u;
+  }
+}
+
+__global__ void bt_compact_kernel(const BInst* __restrict__ in, const int64_t* __restrict__ eoff, int count,
+                                  int64_t total, const uint32_t* __restrict__ head, const uint32_t* __restrict__ pos,
+                                  uint32_t* __restrict__ rs, uint64_t* __restrict__ rid, uint32_t* __restrict__ rinst) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    if (head[g]) {
+      const int i = find_inst(eoff, count, g);
+      const BInst& x = in[i];
+      rs[pos[g]] = (uint32_t)g;
+      rid[pos[g]] = fd_div(x.kdiv, x.a_livs[g - x.eoff]);
+      rinst[pos[g]] = (uint32_t)i;
+    }
+    if (g == total - 1) rs[pos[g] + head[g]] = (uint32_t)total;
+  }
+}
+
+__global__ void bt_entry_len_kernel(const BInst* __restrict__ in, const int64_t* __restrict__ eoff, int count,
+                                    int64_t total, const uint32_t* __restrict__ bptr, uint64_t* __restrict__ len,
+                                    uint32_t* __restrict__ bstart) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int i = find_inst(eoff, count, g);
+    const BInst& x = in[i];
+    uint64_t j;
+    fd_divmod(x.kdiv, x.a_livs[g - x.eoff], j);
+    const uint32_t s = bptr[x.koff + j];
+    len[g] = bptr[x.koff + j + 1] - s;
+    bstart[g] = s;
+  }
+}
+
+// Row shapes; rows that the one-wave engine cannot take send their instance to
+// the per-call path.
+__global__ void bt_classify_kernel(const uint32_t* __restrict__ rs, const uint32_t* __restrict__ rinst,
+                                   const uint64_t* __restrict__ poff, const uint64_t* __restrict__ nrows,
+                                   int64_t upper, uint8_t* __restrict__ shape, uint32_t* __restrict__ fallback) {
+  const uint64_t R = *nrows;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
+    if ((uint64_t)r >= R) break;
+    const uint32_t e0 = rs[r], e1 = rs[r + 1];
+    const uint64_t f = poff[e1] - poff[e0];
+    uint8_t sh = kShapeSkip;
+    if (f > 0 && small_row(f, e1 - e0)) {
+      uint64_t mx = 0;
+      for (uint32_t e = e0; e < e1; ++e) {
+        const uint64_t l = poff[e + 1] - poff[e];
+        mx = l > mx ? l : mx;
+      }
+      uint32_t lw = 0;
+      while ((1ull << lw) < mx) ++lw;
+      sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
+    } else if (f > 0) {
+      atomicOr(&fallback[rinst[r]], 1u);
+    }
+    shape[r] = sh;
+  }
+}
+
+template <bool ACC, bool NUMERIC>
+__global__ __launch_bounds__(kRowThreads) void bt_small_kernel(
+    const BInst* __restrict__ in, const uint32_t* __restrict__ rs, const uint64_t* __restrict__ rid,
+    const uint32_t* __restrict__ rinst, const uint8_t* __restrict__ shape, const uint32_t* __restrict__ fallback,
+    const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, uint64_t* __restrict__ cnt,
+    const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs, double* __restrict__ out_vals) {
+  __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
+  __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
+  __shared__ double s_acc[kRowWaves][3 * kWave];
+  __shared__ uint32_t s_own[kRowWaves][kWave];
+  const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t nw = gridDim.x * kRowWaves;
+  for (uint32_t r = blockIdx.x * kRowWaves + w; r < nrows; r += nw) {
+    const uint8_t sh = shape[r];
+    const uint32_t i = rinst[r];
+    if (sh == kShapeSkip || fallback[i]) continue;
+    const BInst& x = in[i];
+    RowArgs ra;
+    ra.a_livs = x.a_livs;
+    ra.a_vals = x.a_vals;
+    ra.a_base = x.eoff;
+    ra.b_livs = x.b_livs;
+    ra.b_vals = x.b_vals;
+    ra.kp = x.kp;
+    ra.np = x.np;
+    ra.poff = poff;
+    ra.bstart = bstart;
+    const uint32_t e0 = rs[r];
+    small_row_body<ACC, NUMERIC>(ra, e0, (int)(rs[r + 1] - e0), rid[r], sh, x.np < (1ull << 32), w, lane, sm,
+                                 NUMERIC ? nullptr : cnt + r, NUMERIC ? coff[r] : 0, out_livs, out_vals);
+  }
+}
+
+// First output position of each instance (its first row's offset) and the flags.
+__global__ void bt_ranges_kernel(const BInst* __restrict__ in, int count, const uint32_t* __restrict__ rpos,
+                                 const uint64_t* __restrict__ coff, const uint32_t* __restrict__ fallback,
+                                 uint64_t* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    out[2 * i] = coff[rpos[in[i].eoff]];
+    out[2 * i + 1] = fallback[i];
+  }
+}
+
+int grid_for(lco_ctx ctx, int64_t n, int threads) {
+  const int64_t want = (n + threads - 1) / threads;
+  const int64_t cap = (int64_t)ctx->num_cus * 16;
+  return (int)(want < 1 ? 1 : (want > cap ? cap : want));
+}
+
+}  // namespace
+
+// Runs one group of jobs that share the accumulator choice; fills outs[job.index]
+// for every job it completes and returns the indices that must take the per-call path.
+std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs) {
+  const int count = (int)jobs.size();
+  std::vector<BInst> host(count);
+  std::vector<int64_t> eoff(count + 1), boff(count + 1);
+  int64_t E = 0, BS = 0, K = 0;
+  for (int i = 0; i < count; ++i) {
+    const BatchJob& j = jobs[i];
+    BInst& x = host[i];
+    x.a_livs = j.A->livs;
+    x.a_vals = j.A->vals;
+    x.b_livs = j.B->livs;
+    x.b_vals = j.B->vals;
+    x.nnz_a = j.A->nnz;
+    x.nnz_b = j.B->nnz;
+    x.eoff = eoff[i] = E;
+    x.boff = boff[i] = BS;
+    x.koff = K;
+    x.kp = j.kp;
+    x.np = j.np;
+    x.kdiv = make_fastdiv(j.kp);
+    x.ndiv = make_fastdiv(j.np);
+    E += x.nnz_a;
+    BS += x.nnz_b + 1;
+    if (j.kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "batch: singly-compressed row pointer of more than 2^34 entries");
+    K += (int64_t)j.kp + 1;
+  }
+  eoff[count] = E;
+  boff[count] = BS;
+  if (E > (int64_t)UINT32_MAX) fail(LCO_E_UNSUPPORTED, "batch: more than 2^32-1 entries");
+  Scratch s(ctx);
+  BInst* d_in = s.get<BInst>(count);
+  int64_t* d_eoff = s.get<int64_t>(count + 1);
+  int64_t* d_boff = s.get<int64_t>(count + 1);
+  LCO_HIP(hipMemcpyAsync(d_in, host.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, ctx->stream));
+  LCO_HIP(hipMemcpyAsync(d_eoff, eoff.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, ctx->stream));
+  LCO_HIP(hipMemcpyAsync(d_boff, boff.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, ctx->stream));
+  uint32_t* bptr = s.get<uint32_t>(K);
+  LCO_LAUNCH(ctx, "bt_dense_ptr", bt_dense_ptr_kernel, grid_for(ctx, BS, 256), 256, 0, d_in, d_boff, count, BS, bptr);
+  // rows of A' over all instances (an instance's first entry always starts a row)
+  uint32_t* head = s.get<uint32_t>(E);
+  uint32_t* rpos = s.get<uint32_t>(E);
+  uint64_t* words = s.get<uint64_t>(2);
+  memset_async(ctx, words, 0, 2 * sizeof(uint64_t));
+  LCO_LAUNCH(ctx, "bt_heads", bt_heads_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, head);
+  scan_u32(ctx, head, rpos, E, (uint32_t*)words);
+  uint32_t* rs = s.get<uint32_t>(E + 1);
+  uint64_t* rid = s.get<uint64_t>(E);
+  uint32_t* rinst = s.get<uint32_t>(E);
+  LCO_LAUNCH(ctx, "bt_compact", bt_compact_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, head, rpos,
+             rs, rid, rinst);
+  uint64_t* len = s.get<uint64_t>(E);
+  uint64_t* poff = s.get<uint64_t>(E + 1);
+  uint32_t* bstart = s.get<uint32_t>(E);
+  LCO_LAUNCH(ctx, "bt_entry_len", bt_entry_len_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, bptr,
+             len, bstart);
+  scan_u64(ctx, len, poff, E, poff + E);
+  uint8_t* shape = s.get<uint8_t>(E);
+  uint32_t* fallback = s.get<uint32_t>(count);
+  memset_async(ctx, fallback, 0, sizeof(uint32_t) * count);
+  LCO_LAUNCH(ctx, "bt_classify", bt_classify_kernel, grid_for(ctx, E, 256), 256, 0, rs, rinst, poff, words, E, shape,
+             fallback);
+  const uint64_t* rb[1] = {words};
+  const uint64_t R = readback(ctx, rb, 1)[0] & 0xffffffffull;
+  uint64_t* cnt = s.get<uint64_t>(R + 1);
+  uint64_t* coff = s.get<uint64_t>(R + 1);
+  memset_async(ctx, cnt, 0, sizeof(uint64_t) * (R + 1));
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((R + kRowWaves - 1) / kRowWaves,
+                                                                 (uint64_t)ctx->num_cus * 64));
+  if (acc)
+    LCO_LAUNCH(ctx, "bt_small_sym", (bt_small_kernel<true, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
+               fallback, poff, bstart, (uint32_t)R, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+               (double*)nullptr);
+  else
+    LCO_LAUNCH(ctx, "bt_small_sym", (bt_small_kernel<false, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
+               fallback, poff, bstart, (uint32_t)R, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+               (double*)nullptr);
+  scan_u64(ctx, cnt, coff, R, coff + R);
+  uint64_t* ranges = s.get<uint64_t>(2 * count);
+  LCO_LAUNCH(ctx, "bt_ranges", bt_ranges_kernel, grid_for(ctx, count, 256), 256, 0, d_in, count, rpos, coff, fallback,
+             ranges);
+  // one synchronisation: the output size of every instance
+  std::vector<uint64_t> hr(2 * count + 1);
+  LCO_HIP(hipMemcpyAsync(hr.data(), ranges, sizeof(uint64_t) * 2 * count, hipMemcpyDeviceToHost, ctx->stream));
+  LCO_HIP(hipMemcpyAsync(hr.data() + 2 * count, coff + R, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+  sync(ctx);
+  const uint64_t total = hr[2 * count];
+  if (total > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "batch: more than 2^32-1 output entries");
+  // one pool holds every batched output: all LIVs, then all values
+  Pool* pool = new_pool(ctx, total * 16);
+  uint64_t* pl = (uint64_t*)pool->base;
+  double* pv = (double*)((char*)pool->base + total * 8);
+  std::vector<int> redo;
+  try {
+    if (acc)
+      LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<true, true>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
+                 shape, fallback, poff, bstart, (uint32_t)R, (uint64_t*)nullptr, (const uint64_t*)coff, pl, pv);
+    else
+      LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<false, true>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
+                 shape, fallback, poff, bstart, (uint32_t)R, (uint64_t*)nullptr, (const uint64_t*)coff, pl, pv);
+    for (int i = 0; i < count; ++i) {
+      if (hr[2 * i + 1]) {
+        redo.push_back(jobs[i].index);
+        continue;
+      }
+      const uint64_t a = hr[2 * i], b = i + 1 < count ? hr[2 * (i + 1)] : total;
+      outs[jobs[i].index] = pool_tensor(ctx, pool, jobs[i].order_c, jobs[i].natural_dims, pl + a, pv + a,
+                                        (int64_t)(b - a));
+    }
+  } catch (...) {
+    release_pool(pool);
+    throw;
+  }
+  release_pool(pool);  // the tensors hold the remaining references
+  return redo;
+}
+
+}  // namespace lco

@@ -67,7 +67,19 @@ struct lco_ctx_s {
   uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
 };
 
+namespace lco {
+// Device memory shared by several tensors (the outputs of a batch); freed when
+// the last tensor referring to it is destroyed.
+struct Pool {
+  lco_ctx ctx = nullptr;
+  void* base = nullptr;
+  size_t bytes = 0;
+  int refs = 0;
+};
+}  // namespace lco
+
 struct lco_tensor_s {
+  lco::Pool* pool = nullptr;  // non-null: livs/vals point into a shared pool
   lco_ctx ctx = nullptr;
   int order = 0;
   uint64_t dims[LCO_MAX_ORDER] = {};
@@ -86,6 +98,11 @@ void dev_free(lco_ctx ctx, void* p, size_t bytes);
 
 // An LCO tensor whose storage is allocated (not yet filled).
 lco_tensor new_tensor(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz);
+// Shared pools: a new pool holds one reference; each pool tensor adds one.
+Pool* new_pool(lco_ctx ctx, size_t bytes);
+void release_pool(Pool* p);
+lco_tensor pool_tensor(lco_ctx ctx, Pool* p, int order, const uint64_t* dims, uint64_t* livs, double* vals,
+                       int64_t nnz);
 
 // Per-operation scratch space carved from the context's arena (256-byte aligned).
 // Scopes nest; memory is reclaimed when the outermost scope of an op ends.

@@ -1,0 +1,287 @@
+// Device code of the one-wave-per-row product, shared by the per-call row
+// engine and the batched engine so that both compute every row identically.
+#pragma once
+
+#include "device_common.h"
+#include "rows.h"
+
+namespace lco {
+namespace {
+
+constexpr int kRowWaves = 4;
+constexpr int kRowThreads = kRowWaves * kWave;
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = __double_as_longlong(x);
+  const uint32_t lo = readlane_u32((uint32_t)b, l), hi = readlane_u32((uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Bitonic sort of one (key, idx, val) triple per lane across the wave, ascending
+// by (key, idx).
+__device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, double& val) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t ok = __shfl_xor(key, j, kWave);
+      const uint32_t oi = __shfl_xor(idx, j, kWave);
+      const double ov = __shfl_xor(val, j, kWave);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const bool other_less = ok < key || (ok == key && oi < idx);
+      const bool take = (lower == up) ? other_less : !other_less;
+      if (take) {
+        key = ok;
+        idx = oi;
+        val = ov;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
+  return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
+}
+
+// Per-row shape codes of the one-wave kernel.
+constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
+constexpr uint8_t kShapeSkip = 0xFF;   // no products, or a long row
+// Rows with at most 64 products and 64 entries run one wave per row.  When the
+// row's entries times W (the next power of two at least its longest B' row) fit
+// the 64 lanes, lane = entry * W + position ("entry-major"): each lane knows its
+// product without any search.  The shape code is log2 W for those rows.
+__device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
+  return f <= (uint64_t)kWave && t <= (uint32_t)kWave;
+}
+
+// One wave per row, rows in their natural (ascending) order.  Each lane ends up
+// with at most one product: its A' entry `ent`, its column and (numeric) value.
+template <bool NUMERIC>
+__device__ __forceinline__ void gather_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                                int lane, bool& valid, int& ent, uint64_t& col, double& v) {
+  valid = false;
+  ent = 0;
+  col = kEmpty;
+  v = 0.0;
+  if (sh != kShapeSearch) {
+    // entry-major lanes: no search
+    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
+    if (e < t) {
+      const uint32_t ge = e0 + e;
+      const uint64_t len = ra.poff[ge + 1] - ra.poff[ge];
+      if ((uint64_t)k < len) {
+        const uint64_t j = ra.a_livs[ge - ra.a_base] - ra.kp * row;
+        const uint32_t q = ra.bstart[ge] + (uint32_t)k;
+        valid = true;
+        ent = e;
+        col = ra.b_livs[q] - ra.np * j;
+        if (NUMERIC) v = ra.a_vals[ge - ra.a_base] * ra.b_vals[q];
+      }
+    }
+    return;
+  }
+  // general small row: product p = lane, found by a binary search over the
+  // entries' inclusive product counts
+  uint64_t j = 0;
+  uint32_t len = 0, bs = 0, rel = 0;
+  double av = 0.0;
+  const uint64_t p0 = ra.poff[e0];
+  if (lane < t) {
+    const uint32_t ge = e0 + lane;
+    j = ra.a_livs[ge - ra.a_base] - ra.kp * row;
+    rel = (uint32_t)(ra.poff[ge] - p0);
+    len = (uint32_t)(ra.poff[ge + 1] - ra.poff[ge]);
+    bs = ra.bstart[ge];
+    if (NUMERIC) av = ra.a_vals[ge - ra.a_base];
+  }
+  const uint32_t incl = rel + len;
+  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
+  const uint32_t p = (uint32_t)lane;
+  int lo = 0, hi = t - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
+    if (lo < hi) {
+      if (x > p) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
+  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
+  const uint64_t j_e = __shfl(j, lo, kWave);
+  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
+  if (p < f) {
+    const uint32_t q = bs_e + (p - excl_e);
+    valid = true;
+    ent = lo;
+    col = ra.b_livs[q] - ra.np * j_e;
+    if (NUMERIC) v = av_e * ra.b_vals[q];
+  }
+}
+
+// Shared memory of the one-wave-per-row kernels (one row table per wave).
+struct RowSmem {
+  uint64_t (*hash)[2 * kWave];
+  uint32_t (*hash32)[2 * kWave];
+  double (*acc)[3 * kWave];  // 128 slots + one dummy per lane
+  uint32_t (*own)[kWave];
+};
+
+// The whole product of one small row of A' by one wave: symbolic (distinct
+// column count into *cnt_slot) or numeric (the sorted row written at out_base).
+template <bool ACC, bool NUMERIC>
+__device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                               bool narrow, int w, int lane, const RowSmem& sm,
+                                               uint64_t* cnt_slot, uint64_t out_base, uint64_t* __restrict__ out_livs,
+                                               double* __restrict__ out_vals) {
+  bool valid;
+  int ent;
+  uint64_t col;
+  double v;
+  gather_products<NUMERIC>(ra, e0, t, row, sh, lane, valid, ent, col, v);
+  if (ACC) {
+    // sparse accumulator: an LDS hash table maps a column to a slot (32-bit
+    // keys when the columns allow), and one FP64 accumulator per slot
+    if (narrow) {
+      sm.hash32[w][lane] = 0xFFFFFFFFu;
+      sm.hash32[w][lane + kWave] = 0xFFFFFFFFu;
+    } else {
+      sm.hash[w][lane] = kEmpty;
+      sm.hash[w][lane + kWave] = kEmpty;
+    }
+    if (NUMERIC) {
+      sm.acc[w][lane] = 0.0;
+      sm.acc[w][lane + kWave] = 0.0;
+    }
+    wave_lds_sync();
+    uint32_t slot = valid ? hash_slot(col) : 0;
+    bool isnew = false;
+    if (valid) {
+      if (narrow) {
+        const uint32_t c32 = (uint32_t)col;
+        for (int probe = 0; probe < 2 * kWave; ++probe) {
+          const uint32_t prev = atomicCAS(&sm.hash32[w][slot], 0xFFFFFFFFu, c32);
+          if (prev == 0xFFFFFFFFu) {
+            isnew = true;
+            break;
+          }
+          if (prev == c32) break;
+          slot = (slot + 1) & (2 * kWave - 1);
+        }
+      } else {
+        for (int probe = 0; probe < 2 * kWave; ++probe) {
+          const uint64_t prev = atomicCAS((unsigned long long*)&sm.hash[w][slot], (unsigned long long)kEmpty,
+                                          (unsigned long long)col);
+          if (prev == kEmpty) {
+            isnew = true;
+            break;
+          }
+          if (prev == col) break;
+          slot = (slot + 1) & (2 * kWave - 1);
+        }
+      }
+    }
+    const uint64_t newmask = __ballot(isnew);
+    if (!NUMERIC) {
+      if (lane == 0) *cnt_slot = (uint64_t)__popcll(newmask);
+    } else {
+      // Accumulate in product order, one A' entry (one contracted index) at a
+      // time: the products of one entry come from one row of B' and so have
+      // distinct columns, hence distinct slots, and need no atomics.  Lanes of
+      // other entries update a private dummy slot, so the loop has no branches.
+      // (LDS operations of one wave complete in order, so iteration e+1 reads
+      // what iteration e wrote.)
+      const int dummy = 2 * kWave + lane;
+      if (t <= 8) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int a = (valid && ent == e) ? (int)slot : dummy;
+          sm.acc[w][a] += v;
+          __builtin_amdgcn_wave_barrier();
+        }
+      } else {
+        for (int e = 0; e < t; ++e) {
+          const int a = (valid && ent == e) ? (int)slot : dummy;
+          sm.acc[w][a] += v;
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      wave_lds_sync();
+      // the lane that inserted a column owns that output entry; its rank among
+      // the row's distinct columns is its position in the sorted row
+      double mine = 0.0;
+      if (isnew) mine = sm.acc[w][slot];
+      const int distinct = __popcll(newmask);
+      uint32_t rank = 0;
+      if (narrow && distinct <= 32) {
+        // owners' columns compacted into lanes [0, distinct), compared with
+        // scalar reads at fixed lane indices (no loop, no branches)
+        if (isnew) sm.own[w][__popcll(newmask & lanemask_lt())] = (uint32_t)col;
+        wave_lds_sync();
+        const uint32_t oc = lane < distinct ? sm.own[w][lane] : 0xFFFFFFFFu;
+        const uint32_t c32 = (uint32_t)col;
+#pragma unroll
+        for (int b = 0; b < 32; ++b) rank += readlane_u32(oc, b) < c32 ? 1u : 0u;
+      } else {
+        for (uint64_t mm = newmask; mm; mm &= mm - 1) {
+          const int b = __builtin_ctzll(mm);
+          const uint64_t cb = ((uint64_t)readlane_u32((uint32_t)(col >> 32), b) << 32) |
+                              readlane_u32((uint32_t)col, b);
+          rank += cb < col ? 1u : 0u;
+        }
+      }
+      if (isnew) {
+        const uint64_t o = out_base + rank;
+        out_livs[o] = col + ra.np * row;
+        out_vals[o] = mine;
+      }
+    }
+    wave_lds_sync();
+  } else {
+    // no accumulator: sort (column, product index), then each run head sums
+    // its run (invalid lanes carry the largest key and sort last)
+    uint64_t key = col;
+    uint32_t idx = (uint32_t)lane;
+    double val = v;
+    wave_bitonic(key, idx, val);
+    const uint64_t prev = __shfl_up(key, 1, kWave);
+    const bool head = key != kEmpty && (lane == 0 || prev != key);
+    const uint64_t hmask = __ballot(head);
+    if (!NUMERIC) {
+      if (lane == 0) *cnt_slot = (uint64_t)__popcll(hmask);
+    } else {
+      double acc = 0.0;
+      bool active = head;
+      if (head) acc += val;
+      for (int s = 1; s < kWave; ++s) {
+        const uint64_t ks = __shfl_down(key, s, kWave);
+        const double vs = __shfl_down(val, s, kWave);
+        if (active) {
+          if (lane + s < kWave && ks == key) acc += vs;
+          else active = false;
+        }
+        if (!__any(active)) break;
+      }
+      if (head) {
+        const uint64_t o = out_base + (uint64_t)__popcll(hmask & lanemask_lt());
+        out_livs[o] = key + ra.np * row;
+        out_vals[o] = acc;
+      }
+    }
+  }
+}
+
+}  // namespace
+}  // namespace lco

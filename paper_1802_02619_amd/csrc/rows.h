@@ -1,6 +1,8 @@
 // Shared declarations of the multiplication kernels (row-wise engine and outer product).
 #pragma once
 
+#include <vector>
+
 #include "lco_internal.h"
 
 namespace lco {
@@ -33,12 +35,27 @@ struct RowArgs {
   const uint64_t* nzr_a = nullptr;       //   device count
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
   const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
+  int64_t a_base = 0;                    // index of A' entry 0 in the entry numbering of poff/bstart
 };
 
 // C' = A' * B' row by row; `dense` selects singly (CSR) or doubly (DCSR)
 // compressed B', `acc` the sparse accumulator (CSR, DCSR) or none (CSRNA).
 lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, uint64_t mp, uint64_t kp,
                       uint64_t np, bool dense, bool acc, int out_order, const uint64_t* out_dims);
+
+// One instance of a batch, in the row-engine roles (A' row-major, B' singly compressed).
+struct BatchJob {
+  int index;              // position in the caller's batch
+  const lco_tensor_s* A;  // A'
+  const lco_tensor_s* B;  // B'
+  uint64_t kp, np;
+  int order_c;
+  uint64_t natural_dims[LCO_MAX_ORDER];
+};
+// Runs the jobs (all with or all without accumulator) as one batch; writes
+// outs[job.index] for each completed job and returns the indices that need the
+// per-call path.
+std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs);
 
 // Simple outer product (Section 5.2.5) of A (column-major) and B (row-major).
 lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, const ContractDetail& d);

@@ -1,0 +1,106 @@
+"""GPU: batched contraction equals the per-call path bit for bit (and the oracle).
+
+The batch mixes FD compositions of different grids and orders (the batched
+path), products that need operand or output rearrangement, no-accumulator
+instances, and instances that must fall back to the per-call path (outer
+product, doubly compressed, long rows, empty operands).
+"""
+import numpy as np
+import pytest
+
+import lco_inputs as L
+from conftest import gpu_create
+
+pytestmark = pytest.mark.gpu
+
+
+def np_of(t):
+    d, l_, v = t.to_numpy()
+    return d.tolist(), l_, v.view(np.uint64)
+
+
+def test_batch_mixed_instances_equal_per_call(lco_lib, gpu_ctx, oracle_mod):
+    rng = np.random.default_rng(4096)
+    items, refs = [], []
+    keep = []
+    # FD compositions (batched, accumulator path)
+    for side, dim in ((8, 2), (13, 2), (31, 2), (8, 3), (11, 3), (20, 3)):
+        c, v = L.fd_laplacian(side, dim)
+        g = gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v)
+        keep.append(g)
+        la = list(range(2 * dim))
+        lb = list(range(dim, 3 * dim))
+        lc = list(range(dim)) + list(range(2 * dim, 3 * dim))
+        items.append((g, la, g, lb, lc))
+        o = oracle_mod.create([side] * (2 * dim), c, v)
+        refs.append(oracle_mod.contract(o, la, o, lb, lc))
+    # random products: rearranged operands and outputs, no-accumulator forced, fallbacks
+    ca, va = L.random_sparse(rng, [9, 12, 7], 300)
+    cb, vb = L.random_sparse(rng, [7, 12, 10], 300)
+    ga, gb = gpu_create(lco_lib, gpu_ctx, [9, 12, 7], ca, va), gpu_create(lco_lib, gpu_ctx, [7, 12, 10], cb, vb)
+    keep += [ga, gb]
+    oa, ob = oracle_mod.create([9, 12, 7], ca, va), oracle_mod.create([7, 12, 10], cb, vb)
+    for (la, lb, lc, flags) in (([0, 1, 2], [2, 1, 3], [0, 3], 0),
+                                ([0, 1, 2], [2, 1, 3], [3, 0], 0),
+                                ([0, 1, 2], [2, 1, 3], [0, 3], lco_lib.ALGO_IDS["CSRNA"]),
+                                ([0, 1, 2], [2, 1, 3], [3, 0], lco_lib.ALGO_IDS["CSCNA"]),
+                                ([0, 1, 2], [2, 1, 3], [0, 3], lco_lib.ALGO_IDS["DCSR"]),
+                                ([0, 1, 2], [2, 1, 3], [0, 3], lco_lib.ALGO_IDS["SOP"]),
+                                ([0, 1, 2], [3, 4, 5], [0, 1, 2, 3, 4, 5], 0)):
+        items.append((ga, la, gb, lb, lc, flags))
+        refs.append(oracle_mod.contract(oa, la, ob, lb, lc))
+    # a long-row instance (falls back) and an empty one
+    cl, vl = L.random_sparse(rng, [40, 200], 4000)
+    cm, vm = L.random_sparse(rng, [200, 150], 6000)
+    gl, gm = gpu_create(lco_lib, gpu_ctx, [40, 200], cl, vl), gpu_create(lco_lib, gpu_ctx, [200, 150], cm, vm)
+    ge = gpu_create(lco_lib, gpu_ctx, [200, 150], np.zeros((0, 2), np.uint64), np.zeros(0))
+    keep += [gl, gm, ge]
+    ol, om = oracle_mod.create([40, 200], cl, vl), oracle_mod.create([200, 150], cm, vm)
+    items.append((gl, [0, 1], gm, [1, 2], [0, 2]))
+    refs.append(oracle_mod.contract(ol, [0, 1], om, [1, 2], [0, 2]))
+    items.append((gl, [0, 1], ge, [1, 2], [0, 2]))
+    refs.append(None)
+
+    outs = lco_lib.lco_contract_batch(gpu_ctx, items)
+    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call}", flush=True)
+    assert batched >= 6 and per_call >= 4  # FD compositions batch; long rows / DCSR / SOP fall back
+    for it, out, ref in zip(items, outs, refs):
+        single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
+        got, alone = np_of(out), np_of(single)
+        assert got[0] == alone[0]
+        assert np.array_equal(got[1], alone[1]) and np.array_equal(got[2], alone[2])
+        if ref is None:
+            assert out.nnz == 0
+        else:
+            assert np.array_equal(got[1], ref.livs)
+            assert np.array_equal(got[2], ref.vals.view(np.uint64))
+        single.destroy()
+    # outputs share one allocation; releasing them in any order is safe
+    for out in outs[::2] + outs[1::2]:
+        out.destroy()
+
+
+def test_batch_many_small_fd(lco_lib, gpu_ctx, oracle_mod):
+    """200 uneven 2-D / 3-D FD compositions (sides 4..24) in one batch: every result equals its
+    closed-form size and the per-call result."""
+    rng = np.random.default_rng(7)
+    items, sizes = [], []
+    for _ in range(200):
+        dim = int(rng.integers(2, 4))
+        side = int(rng.integers(4, 25 if dim == 2 else 13))
+        c, v = L.fd_laplacian(side, dim)
+        g = gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v)
+        items.append((g, list(range(2 * dim)), g, list(range(dim, 3 * dim)),
+                      list(range(dim)) + list(range(2 * dim, 3 * dim))))
+        s = side
+        sizes.append(s * s + 4 * s * (s - 1) + 4 * (s - 1) ** 2 + 4 * s * (s - 2) if dim == 2 else
+                     s**3 + 6 * s * s * (s - 1) + 12 * s * (s - 1) ** 2 + 6 * s * s * (s - 2))
+    outs = lco_lib.lco_contract_batch(gpu_ctx, items)
+    assert lco_lib.lco_batch_stats(gpu_ctx) == (200, 0)
+    for it, out, n in zip(items, outs, sizes):
+        assert out.nnz == n
+    for k in (0, 57, 199):
+        single = lco_lib.lco_contract(gpu_ctx, *items[k])
+        a, b = np_of(outs[k]), np_of(single)
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
