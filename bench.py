@@ -76,6 +76,23 @@ def measured_traffic(kernel: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10):
+    """Measured device-copy ceiling: a plain elementwise copy of `nbytes` (read + write) on the
+    current stream, timed with HIP events; GB/s counts both directions."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
+        torch.neg(src, out=dst)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = statistics.median(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(coords, vals, nnz_c_total: int, frac_den: int = 32):
     """The oracle (single thread) on a bounded sample of the same step."""
     import numpy as np
@@ -113,6 +130,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -127,6 +146,9 @@ def main():
     import paper_1802_02619_amd as lco
 
     torch.cuda.set_device(0)
+    if args.copy_probe_only:
+        print(json.dumps({"copy_GBps": copy_ceiling(torch), "bytes_each_way": 1 << 30}), flush=True)
+        return
     ctx = lco.lco_ctx_create(0)
     coords, vals = L.fd_laplacian(SIDE, 3)
     idx_d = torch.from_numpy(coords.view(np.int64).reshape(-1).copy()).to("cuda:0")
@@ -218,6 +240,7 @@ def main():
             "dims": [SIDE] * 6, "nnz_in": nnz_in, "nnz_out": nnz_c, "algo": plan["algo_name"],
             "index": "u64 LIV", "parallelism": "single GPU",
         },
+        "copy_ceiling_GBps": copy_ceiling(torch),
         "permute": {"ms": perm_ms, "effective_GBps": perm_gbps, "frac_hbm_peak": perm_gbps / HBM_PEAK_GBPS,
                     "bytes_algorithmic": 32 * nnz_in},
         "roofline": roof,

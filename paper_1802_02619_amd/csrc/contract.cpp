@@ -76,10 +76,6 @@ lco_status set_error_msg(lco_status s, const char* msg);
 
 using namespace lco;
 
-namespace {
-int64_t g_batch_stats[2] = {0, 0};  // per context would need the context; the last call on any context
-}
-
 extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs) {
   if (!ctx || count < 0 || (count && (!descs || !outs))) return set_error_msg(LCO_E_ARG, "lco_contract_batch: bad argument");
   for (int i = 0; i < count; ++i) outs[i] = nullptr;
@@ -148,8 +144,8 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
     percall.insert(percall.end(), redo.begin(), redo.end());
     for (int i : percall) outs[i] = contract_run(ctx, descs[i].a, descs[i].b, plans[i]);
     for (lco_tensor t : temps) lco_destroy(t);
-    g_batch_stats[0] = (int64_t)batched.size() - (int64_t)redo.size();
-    g_batch_stats[1] = (int64_t)percall.size();
+    ctx->batch_stats[0] = (int64_t)batched.size() - (int64_t)redo.size();
+    ctx->batch_stats[1] = (int64_t)percall.size();
     return LCO_OK;
   } catch (const Error& e) {
     for (lco_tensor t : temps) lco_destroy(t);
@@ -170,7 +166,7 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
 
 extern "C" lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call) {
   if (!ctx || !batched || !per_call) return set_error_msg(LCO_E_ARG, "lco_batch_stats: bad argument");
-  *batched = g_batch_stats[0];
-  *per_call = g_batch_stats[1];
+  *batched = ctx->batch_stats[0];
+  *per_call = ctx->batch_stats[1];
   return LCO_OK;
 }

@@ -68,6 +68,10 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T* wsum, T& total) {
 // repeated invariant division, then re-linearise with the new order's weights.
 __device__ __forceinline__ uint64_t shuffle_liv(const ShuffleParams& sp, uint64_t x) {
   uint64_t out = 0;
+  if (sp.all_pow2) {
+    for (int q = 0; q < sp.order; ++q) out |= ((x >> sp.in_shift[q]) & sp.in_mask[q]) << sp.out_shift[q];
+    return out;
+  }
   for (int q = 0; q < sp.order - 1; ++q) {
     uint64_t c;
     x = fd_divmod(sp.dim[q], x, c);

@@ -133,8 +133,8 @@ __global__ __launch_bounds__(kRowThreads) void bt_small_kernel(
   __shared__ uint32_t s_own[kRowWaves][kWave];
   const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t nw = gridDim.x * kRowWaves;
-  for (uint32_t r = blockIdx.x * kRowWaves + w; r < nrows; r += nw) {
+  const RowSpan sp = xcd_row_span(nrows, w);
+  for (uint64_t r = sp.first; r < sp.end; r += sp.step) {
     const uint8_t sh = shape[r];
     const uint32_t i = rinst[r];
     if (sh == kShapeSkip || fallback[i]) continue;

@@ -334,6 +334,27 @@ int grid_for(lco_ctx ctx, int64_t n, int threads) {
 
 }  // namespace
 
+ShuffleParams make_shuffle(int order, const uint64_t* dims, const uint64_t* new_weight_of_input_mode) {
+  ShuffleParams sp;
+  sp.order = order;
+  sp.all_pow2 = 1;
+  uint32_t at = 0;
+  for (int q = 0; q < order; ++q) {
+    sp.dim[q] = make_fastdiv(dims[q]);
+    sp.new_weight[q] = new_weight_of_input_mode[q];
+    const uint64_t w = new_weight_of_input_mode[q];
+    if (!sp.dim[q].pow2 || (w & (w - 1)) != 0) {
+      sp.all_pow2 = 0;
+      continue;
+    }
+    sp.in_shift[q] = at;
+    sp.in_mask[q] = dims[q] - 1;
+    sp.out_shift[q] = (uint32_t)__builtin_ctzll(w);
+    at += sp.dim[q].shift;
+  }
+  return sp;
+}
+
 int default_digit_cap() {
   static int cap = [] {
     const char* e = std::getenv("LCO_DIGIT_BITS");
@@ -434,12 +455,7 @@ void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, 
                      double* out_vals) {
   const int64_t n = in->nnz;
   if (n == 0) return;
-  ShuffleParams sp;
-  sp.order = in->order;
-  for (int q = 0; q < in->order; ++q) {
-    sp.dim[q] = make_fastdiv(in->dims[q]);
-    sp.new_weight[q] = plan.new_weight_of_input_mode[q];
-  }
+  const ShuffleParams sp = make_shuffle(in->order, in->dims, plan.new_weight_of_input_mode);
   KeyParams kp;
   kp.key_div = make_fastdiv(plan.pub.key_div);
   kp.key_base = 0;

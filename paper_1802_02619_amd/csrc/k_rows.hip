@@ -145,9 +145,9 @@ __global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, uint
   __shared__ uint32_t s_own[kRowWaves][kWave];
   const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t nw = gridDim.x * kRowWaves;
   const bool narrow = ra.np < (1ull << 32);  // columns fit 32 bits below the padding key
-  for (uint32_t r = blockIdx.x * kRowWaves + w; r < nzr; r += nw) {
+  const RowSpan sp = xcd_row_span(nzr, w);
+  for (uint64_t r = sp.first; r < sp.end; r += sp.step) {
     const uint8_t sh = shape[r];
     if (sh == kShapeSkip) continue;
     const uint32_t e0 = ra.row_start[r];

@@ -65,6 +65,7 @@ struct lco_ctx_s {
   uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words)
   lco::Timer timer;
   uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
+  int64_t batch_stats[2] = {0, 0};  // last batch on this context: instances batched, run per call
 };
 
 namespace lco {
@@ -179,7 +180,14 @@ struct ShuffleParams {
   int order = 0;
   FastDiv dim[kMaxOrder];        // old dimensions, least significant first
   uint64_t new_weight[kMaxOrder];  // weight of old mode q in the new LIV
+  // When every dimension is a power of two the shuffle only moves bit fields:
+  // old mode q is bits [in_shift[q], in_shift[q] + log2 dim) of the old LIV and
+  // lands at bit out_shift[q] of the new one.
+  int all_pow2 = 0;
+  uint32_t in_shift[kMaxOrder] = {}, out_shift[kMaxOrder] = {};
+  uint64_t in_mask[kMaxOrder] = {};
 };
+ShuffleParams make_shuffle(int order, const uint64_t* dims, const uint64_t* new_weight_of_input_mode);
 
 // Key of an element for the radix passes: key = (x / key_div) - key_base.
 struct KeyParams {

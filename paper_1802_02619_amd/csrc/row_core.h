@@ -12,6 +12,25 @@ constexpr int kRowWaves = 4;
 constexpr int kRowThreads = kRowWaves * kWave;
 constexpr uint64_t kEmpty = ~0ull;
 
+// Rows handled by one wave.  Workgroups are dispatched round-robin over the
+// eight XCDs (block b runs on XCD b % 8), each with its own L2; giving every
+// XCD one contiguous share of the rows keeps neighbouring rows, which gather
+// the same rows of B', in one L2.  Every row in [0, n) is visited exactly once
+// for any grid size.
+constexpr uint32_t kXcds = 8;
+struct RowSpan {
+  uint64_t first, end, step;
+};
+__device__ __forceinline__ RowSpan xcd_row_span(uint64_t n, int w) {
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  if (G < kXcds) return {(uint64_t)b * kRowWaves + w, n, (uint64_t)G * kRowWaves};
+  const uint32_t x = b % kXcds, slot = b / kXcds, nb = (G - x + kXcds - 1) / kXcds;
+  const uint64_t chunk = (n + kXcds - 1) / kXcds;
+  const uint64_t begin = x * chunk < n ? x * chunk : n;
+  const uint64_t end = begin + chunk < n ? begin + chunk : n;
+  return {begin + (uint64_t)slot * kRowWaves + w, end, (uint64_t)nb * kRowWaves};
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
