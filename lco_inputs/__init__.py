@@ -24,6 +24,12 @@ Workloads (all synthetic, seeded, shaped like the paper's benchmark operators):
 * ``random_sparse(rng, dims, nnz)`` -- distinct uniformly random coordinates.
 * ``diagonal(order, n)`` -- the purely diagonal tensor of the paper's Figure on
   hyper-sparsity of matricised tensors (all-zero except i=j=...).
+* ``batched_fd_instances(count, seed)`` -- the (dimension, grid side) of each
+  instance of a batch of FD self-compositions: 2-D 5-point or 3-D 7-point
+  (50/50), side uniform in 8..64.
+* ``serving_trace(seconds, rate, seed)`` -- a Poisson request stream: arrival
+  times and, per request, its class (small 2-D FD composition, large 3-D FD
+  composition, hyper-sparse Kronecker pair) and size parameter.
 """
 from __future__ import annotations
 
@@ -34,6 +40,8 @@ __all__ = [
     "kronecker_hypersparse",
     "random_sparse",
     "diagonal",
+    "batched_fd_instances",
+    "serving_trace",
     "KRON_PROBS",
 ]
 
@@ -127,3 +135,36 @@ def diagonal(order: int, n: int, values=None):
     coords = np.ascontiguousarray(np.stack([c] * order, axis=1))
     vals = np.arange(1, n + 1, dtype=np.float64) if values is None else np.asarray(values, dtype=np.float64)
     return coords, vals
+
+
+def batched_fd_instances(count: int = 4096, seed: int = 4096, lo: int = 8, hi: int = 64):
+    """``[(dim, side), ...]``: each instance is the ``dim``-D FD Laplacian on a ``side**dim`` grid,
+    composed with itself.  Sides are drawn first (uniform in ``lo..hi``), then the kinds
+    (0: 2-D 5-point, 1: 3-D 7-point), from ``PCG64(seed)``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = rng.integers(lo, hi + 1, size=count)
+    kind = rng.integers(0, 2, size=count)
+    return [(2 + int(k), int(s)) for s, k in zip(side, kind)]
+
+
+SERVE_CLASSES = ("fd2", "fd3", "kron")
+
+
+def serving_trace(seconds: float = 60.0, rate: float = 200.0, seed: int = 5):
+    """A Poisson request stream from ``PCG64(seed)``: exponential inter-arrival gaps of mean
+    ``1/rate`` seconds up to ``seconds``; per request a uniform draw picks the class
+    (70 % ``fd2``: 2-D 5-point FD composition with side U{16..96}; 25 % ``fd3``: 3-D 7-point
+    with side U{64..128}; 5 % ``kron``: a hyper-sparse Kronecker pair with 2**L per mode,
+    L U{12..16}).  Returns ``(arrival_s, cls, param)`` arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_max = int(seconds * rate * 2 + 100)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_max))
+    n = int(np.searchsorted(t, seconds))
+    t = t[:n]
+    u = rng.random(n)
+    cls = np.where(u < 0.70, 0, np.where(u < 0.95, 1, 2)).astype(np.int64)
+    p2 = rng.integers(16, 97, size=n)
+    p3 = rng.integers(64, 129, size=n)
+    pk = rng.integers(12, 17, size=n)
+    param = np.where(cls == 0, p2, np.where(cls == 1, p3, pk)).astype(np.int64)
+    return t, cls, param

@@ -126,15 +126,23 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
       (algo == LCO_ALG_CSR || algo == LCO_ALG_CSC ? acc_jobs : na_jobs).push_back(j);
       batched.push_back(i);
     }
+    // each group runs in chunks of bounded total entries (bounded scratch, 32-bit entry indices)
     std::vector<int> redo;
-    if (!acc_jobs.empty()) {
-      std::vector<int> r = batch_group(ctx, acc_jobs, true, outs);
-      redo.insert(redo.end(), r.begin(), r.end());
-    }
-    if (!na_jobs.empty()) {
-      std::vector<int> r = batch_group(ctx, na_jobs, false, outs);
-      redo.insert(redo.end(), r.begin(), r.end());
-    }
+    auto run_chunks = [&](const std::vector<BatchJob>& jobs, bool acc) {
+      size_t i = 0;
+      while (i < jobs.size()) {
+        std::vector<BatchJob> chunk;
+        int64_t entries = 0;
+        while (i < jobs.size() && (chunk.empty() || entries + jobs[i].A->nnz <= kBatchChunkEntries)) {
+          entries += jobs[i].A->nnz;
+          chunk.push_back(jobs[i++]);
+        }
+        std::vector<int> r = batch_group(ctx, chunk, acc, outs);
+        redo.insert(redo.end(), r.begin(), r.end());
+      }
+    };
+    run_chunks(acc_jobs, true);
+    run_chunks(na_jobs, false);
     for (int i : batched) {
       if (!outs[i] || !plans[i].pub.permute_c) continue;
       lco_tensor natural = outs[i];

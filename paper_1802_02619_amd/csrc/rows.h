@@ -52,6 +52,8 @@ struct BatchJob {
   int order_c;
   uint64_t natural_dims[LCO_MAX_ORDER];
 };
+// A batch runs in chunks of at most this many A' entries in total.
+constexpr int64_t kBatchChunkEntries = int64_t(1) << 26;
 // Runs the jobs (all with or all without accumulator) as one batch; writes
 // outs[job.index] for each completed job and returns the indices that need the
 // per-call path.
