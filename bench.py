@@ -210,6 +210,141 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
     }
 
 
+def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
+    """Replay a Poisson request trace in real time against the continuous-batching server, then
+    the same trace against serial plain calls (one worker, one request at a time, FIFO)."""
+    t_arr, cls, param = L.serving_trace(seconds)
+    n = len(t_arr)
+    dev = torch.device("cuda", 0)
+
+    def make(coords, vals, dims, flags):
+        return lco.lco_create(ctx, dims, coords.reshape(-1).contiguous(), vals, flags)
+
+    pool = {}
+    for c, p in sorted(set(zip(cls.tolist(), param.tolist()))):
+        if c in (0, 1):
+            dim = 2 + c
+            co, va = L.fd_laplacian_torch(p, dim, dev)
+            pool[(c, p)] = make(co, va, [p] * (2 * dim), lco.LCO_COORDS)
+        else:
+            pair = []
+            for seed in (1, 2):
+                co, va = L.kronecker_hypersparse_torch(p, 1 << (p + 8), seed, dev)
+                pair.append(make(co, va, [1 << p] * 4, lco.LCO_COORDS | lco.LCO_SUM_DUPLICATES))
+            pool[(c, p)] = tuple(pair)
+        del co, va
+    torch.cuda.synchronize()
+
+    def request(i):
+        c, p = int(cls[i]), int(param[i])
+        if c == 2:
+            a, b = pool[(c, p)]
+            return (a, [0, 1, 2, 3], b, [2, 3, 4, 5], [0, 1, 4, 5])
+        a = pool[(c, p)]
+        la, lb, lc = fd_labels(2 + c)
+        return (a, la, a, lb, lc)
+
+    # the smallest request of each class is kept and compared with a plain call on its own
+    probe = {}
+    for i in range(n):
+        k = int(cls[i])
+        if k not in probe or param[i] < param[probe[k]]:
+            probe[k] = i
+
+    def replay(server):
+        lat = np.zeros(n)
+        nnz = np.zeros(n, dtype=np.int64)
+        bs = np.zeros(n, dtype=np.int64)
+        kept = {}
+        bad = []
+        base = 0
+        for k in probe.values():  # warm-up: one request per class, drained before the clock starts
+            base = server.submit(*request(k)) + 1
+        server.drain()
+        for r in server.poll():
+            if r["out"] is not None:
+                r["out"].destroy()
+
+        def handle(results):
+            for r in results:
+                i = r["ticket"] - base
+                if r["status"] != 0 or r["out"] is None:
+                    bad.append(i)
+                    continue
+                lat[i], bs[i] = r["latency_ms"], r["batch_size"]
+                nnz[i] = r["out"].nnz
+                if i in probe.values():
+                    kept[i] = r["out"]  # read after the replay
+                else:
+                    r["out"].destroy()
+
+        t0 = time.perf_counter()
+        for i in range(n):
+            target = t0 + t_arr[i]
+            while True:
+                handle(server.poll())
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 2e-4))
+            server.submit(*request(i))
+        server.drain()
+        handle(server.poll())
+        wall = time.perf_counter() - t0
+        for i, t in list(kept.items()):
+            kept[i] = t.to_numpy()
+            t.destroy()
+        return lat, nnz, bs, kept, bad, wall
+
+    out = {"workload": f"Poisson trace, 200 req/s for {seconds:g} s (seed 5): 70% 2-D 5-point FD compositions "
+                       "(side 16..96), 25% 3-D 7-point (side 64..128), 5% hyper-sparse Kronecker pairs "
+                       "(2^L per mode, L 12..16, 2^(L+8) draws); operands resident in HBM",
+           "requests": n}
+    for name, kw in (("served", dict(workers=workers, max_batch=256, plain=False)),
+                     ("serial_plain", dict(workers=1, max_batch=1, plain=True))):
+        srv = lco.Server(0, **kw)
+        try:
+            lat, nnz, bs, kept, bad, wall = replay(srv)
+        finally:
+            srv.destroy()
+        ok = lat > 0
+        per = {}
+        for c, cname in enumerate(("fd2", "fd3", "kron")):
+            m = ok & (cls == c)
+            if m.any():
+                per[cname] = {"n": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
+                              "p99_ms": float(np.percentile(lat[m], 99))}
+        out[name] = {"p50_ms": float(np.percentile(lat[ok], 50)), "p99_ms": float(np.percentile(lat[ok], 99)),
+                     "mean_ms": float(lat[ok].mean()), "req_per_s": float(ok.sum() / wall),
+                     "output_nnz_per_s": float(nnz[ok].sum() / wall), "wall_s": wall, "errors": len(bad),
+                     "mean_batch": float(bs[ok].mean()), "max_batch": int(bs[ok].max()), "per_class": per,
+                     "config": kw}
+        out[name + "_nnz"] = nnz
+        out[name + "_kept"] = kept
+    # every request: identical output size in both modes; FD sizes equal the closed form
+    same = bool(np.array_equal(out.pop("served_nnz"), out["serial_plain_nnz"]))
+    fdn = out.pop("serial_plain_nnz")
+    fd_ok = all(fdn[i] == fd_compose_nnz(2 + int(cls[i]), int(param[i])) for i in range(n) if cls[i] < 2)
+    # probes: served result == serial plain result == a plain call on the main context
+    ks, kp = out.pop("served_kept"), out.pop("serial_plain_kept")
+    ident = True
+    for i in probe.values():
+        a = lco.lco_contract(ctx, *request(i))
+        _, la_, va_ = a.to_numpy()
+        a.destroy()
+        for kept in (ks, kp):
+            ident &= i in kept and np.array_equal(kept[i][1], la_) and \
+                np.array_equal(kept[i][2].view(np.uint64), va_.view(np.uint64))
+    for t in pool.values():
+        for x in (t if isinstance(t, tuple) else (t,)):
+            x.destroy()
+    out["nnz_same_served_vs_plain"] = same
+    out["fd_nnz_closed_form_ok"] = bool(fd_ok)
+    out["probes_bit_identical"] = bool(ident)
+    out["p99_speedup_served_vs_plain"] = out["serial_plain"]["p99_ms"] / out["served"]["p99_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +353,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the replayed request trace (0: skip the serving leg)")
+    ap.add_argument("--serve-workers", type=int, default=3)
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -336,6 +474,8 @@ def main():
     }
     if args.batch_count > 0:
         out["batched"] = batched_leg(lco, ctx, torch, np, L, args.batch_count, args.batch_reps)
+    if args.serve_seconds > 0:
+        out["serving"] = serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers)
     if not args.no_cpu_baseline:
         cb, (rows, c_sub) = cpu_baseline(coords, vals, nnz_c)
         # the sampled rows of the GPU result must equal the oracle's

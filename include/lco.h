@@ -29,7 +29,9 @@
  *     that stream before returning; lco_permute does not.
  *   - Tensors are owned by the caller and released with lco_destroy, which must
  *     happen before the context that made them is destroyed.  Inputs are never
- *     modified.
+ *     modified.  An input may come from any context on the same device; work
+ *     that produced it on another stream must be complete (or ordered before
+ *     the call by the caller).
  *   - LIVs are unsigned: the product of a tensor's dimensions may be anything up
  *     to and including 2^64 (the paper limits itself to signed 63-bit LIVs).
  *   - At most LCO_MAX_ORDER modes per tensor; at most 2^32-1 non-zeros per
@@ -112,6 +114,11 @@ lco_status lco_create(lco_ctx ctx, int order, const uint64_t* dims, int64_t nnz,
 
 /* Release a tensor's device memory (stream-ordered) and its handle. */
 lco_status lco_destroy(lco_tensor t);
+
+/* Copy a tensor's nnz LIVs and values into host arrays `livs` / `vals` (each
+ * with room for lco_nnz(t) entries; either may be NULL to skip it).  Blocking:
+ * waits for the tensor's context stream, then copies. */
+lco_status lco_read(lco_tensor t, uint64_t* livs, double* vals);
 
 int64_t lco_nnz(lco_tensor t);
 int lco_order(lco_tensor t);
@@ -208,6 +215,58 @@ typedef struct {
 lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs);
 /* How many instances of the last lco_contract_batch call ran batched / per call. */
 lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A request server for contractions (continuous batching).  Requests are
+ * submitted as they arrive; `workers` threads each own a HIP stream (default
+ * priority) and a context allocating with stream-ordered hipMallocAsync.  A
+ * worker that becomes free takes every pending request that fits -- in arrival
+ * order, up to `max_batch`, while the sum of their estimated device footprints
+ * stays within `hbm_budget` bytes -- and runs them as one lco_contract_batch;
+ * requests that arrive meanwhile wait for the next free worker, so batches of
+ * different workers overlap on the device.  Requests whose plan is not a
+ * row-engine product (doubly compressed, outer product) or whose operands hold
+ * more than `solo_nnz` non-zeros are run in a batch of their own.  With
+ * `plain` set every request runs alone through lco_contract (the serial
+ * baseline when workers == 1).  Results are bit-identical to lco_contract on
+ * the same operands whatever the batch they ran in.
+ *
+ * Operands may belong to any context on the server's device; the caller
+ * guarantees that they are complete (their context synchronised) when
+ * submitted and that they live until the request completes.  Result tensors
+ * belong to the caller (lco_destroy, before lco_server_destroy); their LIVs and
+ * values are read with lco_read. */
+typedef struct lco_server_s* lco_server;
+
+typedef struct {
+  int workers;          /* >= 1 */
+  int max_batch;        /* >= 1 */
+  int plain;            /* 0 or 1 */
+  int64_t solo_nnz;     /* operands with more non-zeros (nnz_a + nnz_b) run alone; <= 0: never */
+  uint64_t hbm_budget;  /* bytes; a request above the whole budget runs when nothing else is in flight */
+} lco_server_config;
+
+typedef struct {
+  int64_t ticket;       /* from lco_server_submit */
+  lco_status status;    /* the request's own result */
+  lco_tensor out;       /* the product (NULL on error) */
+  double latency_ms;    /* submission -> result complete on the device */
+  double queue_ms;      /* submission -> its batch started */
+  int batch_size;       /* requests in the batch it ran in */
+} lco_server_result;
+
+lco_status lco_server_create(int device, const lco_server_config* cfg, lco_server* out);
+/* Enqueue a product (arguments as lco_contract; label arrays are copied).
+ * *ticket receives the request's number (0, 1, 2, ... in submission order). */
+lco_status lco_server_submit(lco_server s, const lco_contract_desc* desc, int64_t* ticket);
+/* Non-blocking: moves up to `cap` completed requests into results[] and sets
+ * *count to how many. */
+lco_status lco_server_poll(lco_server s, lco_server_result* results, int cap, int* count);
+/* Block until every submitted request has completed (they stay pollable). */
+lco_status lco_server_drain(lco_server s);
+/* Drain, join the workers, release results never polled, destroy the server. */
+lco_status lco_server_destroy(lco_server s);
 
 /* The plan lco_contract would run for these operands, without running it. */
 lco_status lco_plan_info(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,

@@ -27,6 +27,12 @@ Workloads (all synthetic, seeded, shaped like the paper's benchmark operators):
 * ``batched_fd_instances(count, seed)`` -- the (dimension, grid side) of each
   instance of a batch of FD self-compositions: 2-D 5-point or 3-D 7-point
   (50/50), side uniform in 8..64.
+* ``fd_laplacian_torch`` / ``kronecker_hypersparse_torch`` -- the same recipes
+  producing coordinates directly in device memory with torch (for operand
+  pools too large to generate on the host quickly).  The FD operator is the
+  same set of entries as ``fd_laplacian`` (in another order); the Kronecker
+  tensor follows the same quadrant recipe but draws from torch's generator,
+  so it is not the PCG64 tensor of the same seed.
 * ``serving_trace(seconds, rate, seed)`` -- a Poisson request stream: arrival
   times and, per request, its class (small 2-D FD composition, large 3-D FD
   composition, hyper-sparse Kronecker pair) and size parameter.
@@ -41,6 +47,8 @@ __all__ = [
     "random_sparse",
     "diagonal",
     "batched_fd_instances",
+    "fd_laplacian_torch",
+    "kronecker_hypersparse_torch",
     "serving_trace",
     "KRON_PROBS",
 ]
@@ -155,16 +163,64 @@ def serving_trace(seconds: float = 60.0, rate: float = 200.0, seed: int = 5):
     ``1/rate`` seconds up to ``seconds``; per request a uniform draw picks the class
     (70 % ``fd2``: 2-D 5-point FD composition with side U{16..96}; 25 % ``fd3``: 3-D 7-point
     with side U{64..128}; 5 % ``kron``: a hyper-sparse Kronecker pair with 2**L per mode,
-    L U{12..16}).  Returns ``(arrival_s, cls, param)`` arrays."""
+    L U{12..16}).  Requests are drawn in blocks of 4096 (gaps, class draws, then the three
+    size draws), so a shorter window is a prefix of a longer one.  Returns
+    ``(arrival_s, cls, param)`` arrays."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    n_max = int(seconds * rate * 2 + 100)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=n_max))
+    ts, cs, ps = [], [], []
+    t_end = 0.0
+    while t_end < seconds:
+        gaps = rng.exponential(1.0 / rate, size=4096)
+        u = rng.random(4096)
+        p2 = rng.integers(16, 97, size=4096)
+        p3 = rng.integers(64, 129, size=4096)
+        pk = rng.integers(12, 17, size=4096)
+        t = t_end + np.cumsum(gaps)
+        t_end = float(t[-1])
+        cls = np.where(u < 0.70, 0, np.where(u < 0.95, 1, 2)).astype(np.int64)
+        ts.append(t)
+        cs.append(cls)
+        ps.append(np.where(cls == 0, p2, np.where(cls == 1, p3, pk)).astype(np.int64))
+    t, cls, param = np.concatenate(ts), np.concatenate(cs), np.concatenate(ps)
     n = int(np.searchsorted(t, seconds))
-    t = t[:n]
-    u = rng.random(n)
-    cls = np.where(u < 0.70, 0, np.where(u < 0.95, 1, 2)).astype(np.int64)
-    p2 = rng.integers(16, 97, size=n)
-    p3 = rng.integers(64, 129, size=n)
-    pk = rng.integers(12, 17, size=n)
-    param = np.where(cls == 0, p2, np.where(cls == 1, p3, pk)).astype(np.int64)
-    return t, cls, param
+    return t[:n], cls[:n], param[:n]
+
+
+def fd_laplacian_torch(side: int, dim: int, device):
+    """``(coords, vals)`` torch tensors on ``device``: the entries of ``fd_laplacian(side, dim)``
+    (coordinates int64 of shape ``(nnz, 2*dim)``, row point then column point), unsorted."""
+    import torch
+    n = side**dim
+    p = torch.arange(n, device=device, dtype=torch.int64)
+    pts = [(p // side**a) % side for a in range(dim)]  # x, y[, z] of each grid point
+    cs = [torch.stack(pts + pts, dim=1)]
+    vs = [torch.full((n,), -2.0 * dim, dtype=torch.float64, device=device)]
+    for a in range(dim):
+        for step in (-1, 1):
+            q = pts[a] + step
+            ok = (q >= 0) & (q < side)
+            row = list(pts)
+            row[a] = q
+            c = torch.stack(row + pts, dim=1)[ok]
+            cs.append(c)
+            vs.append(torch.ones(c.shape[0], dtype=torch.float64, device=device))
+    return torch.cat(cs), torch.cat(vs)
+
+
+def kronecker_hypersparse_torch(bits: int, draws: int, seed: int, device, probs=KRON_PROBS):
+    """``(coords, vals)`` torch tensors on ``device``: the quadrant recipe of
+    ``kronecker_hypersparse`` with uniform numbers from ``torch.Generator(device).manual_seed(seed)``.
+    Duplicate coordinates are kept."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    cum = torch.tensor(np.cumsum(np.asarray(probs, dtype=np.float64)), dtype=torch.float64, device=device)
+    coords = torch.zeros((draws, 4), dtype=torch.int64, device=device)
+    for b in range(bits):
+        for (m0, m1) in ((0, 1), (2, 3)):
+            u = torch.rand(draws, generator=g, dtype=torch.float64, device=device)
+            q = torch.bucketize(u, cum, right=True).clamp_(max=3)
+            coords[:, m0] |= (q >> 1) << b
+            coords[:, m1] |= (q & 1) << b
+    vals = torch.rand(draws, generator=g, dtype=torch.float64, device=device) * 2.0 - 1.0
+    return coords, vals

@@ -16,7 +16,7 @@ import threading
 __all__ = [
     "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
-    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
+    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
@@ -72,6 +72,16 @@ class RpPlan(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int), ("max_batch", ctypes.c_int), ("plain", ctypes.c_int),
+                ("solo_nnz", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int), ("out", ctypes.c_void_p),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("batch_size", ctypes.c_int)]
+
+
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
@@ -116,6 +126,12 @@ def load_library():
             "lco_timing_kernel_name": (ctypes.c_char_p, [vp, i32]),
             "lco_create": (i32, [vp, i32, pu64, i64, vp, vp, u32, pvp]),
             "lco_destroy": (i32, [vp]),
+            "lco_read": (i32, [vp, vp, vp]),
+            "lco_server_create": (i32, [i32, ctypes.POINTER(ServerConfig), pvp]),
+            "lco_server_submit": (i32, [vp, ctypes.POINTER(ContractDesc), ctypes.POINTER(i64)]),
+            "lco_server_poll": (i32, [vp, ctypes.POINTER(ServerResult), i32, ctypes.POINTER(i32)]),
+            "lco_server_drain": (i32, [vp]),
+            "lco_server_destroy": (i32, [vp]),
             "lco_nnz": (i64, [vp]),
             "lco_order": (i32, [vp]),
             "lco_dims": (pu64, [vp]),
@@ -270,12 +286,15 @@ class Tensor:
         return self.ctx.view(p, n * 8, torch.uint8).view(torch.float64)
 
     def to_numpy(self):
-        """(dims, livs uint64, vals float64) copied to the host."""
+        """(dims, livs uint64, vals float64) copied to the host (lco_read)."""
         import numpy as np
-        self.ctx.synchronize()
-        livs = self.livs().cpu().numpy().view(np.uint64)
-        vals = self.vals().cpu().numpy()
-        return np.array(self.dims, dtype=np.uint64), livs.copy(), vals.copy()
+        n = self.nnz
+        livs = np.empty(n, dtype=np.uint64)
+        vals = np.empty(n, dtype=np.float64)
+        if n:
+            _check(load_library().lco_read(self.handle, livs.ctypes.data_as(ctypes.c_void_p),
+                                           vals.ctypes.data_as(ctypes.c_void_p)))
+        return np.array(self.dims, dtype=np.uint64), livs, vals
 
     def destroy(self):
         if self.handle:
@@ -301,6 +320,12 @@ def lco_create(ctx: Context, dims, idx, vals, flags: int = 0) -> Tensor:
 
 def lco_destroy(t: Tensor):
     t.destroy()
+
+
+def lco_read(t: Tensor):
+    """(livs uint64, vals float64) of a tensor, copied to the host."""
+    _, livs, vals = t.to_numpy()
+    return livs, vals
 
 
 def lco_permute(ctx: Context, t: Tensor, perm) -> Tensor:
@@ -341,6 +366,51 @@ def lco_contract_batch(ctx: Context, items):
     outs = (ctypes.c_void_p * max(1, n))()
     _check(L.lco_contract_batch(ctx.handle, n, descs, outs))
     return [Tensor(ctx, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+class Server:
+    """Continuous-batching request server (lco_server_*).  Result tensors have no Python
+    context: read them with to_numpy() and release them with destroy()."""
+
+    def __init__(self, device: int = 0, workers: int = 3, max_batch: int = 256, plain: bool = False,
+                 solo_nnz: int = 1 << 22, hbm_budget: int = 64 << 30):
+        L = load_library()
+        cfg = ServerConfig(int(workers), int(max_batch), int(bool(plain)), int(solo_nnz), int(hbm_budget))
+        h = ctypes.c_void_p()
+        _check(L.lco_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._buf = (ServerResult * 256)()
+
+    def submit(self, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> int:
+        arrs = (_i32arr(a_labels), _i32arr(b_labels), _i32arr(c_labels))
+        d = ContractDesc(a.handle, arrs[0], b.handle, arrs[1], len(c_labels), arrs[2], int(flags))
+        t = ctypes.c_int64()
+        _check(load_library().lco_server_submit(self.handle, ctypes.byref(d), ctypes.byref(t)))
+        return t.value
+
+    def poll(self):
+        """Completed requests: list of dicts (ticket, status, out Tensor or None, latency_ms,
+        queue_ms, batch_size)."""
+        L = load_library()
+        res = []
+        while True:
+            n = ctypes.c_int()
+            _check(L.lco_server_poll(self.handle, self._buf, len(self._buf), ctypes.byref(n)))
+            for i in range(n.value):
+                r = self._buf[i]
+                res.append({"ticket": r.ticket, "status": r.status,
+                            "out": Tensor(None, ctypes.c_void_p(r.out)) if r.out else None,
+                            "latency_ms": r.latency_ms, "queue_ms": r.queue_ms, "batch_size": r.batch_size})
+            if n.value < len(self._buf):
+                return res
+
+    def drain(self):
+        _check(load_library().lco_server_drain(self.handle))
+
+    def destroy(self):
+        if self.handle:
+            _check(load_library().lco_server_destroy(self.handle))
+            self.handle = None
 
 
 def lco_batch_stats(ctx: Context):

@@ -473,6 +473,18 @@ lco_status lco_destroy(lco_tensor t) {
   LCO_CATCH
 }
 
+lco_status lco_read(lco_tensor t, uint64_t* livs, double* vals) {
+  LCO_TRY
+  if (!t) fail(LCO_E_ARG, "lco_read: tensor is NULL");
+  LCO_HIP(hipSetDevice(t->ctx->device));
+  LCO_HIP(hipStreamSynchronize(t->ctx->stream));
+  const size_t bytes = (size_t)t->nnz * 8;
+  if (bytes && livs) LCO_HIP(hipMemcpy(livs, t->livs, bytes, hipMemcpyDeviceToHost));
+  if (bytes && vals) LCO_HIP(hipMemcpy(vals, t->vals, bytes, hipMemcpyDeviceToHost));
+  return LCO_OK;
+  LCO_CATCH
+}
+
 int64_t lco_nnz(lco_tensor t) { return t ? t->nnz : -1; }
 int lco_order(lco_tensor t) { return t ? t->order : -1; }
 const uint64_t* lco_dims(lco_tensor t) { return t ? t->dims : nullptr; }
@@ -484,7 +496,7 @@ lco_status lco_permute(lco_ctx ctx, lco_tensor in, const int* perm, lco_tensor* 
   if (!out) fail(LCO_E_ARG, "lco_permute: out is NULL");
   *out = nullptr;
   if (!ctx || !in) fail(LCO_E_ARG, "lco_permute: ctx or tensor is NULL");
-  if (in->ctx != ctx) fail(LCO_E_ARG, "lco_permute: tensor belongs to another context");
+  if (in->ctx->device != ctx->device) fail(LCO_E_ARG, "lco_permute: tensor lives on another device");
   RpDetail plan = plan_permute(in->order, in->dims, perm, in->nnz, default_digit_cap());
   LCO_HIP(hipSetDevice(ctx->device));
   lco_tensor t = new_tensor(ctx, in->order, plan.new_dims, in->nnz);
@@ -505,7 +517,8 @@ lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tens
   if (!out) fail(LCO_E_ARG, "lco_contract: out is NULL");
   *out = nullptr;
   if (!ctx || !a || !b) fail(LCO_E_ARG, "lco_contract: ctx or tensor is NULL");
-  if (a->ctx != ctx || b->ctx != ctx) fail(LCO_E_ARG, "lco_contract: tensor belongs to another context");
+  if (a->ctx->device != ctx->device || b->ctx->device != ctx->device)
+    fail(LCO_E_ARG, "lco_contract: tensor lives on another device");
   ContractDetail d = plan_contract(a->order, a->dims, a_labels, a->nnz, b->order, b->dims, b_labels, b->nnz,
                                    c_order, c_labels, flags);
   LCO_HIP(hipSetDevice(ctx->device));

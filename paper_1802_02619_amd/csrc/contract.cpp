@@ -85,7 +85,8 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
     for (int i = 0; i < count; ++i) {
       const lco_contract_desc& x = descs[i];
       if (!x.a || !x.b) fail(LCO_E_ARG, "lco_contract_batch: tensor is NULL");
-      if (x.a->ctx != ctx || x.b->ctx != ctx) fail(LCO_E_ARG, "lco_contract_batch: tensor belongs to another context");
+      if (x.a->ctx->device != ctx->device || x.b->ctx->device != ctx->device)
+        fail(LCO_E_ARG, "lco_contract_batch: tensor lives on another device");
       plans[i] = plan_contract(x.a->order, x.a->dims, x.a_labels, x.a->nnz, x.b->order, x.b->dims, x.b_labels,
                                x.b->nnz, x.c_order, x.c_labels, x.flags);
     }

@@ -1,0 +1,288 @@
+// Request server: continuous batching of contractions over worker streams.
+//
+// Each worker thread owns a HIP stream (default priority) and a context that
+// allocates with stream-ordered hipMallocAsync.  A free worker takes every
+// pending request that fits the device-memory budget, in arrival order, and
+// runs them as one batched contraction; requests arriving meanwhile wait for
+// the next free worker, so the batches of different workers overlap on the
+// device.  A request's result does not depend on the batch it ran in: the
+// batched path computes every row with the same device code and summation
+// order as the per-call path.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+
+#include "lco_internal.h"
+
+namespace lco {
+lco_status set_error(const Error& e);
+lco_status set_error_msg(lco_status s, const char* msg);
+}  // namespace lco
+
+using namespace lco;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+  lco_tensor a = nullptr, b = nullptr;
+  std::vector<int> la, lb, lc;  // never empty, so .data() is valid for order-0 operands
+  int c_order = 0;
+  uint32_t flags = 0;
+  bool solo = false;
+  uint64_t est = 0;      // estimated device footprint (bytes)
+  uint64_t charged = 0;  // what was taken from the budget
+  Clock::time_point arrival, start;
+  lco_server_result res{};
+};
+
+// Device bytes a request may need beyond its resident operands: the product,
+// the multiplication datatype, and (for the outer product and the doubly
+// compressed path) the expanded product list with its sort buffers.
+uint64_t footprint(const ContractDetail& d, int64_t nnz_a, int64_t nnz_b, bool rowwise) {
+  const uint64_t nn = (uint64_t)(nnz_a + nnz_b);
+  return (rowwise ? 128ull : 512ull) * nn + (1ull << 20) + (d.pub.permute_a ? 32ull * nnz_a : 0) +
+         (d.pub.permute_b ? 32ull * nnz_b : 0);
+}
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+struct lco_server_s {
+  lco_server_config cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> pending, done;
+  uint64_t budget_left = 0;
+  int64_t next_ticket = 0;
+  int64_t outstanding = 0;  // submitted and not yet complete
+  bool stop = false;
+  std::vector<hipStream_t> streams;
+  std::vector<lco_ctx> ctxs;
+  std::vector<std::thread> threads;
+};
+
+namespace {
+
+// Called with the lock held: moves the next batch out of `pending`.
+bool take_batch(lco_server s, std::vector<Request*>& batch) {
+  const uint64_t total = s->cfg.hbm_budget;
+  for (auto it = s->pending.begin(); it != s->pending.end() && (int)batch.size() < s->cfg.max_batch;) {
+    Request* r = *it;
+    const bool idle = s->budget_left == total && batch.empty();
+    if ((r->est > s->budget_left && !idle) || (r->solo && !batch.empty())) {
+      ++it;
+      continue;
+    }
+    r->charged = std::min(r->est, s->budget_left);
+    s->budget_left -= r->charged;
+    batch.push_back(r);
+    it = s->pending.erase(it);
+    if (r->solo) break;
+  }
+  return !batch.empty();
+}
+
+void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
+  lco_ctx ctx = s->ctxs[w];
+  const int n = (int)batch.size();
+  std::vector<lco_tensor> outs(n, nullptr);
+  std::vector<lco_status> st(n, LCO_OK);
+  auto alone = [&](int i) {
+    Request* r = batch[i];
+    st[i] = lco_contract(ctx, r->a, r->la.data(), r->b, r->lb.data(), r->c_order, r->lc.data(), r->flags, &outs[i]);
+  };
+  if (s->cfg.plain) {
+    for (int i = 0; i < n; ++i) alone(i);
+  } else {
+    std::vector<lco_contract_desc> d(n);
+    for (int i = 0; i < n; ++i) {
+      Request* r = batch[i];
+      d[i] = {r->a, r->la.data(), r->b, r->lb.data(), r->c_order, r->lc.data(), r->flags};
+    }
+    if (lco_contract_batch(ctx, n, d.data(), outs.data()) != LCO_OK) {
+      // isolate the failure: every request gets its own outcome
+      for (int i = 0; i < n; ++i) alone(i);
+    }
+  }
+  (void)hipStreamSynchronize(s->streams[w]);
+  const Clock::time_point t_done = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int i = 0; i < n; ++i) {
+      Request* r = batch[i];
+      r->res.status = st[i];
+      r->res.out = st[i] == LCO_OK ? outs[i] : nullptr;
+      r->res.latency_ms = ms_between(r->arrival, t_done);
+      r->res.queue_ms = ms_between(r->arrival, r->start);
+      r->res.batch_size = n;
+      s->budget_left += r->charged;
+      s->done.push_back(r);
+      s->outstanding--;
+    }
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
+void worker_main(lco_server s, int w) {
+  (void)hipSetDevice(s->device);
+  std::vector<Request*> batch;
+  for (;;) {
+    batch.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return take_batch(s, batch) || (s->stop && s->pending.empty()); });
+      if (batch.empty()) return;
+    }
+    const Clock::time_point t_start = Clock::now();
+    for (Request* r : batch) r->start = t_start;
+    run_batch(s, w, batch);
+  }
+}
+
+void release(lco_server s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (std::thread& t : s->threads)
+    if (t.joinable()) t.join();
+  for (Request* r : s->done) {
+    if (r->res.out) lco_destroy(r->res.out);
+    delete r;
+  }
+  for (Request* r : s->pending) delete r;
+  for (lco_ctx c : s->ctxs) lco_ctx_destroy(c);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+lco_status lco_server_create(int device, const lco_server_config* cfg, lco_server* out) {
+  if (!out) return set_error_msg(LCO_E_ARG, "lco_server_create: out is NULL");
+  *out = nullptr;
+  if (!cfg || cfg->workers < 1 || cfg->workers > 64 || cfg->max_batch < 1 || (cfg->plain != 0 && cfg->plain != 1) ||
+      cfg->hbm_budget == 0)
+    return set_error_msg(LCO_E_ARG, "lco_server_create: bad configuration");
+  lco_server s = new lco_server_s;
+  s->cfg = *cfg;
+  if (s->cfg.plain) s->cfg.max_batch = 1;
+  s->device = device;
+  s->budget_left = cfg->hbm_budget;
+  try {
+    int count = 0;
+    LCO_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) fail(LCO_E_ARG, "lco_server_create: no such device");
+    LCO_HIP(hipSetDevice(device));
+    // keep freed blocks in the stream-ordered pool instead of returning them at every synchronisation
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t keep = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    for (int w = 0; w < cfg->workers; ++w) {
+      hipStream_t st;
+      LCO_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      s->streams.push_back(st);
+      lco_ctx c = nullptr;
+      const lco_status r = lco_ctx_create(device, st, nullptr, nullptr, nullptr, &c);
+      if (r != LCO_OK) fail(r, "lco_server_create: context creation failed");
+      s->ctxs.push_back(c);
+    }
+    for (int w = 0; w < cfg->workers; ++w) s->threads.emplace_back(worker_main, s, w);
+  } catch (const Error& e) {
+    release(s);
+    return set_error(e);
+  } catch (const std::exception& e) {
+    release(s);
+    return set_error_msg(LCO_E_HIP, e.what());
+  }
+  *out = s;
+  return LCO_OK;
+}
+
+lco_status lco_server_submit(lco_server s, const lco_contract_desc* d, int64_t* ticket) {
+  if (!s || !d || !ticket || !d->a || !d->b) return set_error_msg(LCO_E_ARG, "lco_server_submit: bad argument");
+  *ticket = -1;
+  try {
+    if (d->a->ctx->device != s->device || d->b->ctx->device != s->device)
+      fail(LCO_E_ARG, "lco_server_submit: operand lives on another device");
+    if (d->c_order < 0 || d->c_order > LCO_MAX_ORDER) fail(LCO_E_ARG, "lco_server_submit: bad output order");
+    // argument errors surface here, before the request is queued
+    const ContractDetail plan = plan_contract(d->a->order, d->a->dims, d->a_labels, d->a->nnz, d->b->order,
+                                              d->b->dims, d->b_labels, d->b->nnz, d->c_order, d->c_labels,
+                                              d->flags);
+    Request* r = new Request;
+    r->a = d->a;
+    r->b = d->b;
+    r->la.assign(d->a_labels, d->a_labels + d->a->order);
+    r->lb.assign(d->b_labels, d->b_labels + d->b->order);
+    r->lc.assign(d->c_labels, d->c_labels + d->c_order);
+    if (r->la.empty()) r->la.push_back(0);
+    if (r->lb.empty()) r->lb.push_back(0);
+    if (r->lc.empty()) r->lc.push_back(0);
+    r->c_order = d->c_order;
+    r->flags = d->flags;
+    const int algo = plan.pub.algo;
+    const bool rowwise = !plan.empty && (algo == LCO_ALG_CSR || algo == LCO_ALG_CSC || algo == LCO_ALG_CSRNA ||
+                                         algo == LCO_ALG_CSCNA);
+    const int64_t nn = d->a->nnz + d->b->nnz;
+    r->solo = !plan.empty && (!rowwise || (s->cfg.solo_nnz > 0 && nn > s->cfg.solo_nnz));
+    r->est = footprint(plan, d->a->nnz, d->b->nnz, rowwise || plan.empty);
+    r->arrival = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      r->res.ticket = s->next_ticket++;
+      *ticket = r->res.ticket;
+      s->pending.push_back(r);
+      s->outstanding++;
+    }
+    s->cv_work.notify_one();
+    return LCO_OK;
+  } catch (const Error& e) {
+    return set_error(e);
+  } catch (const std::exception& e) {
+    return set_error_msg(LCO_E_HIP, e.what());
+  }
+}
+
+lco_status lco_server_poll(lco_server s, lco_server_result* results, int cap, int* count) {
+  if (!s || !count || cap < 0 || (cap > 0 && !results)) return set_error_msg(LCO_E_ARG, "lco_server_poll: bad argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int n = 0;
+  while (n < cap && !s->done.empty()) {
+    Request* r = s->done.front();
+    s->done.pop_front();
+    results[n++] = r->res;
+    delete r;
+  }
+  *count = n;
+  return LCO_OK;
+}
+
+lco_status lco_server_drain(lco_server s) {
+  if (!s) return set_error_msg(LCO_E_ARG, "lco_server_drain: server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+  return LCO_OK;
+}
+
+lco_status lco_server_destroy(lco_server s) {
+  if (!s) return LCO_OK;
+  release(s);
+  return LCO_OK;
+}
+
+}  // extern "C"
