@@ -210,9 +210,10 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
     }
 
 
-def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
+def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: float):
     """Replay a Poisson request trace in real time against the continuous-batching server, then
-    the same trace against serial plain calls (one worker, one request at a time, FIFO)."""
+    the same trace against serial plain calls (one worker, one request at a time, FIFO).  With
+    `stress` > 1 the same trace is replayed once more with arrival times divided by `stress`."""
     t_arr, cls, param = L.serving_trace(seconds)
     n = len(t_arr)
     dev = torch.device("cuda", 0)
@@ -251,7 +252,7 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
         if k not in probe or param[i] < param[probe[k]]:
             probe[k] = i
 
-    def replay(server):
+    def replay(server, scale):
         lat = np.zeros(n)
         nnz = np.zeros(n, dtype=np.int64)
         bs = np.zeros(n, dtype=np.int64)
@@ -280,7 +281,7 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
 
         t0 = time.perf_counter()
         for i in range(n):
-            target = t0 + t_arr[i]
+            target = t0 + t_arr[i] / scale
             while True:
                 handle(server.poll())
                 now = time.perf_counter()
@@ -300,27 +301,33 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
                        "(side 16..96), 25% 3-D 7-point (side 64..128), 5% hyper-sparse Kronecker pairs "
                        "(2^L per mode, L 12..16, 2^(L+8) draws); operands resident in HBM",
            "requests": n}
-    for name, kw in (("served", dict(workers=workers, max_batch=256, plain=False)),
-                     ("serial_plain", dict(workers=1, max_batch=1, plain=True))):
-        srv = lco.Server(0, **kw)
-        try:
-            lat, nnz, bs, kept, bad, wall = replay(srv)
-        finally:
-            srv.destroy()
-        ok = lat > 0
-        per = {}
-        for c, cname in enumerate(("fd2", "fd3", "kron")):
-            m = ok & (cls == c)
-            if m.any():
-                per[cname] = {"n": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
-                              "p99_ms": float(np.percentile(lat[m], 99))}
-        out[name] = {"p50_ms": float(np.percentile(lat[ok], 50)), "p99_ms": float(np.percentile(lat[ok], 99)),
-                     "mean_ms": float(lat[ok].mean()), "req_per_s": float(ok.sum() / wall),
-                     "output_nnz_per_s": float(nnz[ok].sum() / wall), "wall_s": wall, "errors": len(bad),
-                     "mean_batch": float(bs[ok].mean()), "max_batch": int(bs[ok].max()), "per_class": per,
-                     "config": kw}
-        out[name + "_nnz"] = nnz
-        out[name + "_kept"] = kept
+
+    def run_modes(scale):
+        res = {}
+        for name, kw in (("served", dict(workers=workers, max_batch=256, plain=False)),
+                         ("serial_plain", dict(workers=1, max_batch=1, plain=True))):
+            srv = lco.Server(0, **kw)
+            try:
+                lat, nnz, bs, kept, bad, wall = replay(srv, scale)
+            finally:
+                srv.destroy()
+            ok = lat > 0
+            per = {}
+            for c, cname in enumerate(("fd2", "fd3", "kron")):
+                m = ok & (cls == c)
+                if m.any():
+                    per[cname] = {"n": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
+                                  "p99_ms": float(np.percentile(lat[m], 99))}
+            res[name] = {"p50_ms": float(np.percentile(lat[ok], 50)), "p99_ms": float(np.percentile(lat[ok], 99)),
+                         "mean_ms": float(lat[ok].mean()), "req_per_s": float(ok.sum() / wall),
+                         "output_nnz_per_s": float(nnz[ok].sum() / wall), "wall_s": wall, "errors": len(bad),
+                         "mean_batch": float(bs[ok].mean()), "max_batch": int(bs[ok].max()), "per_class": per,
+                         "config": kw}
+            res[name + "_nnz"] = nnz
+            res[name + "_kept"] = kept
+        return res
+
+    out.update(run_modes(1.0))
     # every request: identical output size in both modes; FD sizes equal the closed form
     same = bool(np.array_equal(out.pop("served_nnz"), out["serial_plain_nnz"]))
     fdn = out.pop("serial_plain_nnz")
@@ -335,6 +342,13 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int):
         for kept in (ks, kp):
             ident &= i in kept and np.array_equal(kept[i][1], la_) and \
                 np.array_equal(kept[i][2].view(np.uint64), va_.view(np.uint64))
+    if stress > 1:
+        st = run_modes(stress)
+        same &= bool(np.array_equal(st["served_nnz"], fdn)) and bool(np.array_equal(st["serial_plain_nnz"], fdn))
+        out[f"stress_x{stress:g}"] = {"offered_req_per_s": 200.0 * stress, "served": st["served"],
+                                      "serial_plain": st["serial_plain"],
+                                      "p99_speedup_served_vs_plain":
+                                          st["serial_plain"]["p99_ms"] / st["served"]["p99_ms"]}
     for t in pool.values():
         for x in (t if isinstance(t, tuple) else (t,)):
             x.destroy()
@@ -356,6 +370,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the replayed request trace (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-stress", type=float, default=4.0,
+                    help="also replay the trace this many times faster (<= 1: skip)")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -475,7 +491,8 @@ def main():
     if args.batch_count > 0:
         out["batched"] = batched_leg(lco, ctx, torch, np, L, args.batch_count, args.batch_reps)
     if args.serve_seconds > 0:
-        out["serving"] = serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers)
+        out["serving"] = serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers,
+                                     args.serve_stress)
     if not args.no_cpu_baseline:
         cb, (rows, c_sub) = cpu_baseline(coords, vals, nnz_c)
         # the sampled rows of the GPU result must equal the oracle's
