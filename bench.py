@@ -359,12 +359,117 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: fl
     return out
 
 
+def small_leg(lco, ctx, torch, np, L, reps: int):
+    """The 32x32 2-D FD operator (4,992 non-zeros): permutation (2,3,0,1) then the biharmonic
+    self-contraction; latency-bound, so per-call p50/p99 over many repetitions."""
+    c, v = L.fd_laplacian(32, 2)
+    idx_d = torch.from_numpy(c.view(np.int64).reshape(-1).copy()).to("cuda:0")
+    val_d = torch.from_numpy(v).to("cuda:0")
+    A = lco.lco_create(ctx, [32] * 4, idx_d, val_d, lco.LCO_COORDS)
+    la, lb, lc = fd_labels(2)
+    res = {}
+    for name in ("permute", "contract", "permute+contract"):
+        t = []
+        for k in range(reps + 20):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "permute":
+                P = lco.lco_permute(ctx, A, [2, 3, 0, 1])
+                ctx.synchronize()
+                P.destroy()
+            elif name == "contract":
+                C = lco.lco_contract(ctx, A, la, A, lb, lc)
+                ctx.synchronize()
+                n_out = C.nnz
+                C.destroy()
+            else:
+                P = lco.lco_permute(ctx, A, [2, 3, 0, 1])
+                C = lco.lco_contract(ctx, P, la, P, lb, lc)
+                ctx.synchronize()
+                C.destroy()
+                P.destroy()
+            if k >= 20:
+                t.append((time.perf_counter() - t0) * 1e6)
+        res[name] = {"p50_us": float(np.percentile(t, 50)), "p99_us": float(np.percentile(t, 99))}
+    A.destroy()
+    return {"workload": "2-D 5-point FD Laplacian 32x32 (4,992 nnz): permute (2,3,0,1); self-contraction "
+                        "over (2,3)x(0,1)", "nnz_out": n_out, "reps": reps, **res}
+
+
+def hyper_leg(lco, ctx, torch, np, L, reps: int):
+    """The order-4 hyper-sparse Kronecker pair (2^16 per mode, 2^24 draws each, duplicates summed),
+    contracted over (2,3)x(0,1): the outer-product (SOP) path with B permuted (2,3,0,1)."""
+    dev = torch.device("cuda", 0)
+    ops = []
+    for seed in (1, 2):
+        co, va = L.kronecker_hypersparse_torch(16, 1 << 24, seed, dev)
+        ops.append(lco.lco_create(ctx, [1 << 16] * 4, co.reshape(-1).contiguous(), va,
+                                  lco.LCO_COORDS | lco.LCO_SUM_DUPLICATES))
+        del co, va
+    A, B = ops
+    la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
+    plan = lco.lco_plan_info(ctx, A, la, B, lb, lc).as_dict()
+    C = lco.lco_contract(ctx, A, la, B, lb, lc)  # warm-up
+    C.destroy()
+    lco.lco_timing_reset(ctx)
+    lco.lco_timing_enable(ctx, True)
+    t = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C = lco.lco_contract(ctx, A, la, B, lb, lc)
+        ctx.synchronize()
+        t.append(time.perf_counter() - t0)
+        n_out = C.nnz
+        C.destroy()
+    lco.lco_timing_enable(ctx, False)
+    kernels = {}
+    for name in lco.lco_timing_kernels(ctx):
+        n_l, tot = lco.lco_timing_query(ctx, name)
+        if n_l:
+            kernels[name] = {"launches_per_rep": n_l / reps, "ms_per_rep": tot / reps}
+    lco.lco_timing_reset(ctx)
+    ms = statistics.median(t) * 1e3
+    # the same product through the doubly-compressed column path (no operand permute, no product sort)
+    ref = lco.lco_contract(ctx, A, la, B, lb, lc)
+    alt = {}
+    for name in ("DCSC", "DCSR"):
+        f = lco.ALGO_IDS[name]
+        C = lco.lco_contract(ctx, A, la, B, lb, lc, f)
+        C.destroy()
+        tt = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C = lco.lco_contract(ctx, A, la, B, lb, lc, f)
+            ctx.synchronize()
+            tt.append(time.perf_counter() - t0)
+            if len(tt) < reps:
+                C.destroy()
+        same = torch.equal(C.livs(), ref.livs()) and torch.equal(C.vals().view(torch.int64),
+                                                                  ref.vals().view(torch.int64))
+        C.destroy()
+        alt[name] = {"ms": statistics.median(tt) * 1e3, "bit_identical_to_selected": bool(same)}
+    ref.destroy()
+    out = {"workload": "hyper-sparse Kronecker pair, order 4, 2^16 per mode, 2^24 draws each (device generator, "
+                       "seeds 1/2), contracted over (2,3)x(0,1)",
+           "nnz_a": A.nnz, "nnz_b": B.nnz, "nnz_out": n_out, "algo": plan["algo_name"],
+           "permute_b": plan["permute_b"], "ms": ms, "output_nnz_per_s": n_out / (ms * 1e-3), "reps": reps,
+           "forced": alt,
+           "kernels": dict(sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_rep"])[:12])}
+    A.destroy()
+    B.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--small-reps", type=int, default=1000, help="repetitions of the 32x32 leg (0: skip)")
+    ap.add_argument("--hyper-reps", type=int, default=5, help="repetitions of the hyper-sparse leg (0: skip)")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -488,6 +593,10 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if args.small_reps > 0:
+        out["small"] = small_leg(lco, ctx, torch, np, L, args.small_reps)
+    if args.hyper_reps > 0:
+        out["hyper_sparse"] = hyper_leg(lco, ctx, torch, np, L, args.hyper_reps)
     if args.batch_count > 0:
         out["batched"] = batched_leg(lco, ctx, torch, np, L, args.batch_count, args.batch_reps)
     if args.serve_seconds > 0:

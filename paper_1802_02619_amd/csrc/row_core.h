@@ -158,13 +158,21 @@ struct RowSmem {
   uint32_t (*own)[kWave];
 };
 
-// The whole product of one small row of A' by one wave: symbolic (distinct
-// column count into *cnt_slot) or numeric (the sorted row written at out_base).
+// One lane's share of a small row's product: at most one output entry.
+struct RowOut {
+  bool own = false;   // this lane holds an output entry
+  uint32_t rank = 0;  // its position in the sorted row (numeric only)
+  uint64_t col = 0;   // its column of B'
+  double val = 0.0;   // its summed value (numeric only)
+};
+
+// The product of one small row of A' by one wave.  Returns the number of
+// distinct columns (the row's output count); when NUMERIC, `o` receives this
+// lane's output entry.
 template <bool ACC, bool NUMERIC>
-__device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                               bool narrow, int w, int lane, const RowSmem& sm,
-                                               uint64_t* cnt_slot, uint64_t out_base, uint64_t* __restrict__ out_livs,
-                                               double* __restrict__ out_vals) {
+__device__ __forceinline__ uint32_t small_row_compute(const RowArgs& ra, uint32_t e0, int t, uint64_t row,
+                                                      uint8_t sh, bool narrow, int w, int lane, const RowSmem& sm,
+                                                      RowOut& o) {
   bool valid;
   int ent;
   uint64_t col;
@@ -213,9 +221,8 @@ __device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, i
       }
     }
     const uint64_t newmask = __ballot(isnew);
-    if (!NUMERIC) {
-      if (lane == 0) *cnt_slot = (uint64_t)__popcll(newmask);
-    } else {
+    const uint32_t distinct = (uint32_t)__popcll(newmask);
+    if (NUMERIC) {
       // Accumulate in product order, one A' entry (one contracted index) at a
       // time: the products of one entry come from one row of B' and so have
       // distinct columns, hence distinct slots, and need no atomics.  Lanes of
@@ -242,17 +249,21 @@ __device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, i
       // the row's distinct columns is its position in the sorted row
       double mine = 0.0;
       if (isnew) mine = sm.acc[w][slot];
-      const int distinct = __popcll(newmask);
       uint32_t rank = 0;
       if (narrow && distinct <= 32) {
-        // owners' columns compacted into lanes [0, distinct), compared with
-        // scalar reads at fixed lane indices (no loop, no branches)
+        // owners' columns compacted into slots [0, distinct) of a 32-slot list
+        // padded with the largest column, then compared by every lane with
+        // broadcast 16-byte LDS reads (no loop, no branches)
         if (isnew) sm.own[w][__popcll(newmask & lanemask_lt())] = (uint32_t)col;
+        if (lane >= (int)distinct && lane < 32) sm.own[w][lane] = 0xFFFFFFFFu;
         wave_lds_sync();
-        const uint32_t oc = lane < distinct ? sm.own[w][lane] : 0xFFFFFFFFu;
         const uint32_t c32 = (uint32_t)col;
+        const uint4* ol = reinterpret_cast<const uint4*>(sm.own[w]);
 #pragma unroll
-        for (int b = 0; b < 32; ++b) rank += readlane_u32(oc, b) < c32 ? 1u : 0u;
+        for (int q = 0; q < 8; ++q) {
+          const uint4 x = ol[q];
+          rank += (x.x < c32 ? 1u : 0u) + (x.y < c32 ? 1u : 0u) + (x.z < c32 ? 1u : 0u) + (x.w < c32 ? 1u : 0u);
+        }
       } else {
         for (uint64_t mm = newmask; mm; mm &= mm - 1) {
           const int b = __builtin_ctzll(mm);
@@ -261,44 +272,59 @@ __device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, i
           rank += cb < col ? 1u : 0u;
         }
       }
-      if (isnew) {
-        const uint64_t o = out_base + rank;
-        out_livs[o] = col + ra.np * row;
-        out_vals[o] = mine;
-      }
+      o.own = isnew;
+      o.rank = rank;
+      o.col = col;
+      o.val = mine;
     }
     wave_lds_sync();
-  } else {
-    // no accumulator: sort (column, product index), then each run head sums
-    // its run (invalid lanes carry the largest key and sort last)
-    uint64_t key = col;
-    uint32_t idx = (uint32_t)lane;
-    double val = v;
-    wave_bitonic(key, idx, val);
-    const uint64_t prev = __shfl_up(key, 1, kWave);
-    const bool head = key != kEmpty && (lane == 0 || prev != key);
-    const uint64_t hmask = __ballot(head);
-    if (!NUMERIC) {
-      if (lane == 0) *cnt_slot = (uint64_t)__popcll(hmask);
-    } else {
-      double acc = 0.0;
-      bool active = head;
-      if (head) acc += val;
-      for (int s = 1; s < kWave; ++s) {
-        const uint64_t ks = __shfl_down(key, s, kWave);
-        const double vs = __shfl_down(val, s, kWave);
-        if (active) {
-          if (lane + s < kWave && ks == key) acc += vs;
-          else active = false;
-        }
-        if (!__any(active)) break;
+    return distinct;
+  }
+  // no accumulator: sort (column, product index), then each run head sums its
+  // run (invalid lanes carry the largest key and sort last)
+  uint64_t key = col;
+  uint32_t idx = (uint32_t)lane;
+  double val = v;
+  wave_bitonic(key, idx, val);
+  const uint64_t prev = __shfl_up(key, 1, kWave);
+  const bool head = key != kEmpty && (lane == 0 || prev != key);
+  const uint64_t hmask = __ballot(head);
+  if (NUMERIC) {
+    double acc = 0.0;
+    bool active = head;
+    if (head) acc += val;
+    for (int s = 1; s < kWave; ++s) {
+      const uint64_t ks = __shfl_down(key, s, kWave);
+      const double vs = __shfl_down(val, s, kWave);
+      if (active) {
+        if (lane + s < kWave && ks == key) acc += vs;
+        else active = false;
       }
-      if (head) {
-        const uint64_t o = out_base + (uint64_t)__popcll(hmask & lanemask_lt());
-        out_livs[o] = key + ra.np * row;
-        out_vals[o] = acc;
-      }
+      if (!__any(active)) break;
     }
+    o.own = head;
+    o.rank = (uint32_t)__popcll(hmask & lanemask_lt());
+    o.col = key;
+    o.val = acc;
+  }
+  return (uint32_t)__popcll(hmask);
+}
+
+// Symbolic (the row's output count into *cnt_slot) or numeric (the sorted row
+// written at out_base) product of one small row.
+template <bool ACC, bool NUMERIC>
+__device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                               bool narrow, int w, int lane, const RowSmem& sm,
+                                               uint64_t* cnt_slot, uint64_t out_base, uint64_t* __restrict__ out_livs,
+                                               double* __restrict__ out_vals) {
+  RowOut o;
+  const uint32_t d = small_row_compute<ACC, NUMERIC>(ra, e0, t, row, sh, narrow, w, lane, sm, o);
+  if (!NUMERIC) {
+    if (lane == 0) *cnt_slot = d;
+  } else if (o.own) {
+    const uint64_t p = out_base + o.rank;
+    out_livs[p] = o.col + ra.np * row;
+    out_vals[p] = o.val;
   }
 }
 
