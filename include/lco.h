@@ -216,6 +216,41 @@ lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* d
 /* How many instances of the last lco_contract_batch call ran batched / per call. */
 lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call);
 
+/* Planned batches.  lco_batch_plan_create does all the shape-dependent work of
+ * a batch once -- operand and output rearrangements (kept as value gathers),
+ * the multiplication datatypes, every row's shape and output offset -- and
+ * allocates and computes the outputs.  lco_batch_plan_execute then recomputes
+ * every output's values from the operands' current values: only numeric
+ * launches on the context's stream, no allocation, no host synchronisation, so
+ * it can be captured in a HIP graph; lco_batch_plan_graph_launch captures it
+ * once into a graph owned by the plan and replays that graph.  The operands'
+ * LIVs (sparsity patterns) must not change after planning; their values may.
+ *
+ * While planning, an autotuner picks for every group of instances of similar
+ * size (A' non-zeros within a factor of 4) the row-engine branch (accumulator
+ * or sort-based, both of which sum every output in the same order, so the
+ * result does not depend on the choice) and the launch width, by timing the
+ * candidates on the group itself; choices are kept in the context and reused.
+ *
+ * Only instances that the batched path runs completely (row-wise or
+ * column-wise singly compressed products whose rows have at most 64 products)
+ * can be planned; others give LCO_E_UNSUPPORTED.  The outputs belong to the
+ * plan (lco_batch_plan_output returns borrowed handles, valid until
+ * lco_batch_plan_destroy). */
+typedef struct lco_batch_plan_s* lco_batch_plan;
+lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_batch_plan* out);
+/* Borrowed handle of the i-th output (NULL if i is out of range). */
+lco_tensor lco_batch_plan_output(lco_batch_plan p, int i);
+lco_status lco_batch_plan_execute(lco_ctx ctx, lco_batch_plan p);
+lco_status lco_batch_plan_graph_launch(lco_ctx ctx, lco_batch_plan p);
+/* The i-th numeric launch of the plan: its size bucket (floor(log2(nnz of A'))/2),
+ * instances, chosen branch (LCO_ALG_CSR = accumulator, LCO_ALG_CSRNA =
+ * sort-based), blocks per compute unit, and the measured time of the choice
+ * (0 when it came from an earlier plan).  LCO_E_ARG past the last launch. */
+lco_status lco_batch_plan_launch_info(lco_batch_plan p, int i, int* bucket, int* instances, int* algo,
+                                      int* blocks_per_cu, double* ms);
+lco_status lco_batch_plan_destroy(lco_batch_plan p);
+
 /* ------------------------------------------------------------------ serving
  *
  * A request server for contractions (continuous batching).  Requests are

@@ -16,7 +16,7 @@ import threading
 __all__ = [
     "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
-    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
+    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read", "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
@@ -127,6 +127,13 @@ def load_library():
             "lco_create": (i32, [vp, i32, pu64, i64, vp, vp, u32, pvp]),
             "lco_destroy": (i32, [vp]),
             "lco_read": (i32, [vp, vp, vp]),
+            "lco_batch_plan_create": (i32, [vp, i32, ctypes.POINTER(ContractDesc), pvp]),
+            "lco_batch_plan_output": (vp, [vp, i32]),
+            "lco_batch_plan_execute": (i32, [vp, vp]),
+            "lco_batch_plan_graph_launch": (i32, [vp, vp]),
+            "lco_batch_plan_launch_info": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 4 +
+                                           [ctypes.POINTER(ctypes.c_double)]),
+            "lco_batch_plan_destroy": (i32, [vp]),
             "lco_server_create": (i32, [i32, ctypes.POINTER(ServerConfig), pvp]),
             "lco_server_submit": (i32, [vp, ctypes.POINTER(ContractDesc), ctypes.POINTER(i64)]),
             "lco_server_poll": (i32, [vp, ctypes.POINTER(ServerResult), i32, ctypes.POINTER(i32)]),
@@ -366,6 +373,71 @@ def lco_contract_batch(ctx: Context, items):
     outs = (ctypes.c_void_p * max(1, n))()
     _check(L.lco_contract_batch(ctx.handle, n, descs, outs))
     return [Tensor(ctx, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+class _Borrowed(Tensor):
+    """A tensor owned by something else (a batch plan): destroy() does nothing."""
+
+    def destroy(self):
+        self.handle = None
+
+
+def _descs(items):
+    keep = []
+    descs = (ContractDesc * max(1, len(items)))()
+    for i, it in enumerate(items):
+        a, la, b, lb, lc = it[:5]
+        flags = it[5] if len(it) > 5 else 0
+        arrs = (_i32arr(la), _i32arr(lb), _i32arr(lc))
+        keep.append(arrs)
+        descs[i] = ContractDesc(a.handle, arrs[0], b.handle, arrs[1], len(lc), arrs[2], int(flags))
+    return descs, keep
+
+
+class BatchPlan:
+    """lco_batch_plan_*: a batch planned once, re-executed (or replayed as a HIP graph) on demand.
+    `items` as for lco_contract_batch.  outputs() are owned by the plan."""
+
+    def __init__(self, ctx: Context, items):
+        L = load_library()
+        self.ctx = ctx
+        descs, self._keep = _descs(items)
+        h = ctypes.c_void_p()
+        _check(L.lco_batch_plan_create(ctx.handle, len(items), descs, ctypes.byref(h)))
+        self.handle = h
+        self.count = len(items)
+
+    def outputs(self):
+        L = load_library()
+        return [_Borrowed(self.ctx, ctypes.c_void_p(L.lco_batch_plan_output(self.handle, i)))
+                for i in range(self.count)]
+
+    def execute(self):
+        _check(load_library().lco_batch_plan_execute(self.ctx.handle, self.handle))
+
+    def graph_launch(self):
+        _check(load_library().lco_batch_plan_graph_launch(self.ctx.handle, self.handle))
+
+    def launches(self):
+        """Per numeric launch: size bucket, instances, branch, blocks per CU, tuned time (ms)."""
+        L = load_library()
+        out = []
+        i = 0
+        while True:
+            b, n, a, g = (ctypes.c_int() for _ in range(4))
+            ms = ctypes.c_double()
+            st = L.lco_batch_plan_launch_info(self.handle, i, ctypes.byref(b), ctypes.byref(n), ctypes.byref(a),
+                                              ctypes.byref(g), ctypes.byref(ms))
+            if st != 0:
+                return out
+            out.append({"bucket": b.value, "instances": n.value, "branch": ALGOS[a.value],
+                        "blocks_per_cu": g.value, "tuned_ms": ms.value})
+            i += 1
+
+    def destroy(self):
+        if self.handle:
+            _check(load_library().lco_batch_plan_destroy(self.handle))
+            self.handle = None
 
 
 class Server:

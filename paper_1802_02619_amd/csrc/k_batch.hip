@@ -11,6 +11,7 @@
 // (doubly compressed, outer product, long rows) run through the per-call path.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "row_core.h"
@@ -165,6 +166,17 @@ __global__ void bt_ranges_kernel(const BInst* __restrict__ in, int count, const 
   }
 }
 
+__global__ void gather_vals_kernel(const double* __restrict__ src, const uint64_t* __restrict__ idx, int64_t n,
+                                   double* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[idx[i]];
+}
+
+__global__ void iota_kernel(uint64_t* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint64_t)i;
+}
+
 int grid_for(lco_ctx ctx, int64_t n, int threads) {
   const int64_t want = (n + threads - 1) / threads;
   const int64_t cap = (int64_t)ctx->num_cus * 16;
@@ -175,7 +187,38 @@ int grid_for(lco_ctx ctx, int64_t n, int threads) {
 
 // Runs one group of jobs that share the accumulator choice; fills outs[job.index]
 // for every job it completes and returns the indices that must take the per-call path.
-std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs) {
+void gather_values(lco_ctx ctx, const double* src, const uint64_t* idx, int64_t n, double* dst) {
+  if (n > 0) LCO_LAUNCH(ctx, "gather_vals", gather_vals_kernel, grid_for(ctx, n, 256), 256, 0, src, idx, n, dst);
+}
+
+void fill_iota(lco_ctx ctx, uint64_t* out, int64_t n) {
+  if (n > 0) LCO_LAUNCH(ctx, "iota", iota_kernel, grid_for(ctx, n, 256), 256, 0, out, n);
+}
+
+void* KeptBuffers::raw(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = dev_alloc(ctx, bytes);
+  bufs.push_back({p, bytes});
+  return p;
+}
+
+void KeptBuffers::release() {
+  for (auto& b : bufs) dev_free(ctx, b.first, b.second);
+  bufs.clear();
+}
+
+void batch_numeric(lco_ctx ctx, const BatchLaunch& L) {
+  const BInst* in = static_cast<const BInst*>(L.inst);
+  if (L.acc)
+    LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<true, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
+               L.shape, L.fallback, L.poff, L.bstart, L.rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
+  else
+    LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<false, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
+               L.shape, L.fallback, L.poff, L.bstart, L.rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
+}
+
+std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs,
+                             KeptBuffers* keep, BatchLaunch* launch) {
   const int count = (int)jobs.size();
   std::vector<BInst> host(count);
   std::vector<int64_t> eoff(count + 1), boff(count + 1);
@@ -205,7 +248,8 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   boff[count] = BS;
   if (E > (int64_t)UINT32_MAX) fail(LCO_E_UNSUPPORTED, "batch: more than 2^32-1 entries");
   Scratch s(ctx);
-  BInst* d_in = s.get<BInst>(count);
+  auto kept = [&](auto* tag, size_t n) { using T = std::remove_pointer_t<decltype(tag)>; return keep ? keep->get<T>(n) : s.get<T>(n); };
+  BInst* d_in = kept((BInst*)nullptr, count);
   int64_t* d_eoff = s.get<int64_t>(count + 1);
   int64_t* d_boff = s.get<int64_t>(count + 1);
   LCO_HIP(hipMemcpyAsync(d_in, host.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, ctx->stream));
@@ -220,26 +264,26 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   memset_async(ctx, words, 0, 2 * sizeof(uint64_t));
   LCO_LAUNCH(ctx, "bt_heads", bt_heads_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, head);
   scan_u32(ctx, head, rpos, E, (uint32_t*)words);
-  uint32_t* rs = s.get<uint32_t>(E + 1);
-  uint64_t* rid = s.get<uint64_t>(E);
-  uint32_t* rinst = s.get<uint32_t>(E);
+  uint32_t* rs = kept((uint32_t*)nullptr, E + 1);
+  uint64_t* rid = kept((uint64_t*)nullptr, E);
+  uint32_t* rinst = kept((uint32_t*)nullptr, E);
   LCO_LAUNCH(ctx, "bt_compact", bt_compact_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, head, rpos,
              rs, rid, rinst);
   uint64_t* len = s.get<uint64_t>(E);
-  uint64_t* poff = s.get<uint64_t>(E + 1);
-  uint32_t* bstart = s.get<uint32_t>(E);
+  uint64_t* poff = kept((uint64_t*)nullptr, E + 1);
+  uint32_t* bstart = kept((uint32_t*)nullptr, E);
   LCO_LAUNCH(ctx, "bt_entry_len", bt_entry_len_kernel, grid_for(ctx, E, 256), 256, 0, d_in, d_eoff, count, E, bptr,
              len, bstart);
   scan_u64(ctx, len, poff, E, poff + E);
-  uint8_t* shape = s.get<uint8_t>(E);
-  uint32_t* fallback = s.get<uint32_t>(count);
+  uint8_t* shape = kept((uint8_t*)nullptr, E);
+  uint32_t* fallback = kept((uint32_t*)nullptr, count);
   memset_async(ctx, fallback, 0, sizeof(uint32_t) * count);
   LCO_LAUNCH(ctx, "bt_classify", bt_classify_kernel, grid_for(ctx, E, 256), 256, 0, rs, rinst, poff, words, E, shape,
              fallback);
   const uint64_t* rb[1] = {words};
   const uint64_t R = readback(ctx, rb, 1)[0] & 0xffffffffull;
   uint64_t* cnt = s.get<uint64_t>(R + 1);
-  uint64_t* coff = s.get<uint64_t>(R + 1);
+  uint64_t* coff = kept((uint64_t*)nullptr, R + 1);
   memset_async(ctx, cnt, 0, sizeof(uint64_t) * (R + 1));
   const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((R + kRowWaves - 1) / kRowWaves,
                                                                  (uint64_t)ctx->num_cus * 64));
@@ -268,12 +312,23 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   double* pv = (double*)((char*)pool->base + total * 8);
   std::vector<int> redo;
   try {
-    if (acc)
-      LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<true, true>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
-                 shape, fallback, poff, bstart, (uint32_t)R, (uint64_t*)nullptr, (const uint64_t*)coff, pl, pv);
-    else
-      LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<false, true>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
-                 shape, fallback, poff, bstart, (uint32_t)R, (uint64_t*)nullptr, (const uint64_t*)coff, pl, pv);
+    BatchLaunch L;
+    L.acc = acc;
+    L.grid = grid;
+    L.rows = (uint32_t)R;
+    L.inst = d_in;
+    L.rs = rs;
+    L.rid = rid;
+    L.rinst = rinst;
+    L.shape = shape;
+    L.fallback = fallback;
+    L.poff = poff;
+    L.bstart = bstart;
+    L.coff = coff;
+    L.out_livs = pl;
+    L.out_vals = pv;
+    batch_numeric(ctx, L);
+    if (launch) *launch = L;
     for (int i = 0; i < count; ++i) {
       if (hr[2 * i + 1]) {
         redo.push_back(jobs[i].index);

@@ -66,6 +66,8 @@ struct lco_ctx_s {
   lco::Timer timer;
   uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
   int64_t batch_stats[2] = {0, 0};  // last batch on this context: instances batched, run per call
+  // batch-plan autotuner: (size bucket, selected branch) -> (branch, blocks per CU)
+  std::map<int, std::pair<int, int>> tune;
 };
 
 namespace lco {

@@ -8,7 +8,6 @@
 namespace lco {
 namespace {
 
-constexpr int kRowWaves = 4;
 constexpr int kRowThreads = kRowWaves * kWave;
 constexpr uint64_t kEmpty = ~0ull;
 

@@ -52,12 +52,50 @@ struct BatchJob {
   int order_c;
   uint64_t natural_dims[LCO_MAX_ORDER];
 };
+// Rows in flight per workgroup of the one-wave-per-row kernels (one wave each).
+constexpr int kRowWaves = 4;
+
 // A batch runs in chunks of at most this many A' entries in total.
 constexpr int64_t kBatchChunkEntries = int64_t(1) << 26;
+
+// Device buffers that outlive one call (those of a batch plan), released together.
+struct KeptBuffers {
+  lco_ctx ctx = nullptr;
+  std::vector<std::pair<void*, size_t>> bufs;
+  void* raw(size_t bytes);
+  template <class T> T* get(size_t count) { return static_cast<T*>(raw(count * sizeof(T) + 1)); }
+  void release();
+};
+
+// Everything the numeric pass of one batch group reads and writes.
+struct BatchLaunch {
+  bool acc = true;
+  int grid = 1;
+  uint32_t rows = 0;
+  const void* inst = nullptr;  // device array of per-instance descriptors
+  const uint32_t* rs = nullptr;
+  const uint64_t* rid = nullptr;
+  const uint32_t* rinst = nullptr;
+  const uint8_t* shape = nullptr;
+  const uint32_t* fallback = nullptr;
+  const uint64_t* poff = nullptr;
+  const uint32_t* bstart = nullptr;
+  const uint64_t* coff = nullptr;
+  uint64_t* out_livs = nullptr;
+  double* out_vals = nullptr;
+};
+// dst[i] = src[idx[i]] for i < n, and out[i] = i (value-permutation helpers of batch plans).
+void gather_values(lco_ctx ctx, const double* src, const uint64_t* idx, int64_t n, double* dst);
+void fill_iota(lco_ctx ctx, uint64_t* out, int64_t n);
+// The numeric pass: every batched row recomputed from the operands' current values.
+void batch_numeric(lco_ctx ctx, const BatchLaunch& L);
+
 // Runs the jobs (all with or all without accumulator) as one batch; writes
 // outs[job.index] for each completed job and returns the indices that need the
-// per-call path.
-std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs);
+// per-call path.  With `keep`, the buffers the numeric pass reads stay
+// allocated in `keep` and `*launch` describes that pass, so it can be re-run.
+std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs,
+                             KeptBuffers* keep = nullptr, BatchLaunch* launch = nullptr);
 
 // Simple outer product (Section 5.2.5) of A (column-major) and B (row-major).
 lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, const ContractDetail& d);

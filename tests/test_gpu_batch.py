@@ -104,3 +104,71 @@ def test_batch_many_small_fd(lco_lib, gpu_ctx, oracle_mod):
         single = lco_lib.lco_contract(gpu_ctx, *items[k])
         a, b = np_of(outs[k]), np_of(single)
         assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def _planned_items(lco_lib, gpu_ctx, rng):
+    items, keep = [], []
+    for side, dim in ((7, 2), (12, 2), (29, 2), (5, 3), (10, 3)):
+        c, v = L.fd_laplacian(side, dim)
+        g = gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v)
+        keep.append(g)
+        items.append((g, list(range(2 * dim)), g, list(range(dim, 3 * dim)),
+                      list(range(dim)) + list(range(2 * dim, 3 * dim))))
+    # rows of at most 64 products (every instance of a plan runs batched)
+    ca, va = L.random_sparse(rng, [40, 12, 7], 200)
+    cb, vb = L.random_sparse(rng, [7, 12, 30], 200)
+    ga, gb = gpu_create(lco_lib, gpu_ctx, [40, 12, 7], ca, va), gpu_create(lco_lib, gpu_ctx, [7, 12, 30], cb, vb)
+    keep += [ga, gb]
+    # operand rearrangement, output rearrangement, forced sort-based branches
+    items += [(ga, [0, 1, 2], gb, [2, 1, 3], [0, 3]),
+              (ga, [0, 1, 2], gb, [2, 1, 3], [3, 0]),
+              (ga, [0, 1, 2], gb, [2, 1, 3], [0, 3], lco_lib.ALGO_IDS["CSRNA"]),
+              (ga, [0, 1, 2], gb, [2, 1, 3], [3, 0], lco_lib.ALGO_IDS["CSCNA"])]
+    return items, keep
+
+
+def _check_plan_outputs(lco_lib, gpu_ctx, plan, items):
+    for out, it in zip(plan.outputs(), items):
+        single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
+        a, b = np_of(out), np_of(single)
+        single.destroy()
+        assert a[0] == b[0]
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_batch_plan_execute_and_graph_replays(lco_lib, gpu_ctx):
+    """A planned batch equals per-call products; after the operands' values change in place,
+    execute() and every replay of the captured graph equal per-call products on the new values."""
+    rng = np.random.default_rng(99)
+    items, keep = _planned_items(lco_lib, gpu_ctx, rng)
+    plan = lco_lib.BatchPlan(gpu_ctx, items)
+    try:
+        info = plan.launches()
+        print("launches", info, flush=True)
+        assert info and all(x["branch"] in ("CSR", "CSRNA") for x in info)
+        _check_plan_outputs(lco_lib, gpu_ctx, plan, items)
+        for step, scale in enumerate((-1.5, 0.25, 3.0, -2.0)):
+            for t in keep:
+                t.vals().mul_(scale)
+            if step == 0:
+                plan.execute()
+            else:
+                plan.graph_launch()
+            gpu_ctx.synchronize()
+            _check_plan_outputs(lco_lib, gpu_ctx, plan, items)
+    finally:
+        plan.destroy()
+    for t in keep:
+        t.destroy()
+
+
+def test_batch_plan_rejects_outer_product(lco_lib, gpu_ctx):
+    ops = []
+    for seed in (1, 2):
+        c, v = L.kronecker_hypersparse(5, 1 << 9, seed)
+        ops.append(gpu_create(lco_lib, gpu_ctx, [32] * 4, c, v, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES))
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.BatchPlan(gpu_ctx, [(ops[0], [0, 1, 2, 3], ops[1], [2, 3, 4, 5], [0, 1, 4, 5])])
+    assert e.value.code == 7
+    for t in ops:
+        t.destroy()
