@@ -19,11 +19,15 @@ namespace lco {
 
 namespace {
 
-constexpr int kRxWaves = 4;
+constexpr int kRxWaves = 16;
 constexpr int kRxThreads = kRxWaves * kWave;
-constexpr int kRxItems = 16;
+constexpr int kRxItems = 4;
 constexpr int kRxTile = kRxThreads * kRxItems;  // 4096
 constexpr int kRxBins = 256;                    // digits of at most 8 bits
+// the digit-count kernel covers the same 4096-element tiles with fewer, longer waves
+constexpr int kCntWaves = 4;
+constexpr int kCntThreads = kCntWaves * kWave;
+constexpr int kCntItems = kRxTile / kCntThreads;
 
 constexpr int kLdsWaves = 8;
 constexpr int kLdsThreads = kLdsWaves * kWave;
@@ -89,23 +93,23 @@ __device__ __forceinline__ void block_rank(const uint32_t (&dg)[ITEMS], uint32_t
 // ---------------------------------------------------------------- global passes
 
 template <bool SHUF>
-__global__ __launch_bounds__(kRxThreads) void rx_count_kernel(const uint64_t* __restrict__ livs, int64_t n,
+__global__ __launch_bounds__(kCntThreads) void rx_count_kernel(const uint64_t* __restrict__ livs, int64_t n,
                                                               ShuffleParams sp, KeyParams kp, int shift,
                                                               uint32_t mask, uint32_t* __restrict__ counts,
                                                               int64_t num_tiles) {
-  __shared__ uint32_t hist[kRxWaves][kRxBins];
-  for (int i = threadIdx.x; i < kRxWaves * kRxBins; i += kRxThreads) (&hist[0][0])[i] = 0;
+  __shared__ uint32_t hist[kCntWaves][kRxBins];
+  for (int i = threadIdx.x; i < kCntWaves * kRxBins; i += kCntThreads) (&hist[0][0])[i] = 0;
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const int64_t base = (int64_t)blockIdx.x * kRxTile + (int64_t)wave * kRxItems * kWave + lane;
-  uint64_t x[kRxItems];
+  const int64_t base = (int64_t)blockIdx.x * kRxTile + (int64_t)wave * kCntItems * kWave + lane;
+  uint64_t x[kCntItems];
 #pragma unroll
-  for (int it = 0; it < kRxItems; ++it) {
+  for (int it = 0; it < kCntItems; ++it) {
     const int64_t e = base + it * kWave;
     x[it] = e < n ? livs[e] : 0;
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kRxItems; ++it) {
+  for (int it = 0; it < kCntItems; ++it) {
     const int64_t e = base + it * kWave;
     if (e < n) {
       uint64_t v = x[it];
@@ -115,10 +119,10 @@ __global__ __launch_bounds__(kRxThreads) void rx_count_kernel(const uint64_t* __
     }
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d <= mask; d += kRxThreads) {
+  for (uint32_t d = threadIdx.x; d <= mask; d += kCntThreads) {
     uint32_t s = 0;
 #pragma unroll
-    for (int w = 0; w < kRxWaves; ++w) s += hist[w][d];
+    for (int w = 0; w < kCntWaves; ++w) s += hist[w][d];
     counts[(int64_t)d * num_tiles + blockIdx.x] = s;
   }
 }
@@ -132,8 +136,7 @@ __global__ __launch_bounds__(kRxThreads) void rx_scatter_kernel(
   __shared__ uint32_t dstart[kRxBins];
   __shared__ uint32_t gbase[kRxBins];
   __shared__ uint32_t wsum[kRxWaves + 1];
-  __shared__ uint64_t s_liv[kRxTile];
-  __shared__ double s_val[kRxTile];
+  __shared__ uint64_t s_buf[kRxTile];  // the tile in digit order: LIVs, then values
   __shared__ uint8_t s_dig[kRxTile];
   const uint32_t mask = (1u << dbits) - 1u;
   const int wave = threadIdx.x / kWave, lane = lane_id();
@@ -142,16 +145,10 @@ __global__ __launch_bounds__(kRxThreads) void rx_scatter_kernel(
   for (uint32_t d = threadIdx.x; d <= mask; d += kRxThreads) gbase[d] = offsets[(int64_t)d * num_tiles + blockIdx.x];
   uint64_t lv[kRxItems];
   double vv[kRxItems];
+  const uint64_t* lp = livs + base;
+  const double* vp = vals + base;
 #pragma unroll
-  for (int it = 0; it < kRxItems; ++it) {
-    const int64_t e = base + it * kWave;
-    lv[it] = e < n ? livs[e] : 0;
-  }
-#pragma unroll
-  for (int it = 0; it < kRxItems; ++it) {
-    const int64_t e = base + it * kWave;
-    vv[it] = e < n ? vals[e] : 0.0;
-  }
+  for (int it = 0; it < kRxItems; ++it) lv[it] = base + it * kWave < n ? lp[it * kWave] : 0;
   uint32_t dg[kRxItems], pos[kRxItems];
 #pragma unroll
   for (int it = 0; it < kRxItems; ++it) {
@@ -159,20 +156,31 @@ __global__ __launch_bounds__(kRxThreads) void rx_scatter_kernel(
     if (SHUF) lv[it] = shuffle_liv(sp, lv[it]);
     dg[it] = e < n ? digit_of(fd_div(kp.key_div, lv[it]) - kp.key_base, shift, mask) : mask;
   }
+  // the values are needed only after the LIVs are written: their loads overlap the ranking
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) vv[it] = base + it * kWave < n ? vp[it * kWave] : 0.0;
   block_rank<kRxWaves, kRxItems>(dg, pos, dbits, cnt, dstart, wsum);
+  // LIVs and then values pass through one LDS buffer (half the LDS of staging
+  // both at once, so more workgroups fit on a compute unit); each is written
+  // out in digit runs, consecutive lanes to consecutive addresses
 #pragma unroll
   for (int it = 0; it < kRxItems; ++it) {
-    s_liv[pos[it]] = lv[it];
-    s_val[pos[it]] = vv[it];
+    s_buf[pos[it]] = lv[it];
     s_dig[pos[it]] = (uint8_t)dg[it];
   }
   __syncthreads();
   const int valid = (int)((n - tile0) < kRxTile ? (n - tile0) : kRxTile);
   for (int i = threadIdx.x; i < valid; i += kRxThreads) {
     const uint32_t d = s_dig[i];
-    const uint64_t dst = (uint64_t)gbase[d] + (uint32_t)(i - (int)dstart[d]);
-    out_livs[dst] = s_liv[i];
-    out_vals[dst] = s_val[i];
+    out_livs[(uint64_t)gbase[d] + (uint32_t)(i - (int)dstart[d])] = s_buf[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kRxItems; ++it) s_buf[pos[it]] = (uint64_t)__double_as_longlong(vv[it]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < valid; i += kRxThreads) {
+    const uint32_t d = s_dig[i];
+    out_vals[(uint64_t)gbase[d] + (uint32_t)(i - (int)dstart[d])] = __longlong_as_double((long long)s_buf[i]);
   }
 }
 
@@ -418,13 +426,13 @@ void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_val
     double* dv = to_out ? out_vals : tv;
     const int shift = p * dbits;
     if (p == 0 && shuffle) {
-      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<true>, num_tiles, kRxThreads, 0, src_l, n, sp, key, shift,
+      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<true>, num_tiles, kCntThreads, 0, src_l, n, sp, key, shift,
                  bins - 1, counts, num_tiles);
       scan_u32(ctx, counts, offs, (int64_t)bins * num_tiles, nullptr);
       LCO_LAUNCH(ctx, "rx_scatter", rx_scatter_kernel<true>, num_tiles, kRxThreads, 0, src_l, src_v, n, sp, key,
                  shift, dbits, offs, num_tiles, dl, dv);
     } else {
-      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<false>, num_tiles, kRxThreads, 0, src_l, n, sp, key, shift,
+      LCO_LAUNCH(ctx, "rx_count", rx_count_kernel<false>, num_tiles, kCntThreads, 0, src_l, n, sp, key, shift,
                  bins - 1, counts, num_tiles);
       scan_u32(ctx, counts, offs, (int64_t)bins * num_tiles, nullptr);
       LCO_LAUNCH(ctx, "rx_scatter", rx_scatter_kernel<false>, num_tiles, kRxThreads, 0, src_l, src_v, n, sp, key,

@@ -130,10 +130,84 @@ __global__ void list_scatter_kernel(const uint32_t* __restrict__ is2, const uint
     if (is2[r]) list2[q2[r]] = (uint32_t)r;
 }
 
-// ---------------------------------------------------------------- one wave per row
+// ---------------------------------------------------------------- one wave per row, rows in chunks
+//
+// Each wave takes chunks of 64 consecutive rows.  The chunk's row metadata
+// (starts, ids, shapes, output offsets) and a window of 64 consecutive A'
+// entries (product counts, B' row starts, LIVs, values) are read with one
+// coalesced load per array; a row then takes its entries' data from the window
+// by lane shuffles, so the only global loads that depend on the row are those
+// of its rows of B'.  The window moves forward when a row's entries leave it
+// (rows are consecutive, so their entries are too).
+constexpr int kChunkRows = kWave;
 
-template <bool DENSE, bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, uint32_t nzr,
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
+  return ((uint64_t)readlane_u32((uint32_t)(x >> 32), l) << 32) | readlane_u32((uint32_t)x, l);
+}
+
+template <bool NUMERIC>
+__device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                                int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_liv,
+                                                double x_av, bool& valid, int& ent, uint64_t& col, double& v) {
+  valid = false;
+  ent = 0;
+  col = kEmpty;
+  v = 0.0;
+  const int first = (int)((int64_t)e0 - w0);  // window lane of the row's first entry
+  if (sh != kShapeSearch) {
+    // entry-major lanes: lane = entry * W + position
+    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
+    const int src = (first + e) & (kWave - 1);
+    const uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
+    const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
+    const uint64_t al = __shfl(x_liv, src, kWave);
+    const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+    if (e < t && (uint32_t)k < len) {
+      const uint32_t q = bs + (uint32_t)k;
+      valid = true;
+      ent = e;
+      col = ra.b_livs[q] - ra.np * (al - ra.kp * row);
+      if (NUMERIC) v = av * ra.b_vals[q];
+    }
+    return;
+  }
+  // general small row: lane p takes product p, found by a binary search over the
+  // entries' inclusive product counts
+  const int src = (first + lane) & (kWave - 1);
+  uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
+  const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
+  const uint64_t al = __shfl(x_liv, src, kWave);
+  const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+  if (lane >= t) len = 0;
+  const uint32_t incl = wave_inclusive_scan(len);
+  const uint32_t rel = incl - len;
+  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
+  const uint32_t p = (uint32_t)lane;
+  int lo = 0, hi = t - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
+    if (lo < hi) {
+      if (x > p) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
+  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
+  const uint64_t al_e = __shfl(al, lo, kWave);
+  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
+  if (p < f) {
+    const uint32_t q = bs_e + (p - excl_e);
+    valid = true;
+    ent = lo;
+    col = ra.b_livs[q] - ra.np * (al_e - ra.kp * row);
+    if (NUMERIC) v = av_e * ra.b_vals[q];
+  }
+}
+
+template <bool ACC, bool NUMERIC>
+__global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint32_t nzr,
                                                                 const uint8_t* __restrict__ shape,
                                                                 uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
@@ -145,17 +219,61 @@ __global__ __launch_bounds__(kRowThreads) void row_small_kernel(RowArgs ra, uint
   __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
   const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const bool narrow = ra.np < (1ull << 32);  // columns fit 32 bits below the padding key
-  const RowSpan sp = xcd_row_span(nzr, w);
-  for (uint64_t r = sp.first; r < sp.end; r += sp.step) {
-    const uint8_t sh = shape[r];
-    if (sh == kShapeSkip) continue;
-    const uint32_t e0 = ra.row_start[r];
-    small_row_body<ACC, NUMERIC>(ra, e0, (int)(ra.row_start[r + 1] - e0), ra.row_id[r], sh, narrow, w, lane, sm,
-                                 NUMERIC ? nullptr : cnt + r, NUMERIC ? coff[r] : 0, out_livs, out_vals);
+  const bool narrow = ra.np < (1ull << 32);
+  const uint64_t nchunks = ((uint64_t)nzr + kChunkRows - 1) / kChunkRows;
+  const RowSpan span = xcd_row_span(nchunks, w);
+  for (uint64_t c = span.first; c < span.end; c += span.step) {
+    const uint64_t r0 = c * kChunkRows;
+    const int rows = (int)((uint64_t)nzr - r0 < (uint64_t)kChunkRows ? (uint64_t)nzr - r0 : (uint64_t)kChunkRows);
+    uint32_t m_s0 = 0, m_s1 = 0, m_sh = kShapeSkip;
+    uint64_t m_id = 0, m_off = 0;
+    if (lane < rows) {
+      const uint64_t r = r0 + lane;
+      m_s0 = ra.row_start[r];
+      m_s1 = ra.row_start[r + 1];
+      m_id = ra.row_id[r];
+      m_sh = shape[r];
+      if (NUMERIC) m_off = coff[r];
+    }
+    uint32_t my_cnt = 0;
+    int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+    uint32_t x_len = 0, x_bs = 0;
+    uint64_t x_liv = 0;
+    double x_av = 0.0;
+    for (int i = 0; i < rows; ++i) {
+      const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
+      if (sh == kShapeSkip) continue;
+      const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
+      const uint64_t row = readlane_u64(m_id, i);
+      const int t = (int)(e1 - e0);
+      if ((int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
+        w0 = e0;
+        const int64_t e = w0 + lane;
+        if (e < ra.nnz_a) {
+          x_len = (uint32_t)ra.elen[e];
+          x_bs = ra.bstart[e];
+          x_liv = ra.a_livs[e];
+          if (NUMERIC) x_av = ra.a_vals[e];
+        }
+      }
+      bool valid;
+      int ent;
+      uint64_t col;
+      double v;
+      window_products<NUMERIC>(ra, e0, t, row, sh, lane, w0, x_len, x_bs, x_liv, x_av, valid, ent, col, v);
+      RowOut o;
+      const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
+      if (!NUMERIC) {
+        if (lane == i) my_cnt = d;
+      } else if (o.own) {
+        const uint64_t pos = readlane_u64(m_off, i) + o.rank;
+        out_livs[pos] = o.col + ra.np * row;
+        out_vals[pos] = o.val;
+      }
+    }
+    if (!NUMERIC && lane < rows) cnt[r0 + lane] = my_cnt;
   }
 }
-
 
 // ---------------------------------------------------------------- long rows (global sort)
 
@@ -293,6 +411,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
   else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
   ra.bstart = bstart;
+  ra.elen = len;
   scan_u64(ctx, len, poff, na, poff + na);
   ra.poff = poff;
   // flag long rows (they keep row order), count them and place their products
@@ -316,16 +435,15 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
   uint64_t* coff = s.get<uint64_t>(nzr + 1);
   memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));
-  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + kRowWaves - 1) / kRowWaves,
-                                                                       (uint64_t)ctx->num_cus * 64));
-#define LCO_ROW_SMALL(NUM, ...)                                                                                 \
-  do {                                                                                                          \
-    if (dense && acc) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<true, true, NUM>), \
-                                 small_grid, kRowThreads, 0, __VA_ARGS__);                                      \
-    else if (dense) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<true, false, NUM>), \
-                               small_grid, kRowThreads, 0, __VA_ARGS__);                                        \
-    else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_small_kernel<false, true, NUM>),          \
-                    small_grid, kRowThreads, 0, __VA_ARGS__);                                                   \
+  const uint64_t nchunks = (nzr + kChunkRows - 1) / kChunkRows;
+  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nchunks + kRowWaves - 1) / kRowWaves,
+                                                                       (uint64_t)ctx->num_cus * 16));
+#define LCO_ROW_SMALL(NUM, ...)                                                                                  \
+  do {                                                                                                           \
+    if (acc) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<true, NUM>), small_grid,  \
+                        kRowThreads, 0, __VA_ARGS__);                                                            \
+    else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM>), small_grid,     \
+                    kRowThreads, 0, __VA_ARGS__);                                                                \
   } while (0)
   LCO_ROW_SMALL(false, ra, (uint32_t)nzr, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
   // long rows: expand, sort by (row rank, column), count distinct

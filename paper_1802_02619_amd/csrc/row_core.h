@@ -168,15 +168,11 @@ struct RowOut {
 // The product of one small row of A' by one wave.  Returns the number of
 // distinct columns (the row's output count); when NUMERIC, `o` receives this
 // lane's output entry.
+// The reduction of one small row's products (one per lane: `valid`, its A'
+// entry `ent` in the row, column `col`, value `v`) into the row's output.
 template <bool ACC, bool NUMERIC>
-__device__ __forceinline__ uint32_t small_row_compute(const RowArgs& ra, uint32_t e0, int t, uint64_t row,
-                                                      uint8_t sh, bool narrow, int w, int lane, const RowSmem& sm,
-                                                      RowOut& o) {
-  bool valid;
-  int ent;
-  uint64_t col;
-  double v;
-  gather_products<NUMERIC>(ra, e0, t, row, sh, lane, valid, ent, col, v);
+__device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col, double v, int t, bool narrow, int w,
+                                               int lane, const RowSmem& sm, RowOut& o) {
   if (ACC) {
     // sparse accumulator: an LDS hash table maps a column to a slot (32-bit
     // keys when the columns allow), and one FP64 accumulator per slot
@@ -307,6 +303,18 @@ __device__ __forceinline__ uint32_t small_row_compute(const RowArgs& ra, uint32_
     o.val = acc;
   }
   return (uint32_t)__popcll(hmask);
+}
+
+template <bool ACC, bool NUMERIC>
+__device__ __forceinline__ uint32_t small_row_compute(const RowArgs& ra, uint32_t e0, int t, uint64_t row,
+                                                      uint8_t sh, bool narrow, int w, int lane, const RowSmem& sm,
+                                                      RowOut& o) {
+  bool valid;
+  int ent;
+  uint64_t col;
+  double v;
+  gather_products<NUMERIC>(ra, e0, t, row, sh, lane, valid, ent, col, v);
+  return row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
 }
 
 // Symbolic (the row's output count into *cnt_slot) or numeric (the sorted row
