@@ -130,9 +130,10 @@ __global__ __launch_bounds__(kRowThreads) void bt_small_kernel(
     const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs, double* __restrict__ out_vals) {
   __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
   __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
-  __shared__ double s_acc[kRowWaves][3 * kWave];
+  __shared__ double s_vals[kRowWaves][kWave + 8];
+  __shared__ uint64_t s_lanes[kRowWaves][2 * kWave];
   __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
-  const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
+  const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
   const RowSpan sp = xcd_row_span(nrows, w);
   for (uint64_t r = sp.first; r < sp.end; r += sp.step) {

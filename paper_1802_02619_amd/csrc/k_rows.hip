@@ -147,7 +147,7 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
 
 template <bool NUMERIC>
 __device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                                int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_liv,
+                                                int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_jn,
                                                 double x_av, bool& valid, int& ent, uint64_t& col, double& v) {
   valid = false;
   ent = 0;
@@ -160,13 +160,13 @@ __device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, 
     const int src = (first + e) & (kWave - 1);
     const uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
     const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
-    const uint64_t al = __shfl(x_liv, src, kWave);
+    const uint64_t jn = __shfl(x_jn, src, kWave);
     const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
     if (e < t && (uint32_t)k < len) {
       const uint32_t q = bs + (uint32_t)k;
       valid = true;
       ent = e;
-      col = ra.b_livs[q] - ra.np * (al - ra.kp * row);
+      col = ra.b_livs[q] - (NUMERIC ? ra.np * (jn - ra.kp * row) : jn);
       if (NUMERIC) v = av * ra.b_vals[q];
     }
     return;
@@ -176,7 +176,7 @@ __device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, 
   const int src = (first + lane) & (kWave - 1);
   uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
   const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
-  const uint64_t al = __shfl(x_liv, src, kWave);
+  const uint64_t jn = __shfl(x_jn, src, kWave);
   const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
   if (lane >= t) len = 0;
   const uint32_t incl = wave_inclusive_scan(len);
@@ -195,13 +195,13 @@ __device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, 
   }
   const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
   const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
-  const uint64_t al_e = __shfl(al, lo, kWave);
+  const uint64_t jn_e = __shfl(jn, lo, kWave);
   const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
   if (p < f) {
     const uint32_t q = bs_e + (p - excl_e);
     valid = true;
     ent = lo;
-    col = ra.b_livs[q] - ra.np * (al_e - ra.kp * row);
+    col = ra.b_livs[q] - (NUMERIC ? ra.np * (jn_e - ra.kp * row) : jn_e);
     if (NUMERIC) v = av_e * ra.b_vals[q];
   }
 }
@@ -215,9 +215,10 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
                                                                 double* __restrict__ out_vals) {
   __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
   __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
-  __shared__ double s_acc[kRowWaves][3 * kWave];
+  __shared__ double s_vals[kRowWaves][kWave + 8];
+  __shared__ uint64_t s_lanes[kRowWaves][2 * kWave];
   __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
-  const RowSmem sm{s_hash, s_hash32, s_acc, s_own};
+  const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
   const bool narrow = ra.np < (1ull << 32);
   const uint64_t nchunks = ((uint64_t)nzr + kChunkRows - 1) / kChunkRows;
@@ -237,8 +238,11 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
     }
     uint32_t my_cnt = 0;
     int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+    // window lane l: entry w0 + l's product count, B' row start, value, and its
+    // LIV (numeric pass) or j * n' (symbolic pass: the LIV of its B' row's first
+    // position, j = its contracted index)
     uint32_t x_len = 0, x_bs = 0;
-    uint64_t x_liv = 0;
+    uint64_t x_jn = 0;
     double x_av = 0.0;
     for (int i = 0; i < rows; ++i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
@@ -252,7 +256,13 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
         if (e < ra.nnz_a) {
           x_len = (uint32_t)ra.elen[e];
           x_bs = ra.bstart[e];
-          x_liv = ra.a_livs[e];
+          if (NUMERIC) {
+            x_jn = ra.a_livs[e];  // (measured faster to keep the LIV in the numeric pass)
+          } else {
+            uint64_t j;
+            fd_divmod(ra.kdiv, ra.a_livs[e], j);
+            x_jn = j * ra.np;
+          }
           if (NUMERIC) x_av = ra.a_vals[e];
         }
       }
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
       int ent;
       uint64_t col;
       double v;
-      window_products<NUMERIC>(ra, e0, t, row, sh, lane, w0, x_len, x_bs, x_liv, x_av, valid, ent, col, v);
+      window_products<NUMERIC>(ra, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, valid, ent, col, v);
       RowOut o;
       const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
       if (!NUMERIC) {

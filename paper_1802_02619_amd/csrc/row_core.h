@@ -71,6 +71,9 @@ __device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, doubl
 __device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
   return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
 }
+__device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
+  return (c * 0x9E3779B1u) >> 25;  // 7 bits, for columns below 2^32
+}
 
 // Per-row shape codes of the one-wave kernel.
 constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
@@ -153,7 +156,8 @@ __device__ __forceinline__ void gather_products(const RowArgs& ra, uint32_t e0, 
 struct RowSmem {
   uint64_t (*hash)[2 * kWave];
   uint32_t (*hash32)[2 * kWave];
-  double (*acc)[3 * kWave];  // 128 slots + one dummy per lane
+  double (*vals)[kWave + 8];      // each lane's product value, and a zero at index kWave
+  uint64_t (*lanes)[2 * kWave];   // per hash slot: the lanes whose product has that column
   uint32_t (*own)[kWave];
 };
 
@@ -184,8 +188,9 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
       sm.hash[w][lane + kWave] = kEmpty;
     }
     if (NUMERIC) {
-      sm.acc[w][lane] = 0.0;
-      sm.acc[w][lane + kWave] = 0.0;
+      sm.lanes[w][lane] = 0;
+      sm.lanes[w][lane + kWave] = 0;
+      if (lane == 0) sm.vals[w][kWave] = 0.0;
     }
     wave_lds_sync();
     uint32_t slot = valid ? hash_slot(col) : 0;
@@ -218,32 +223,30 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     const uint64_t newmask = __ballot(isnew);
     const uint32_t distinct = (uint32_t)__popcll(newmask);
     if (NUMERIC) {
-      // Accumulate in product order, one A' entry (one contracted index) at a
-      // time: the products of one entry come from one row of B' and so have
-      // distinct columns, hence distinct slots, and need no atomics.  Lanes of
-      // other entries update a private dummy slot, so the loop has no branches.
-      // (LDS operations of one wave complete in order, so iteration e+1 reads
-      // what iteration e wrote.)
-      const int dummy = 2 * kWave + lane;
-      if (t <= 8) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int a = (valid && ent == e) ? (int)slot : dummy;
-          sm.acc[w][a] += v;
-          __builtin_amdgcn_wave_barrier();
-        }
-      } else {
-        for (int e = 0; e < t; ++e) {
-          const int a = (valid && ent == e) ? (int)slot : dummy;
-          sm.acc[w][a] += v;
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
+      // Every product records its lane in its column's slot and stages its value
+      // by lane.  The owner of a column (the lane that inserted it, i.e. its
+      // first product) then sums the column's products in ascending lane order,
+      // which is ascending A' entry (contracted index) order, starting from 0.0:
+      // the values are read eight at a time (absent ones read the staged zero,
+      // and adding +0.0 to a sum that started at +0.0 changes nothing), so the
+      // reads of a group are independent and overlap.
+      if (valid) atomicOr((unsigned long long*)&sm.lanes[w][slot], 1ull << lane);
+      sm.vals[w][lane] = v;
       wave_lds_sync();
-      // the lane that inserted a column owns that output entry; its rank among
-      // the row's distinct columns is its position in the sorted row
       double mine = 0.0;
-      if (isnew) mine = sm.acc[w][slot];
+      uint64_t m = isnew ? sm.lanes[w][slot] : 0ull;
+      const int groups = (t + 7) >> 3;  // a column has at most one product per entry
+      for (int g = 0; g < groups; ++g) {
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int l = m ? __builtin_ctzll(m) : kWave;
+          m &= m - 1;
+          x[k] = sm.vals[w][l];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mine += x[k];
+      }
       uint32_t rank = 0;
       if (narrow && distinct <= 32) {
         // owners' columns compacted into slots [0, distinct) of a 32-slot list
