@@ -93,41 +93,33 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_
   }
 }
 
-// Flags the long rows of A' (is2, f2) and writes the shape code of every row;
-// the rows keep their natural order.
-__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ f2,
-                                    uint32_t* __restrict__ is2, uint8_t* __restrict__ shape) {
+// Writes the shape code of every row and collects the long rows (more than 64
+// products or entries) in `list2` with their product counts `f2` (list order is
+// arbitrary; each long row's result depends only on its own products).
+__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ n2, uint32_t* __restrict__ list2,
+                                    uint64_t* __restrict__ f2, uint8_t* __restrict__ shape) {
   const uint64_t nzr = *ra.nzr_a;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t f = 0;
-    uint32_t big = 0;
-    uint8_t sh = kShapeSkip;
-    if ((uint64_t)r < nzr) {
-      const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
-      f = ra.poff[e1] - ra.poff[e0];
-      if (f > 0 && small_row(f, e1 - e0)) {
-        uint64_t mx = 0;
-        for (uint32_t e = e0; e < e1; ++e) {
-          const uint64_t l = ra.poff[e + 1] - ra.poff[e];
-          mx = l > mx ? l : mx;
-        }
-        uint32_t lw = 0;
-        while ((1ull << lw) < mx) ++lw;
-        sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
-      } else if (f > 0) {
-        big = 1;
-      }
+    if ((uint64_t)r >= nzr) break;
+    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+    uint64_t f = 0, mx = 0;
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint64_t l = ra.elen[e];
+      f += l;
+      mx = l > mx ? l : mx;
     }
-    is2[r] = big;
-    f2[r] = big ? f : 0;
+    uint8_t sh = kShapeSkip;
+    if (f > 0 && small_row(f, e1 - e0)) {
+      uint32_t lw = 0;
+      while ((1ull << lw) < mx) ++lw;
+      sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
+    } else if (f > 0) {
+      const uint64_t i = atomicAdd((unsigned long long*)n2, 1ull);
+      list2[i] = (uint32_t)r;
+      f2[i] = f;
+    }
     shape[r] = sh;
   }
-}
-
-__global__ void list_scatter_kernel(const uint32_t* __restrict__ is2, const uint32_t* __restrict__ q2, int64_t n,
-                                    uint32_t* __restrict__ list2) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    if (is2[r]) list2[q2[r]] = (uint32_t)r;
 }
 
 // ---------------------------------------------------------------- one wave per row, rows in chunks
@@ -289,11 +281,12 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
 
 constexpr int kBigThreads = 256;
 
+// Long row number li (list[li]) expands its products at off2[li], keyed by
+// (li, column); the key's list position keeps every row's products together.
 template <bool DENSE>
 __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, const uint32_t* __restrict__ list,
                                                                  uint32_t count, const uint64_t* __restrict__ off2,
-                                                                 const uint32_t* __restrict__ q2, int colbits,
-                                                                 uint64_t* __restrict__ keys,
+                                                                 int colbits, uint64_t* __restrict__ keys,
                                                                  double* __restrict__ vals) {
   for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
     const uint32_t r = list[li];
@@ -301,8 +294,8 @@ __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, con
     const uint64_t p0 = ra.poff[e0];
     const uint64_t f = ra.poff[e1] - p0;
     const uint64_t row = ra.row_id[r];
-    const uint64_t qk = (uint64_t)q2[r] << colbits;
-    const uint64_t base = off2[r];
+    const uint64_t qk = (uint64_t)li << colbits;
+    const uint64_t base = off2[li];
     for (uint64_t p = threadIdx.x; p < f; p += kBigThreads) {
       // last A' entry e in [e0, e1) with poff[e] <= p0 + p
       uint32_t lo = e0, hi = e1 - 1;
@@ -335,8 +328,8 @@ __global__ __launch_bounds__(kBigThreads) void big_reduce_kernel(RowArgs ra, con
   __shared__ uint32_t wsum[kBigThreads / kWave + 1];
   for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
     const uint32_t r = list[li];
-    const uint64_t f = ra.poff[ra.row_start[r + 1]] - ra.poff[ra.row_start[r]];
-    const uint64_t base = off2[r];
+    const uint64_t f = off2[li + 1] - off2[li];
+    const uint64_t base = off2[li];
     const uint64_t row = ra.row_id[r];
     uint64_t run = 0;  // heads seen before this chunk
     for (uint64_t c0 = 0; c0 < f; c0 += kBigThreads) {
@@ -422,25 +415,28 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
   ra.bstart = bstart;
   ra.elen = len;
-  scan_u64(ctx, len, poff, na, poff + na);
-  ra.poff = poff;
-  // flag long rows (they keep row order), count them and place their products
+  // row shapes; long rows collected with their product counts
+  uint64_t* n2_dev = s.get<uint64_t>(1);
   uint32_t* list2 = s.get<uint32_t>(na);
-  uint64_t* counters = s.get<uint64_t>(2);
   uint64_t* f2 = s.get<uint64_t>(na);
-  uint32_t* is2 = s.get<uint32_t>(na);
-  uint64_t* off2 = s.get<uint64_t>(na + 1);
-  uint32_t* q2 = s.get<uint32_t>(na);
-  memset_async(ctx, counters, 0, 2 * sizeof(uint64_t));
+  memset_async(ctx, n2_dev, 0, sizeof(uint64_t));
   uint8_t* shape = s.get<uint8_t>(na);
-  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, f2, is2, shape);
-  scan_u64(ctx, f2, off2, na, counters);
-  scan_u32(ctx, is2, q2, na, (uint32_t*)(counters + 1));
-  const uint64_t* rb1[3] = {arows.count, counters + 1, counters};
-  const uint64_t* h = readback(ctx, rb1, 3);
-  const uint64_t nzr = h[0], n2 = h[1], f2_total = h[2];
-  if (n2) LCO_LAUNCH(ctx, "list_scatter", list_scatter_kernel, grid_for(ctx, nzr, 256), 256, 0, is2, q2, (int64_t)nzr,
-                     list2);
+  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, n2_dev, list2, f2,
+             shape);
+  const uint64_t* rb1[2] = {arows.count, n2_dev};
+  const uint64_t* h = readback(ctx, rb1, 2);
+  const uint64_t nzr = h[0], n2 = h[1];
+  uint64_t f2_total = 0;
+  uint64_t* off2 = nullptr;
+  if (n2) {
+    // the long-row path locates products through the entries' product offsets
+    scan_u64(ctx, len, poff, na, poff + na);
+    ra.poff = poff;
+    off2 = s.get<uint64_t>(n2 + 1);
+    scan_u64(ctx, f2, off2, (int64_t)n2, off2 + n2);
+    const uint64_t* rb[1] = {off2 + n2};
+    f2_total = readback(ctx, rb, 1)[0];
+  }
   // per-row output counts
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
   uint64_t* coff = s.get<uint64_t>(nzr + 1);
@@ -472,10 +468,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     pvals = s.get<double>(f2_total);
     if (dense)
       LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2, off2,
-                 q2, colbits, ek, ev);
+                 colbits, ek, ev);
     else
       LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
-                 off2, q2, colbits, ek, ev);
+                 off2, colbits, ek, ev);
     KeyParams kparams;
     radix_sort_pairs(ctx, ek, ev, keys, pvals, (int64_t)f2_total, nullptr, kparams, colbits + qbits, 0);
     LCO_LAUNCH(ctx, "big_reduce_sym", big_reduce_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
