@@ -298,8 +298,11 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: fl
             if r["out"] is not None:
                 r["out"].destroy()
 
+        received = [0]
+
         def handle(results):
             for r in results:
+                received[0] += 1
                 i = r["ticket"] - base
                 if r["status"] != 0 or r["out"] is None:
                     bad.append(i)
@@ -321,8 +324,11 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: fl
                     break
                 time.sleep(min(target - now, 2e-4))
             server.submit(*request(i))
-        server.drain()
-        handle(server.poll())
+        # drain while consuming results (completed outputs are the caller's memory)
+        while received[0] < n:
+            handle(server.poll())
+            if received[0] < n:
+                time.sleep(2e-4)
         wall = time.perf_counter() - t0
         for i, t in list(kept.items()):
             kept[i] = t.to_numpy()

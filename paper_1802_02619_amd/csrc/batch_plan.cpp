@@ -91,8 +91,7 @@ void tune_launch(lco_ctx ctx, BatchLaunch& L, int bucket, LaunchInfo& info) {
   auto it = ctx->tune.find(key);
   if (it != ctx->tune.end()) {
     L.acc = it->second.first != 0;
-    L.grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((L.rows + kRowWaves - 1) / kRowWaves,
-                                                           (uint64_t)ctx->num_cus * it->second.second));
+    L.grid = batch_grid(ctx, L.rows, L.chunk_rows, it->second.second);
     info.ms = 0.0;
   } else {
     const bool timer_was_on = ctx->timer.on;
@@ -100,11 +99,10 @@ void tune_launch(lco_ctx ctx, BatchLaunch& L, int bucket, LaunchInfo& info) {
     double best = 1e30;
     int best_acc = L.acc, best_bpc = 0;
     for (int acc = 1; acc >= 0; --acc) {
-      for (int bpc : {8, 32, 128}) {
+      for (int bpc : {4, 8, 16}) {
         BatchLaunch c = L;
         c.acc = acc != 0;
-        c.grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((L.rows + kRowWaves - 1) / kRowWaves,
-                                                               (uint64_t)ctx->num_cus * bpc));
+        c.grid = batch_grid(ctx, L.rows, L.chunk_rows, bpc);
         const double ms = time_launch(ctx, c);
         if (ms < best) {
           best = ms;
@@ -116,8 +114,7 @@ void tune_launch(lco_ctx ctx, BatchLaunch& L, int bucket, LaunchInfo& info) {
     ctx->timer.on = timer_was_on;
     ctx->tune[key] = {best_acc, best_bpc};
     L.acc = best_acc != 0;
-    L.grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((L.rows + kRowWaves - 1) / kRowWaves,
-                                                           (uint64_t)ctx->num_cus * best_bpc));
+    L.grid = batch_grid(ctx, L.rows, L.chunk_rows, best_bpc);
     info.ms = best;
   }
   info.algo = L.acc ? LCO_ALG_CSR : LCO_ALG_CSRNA;

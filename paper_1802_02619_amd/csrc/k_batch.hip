@@ -122,12 +122,18 @@ __global__ void bt_classify_kernel(const uint32_t* __restrict__ rs, const uint32
   }
 }
 
+// The batched rows in chunks of consecutive rows per wave, with the chunk's row
+// metadata and a window of 64 consecutive entries loaded coalesced (the rows'
+// products are then gathered by lane shuffles, as in the per-call engine).  A
+// window holds entries of one instance only; a row of another instance, or
+// entries outside the window, move it.
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void bt_small_kernel(
+__global__ __launch_bounds__(kRowThreads) void bt_chunk_kernel(
     const BInst* __restrict__ in, const uint32_t* __restrict__ rs, const uint64_t* __restrict__ rid,
     const uint32_t* __restrict__ rinst, const uint8_t* __restrict__ shape, const uint32_t* __restrict__ fallback,
-    const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, uint64_t* __restrict__ cnt,
-    const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs, double* __restrict__ out_vals) {
+    const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, int chunk_rows,
+    uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs,
+    double* __restrict__ out_vals) {
   __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
   __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
   __shared__ double s_vals[kRowWaves][kWave + 8];
@@ -135,25 +141,71 @@ __global__ __launch_bounds__(kRowThreads) void bt_small_kernel(
   __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
   const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const RowSpan sp = xcd_row_span(nrows, w);
-  for (uint64_t r = sp.first; r < sp.end; r += sp.step) {
-    const uint8_t sh = shape[r];
-    const uint32_t i = rinst[r];
-    if (sh == kShapeSkip || fallback[i]) continue;
-    const BInst& x = in[i];
-    RowArgs ra;
-    ra.a_livs = x.a_livs;
-    ra.a_vals = x.a_vals;
-    ra.a_base = x.eoff;
-    ra.b_livs = x.b_livs;
-    ra.b_vals = x.b_vals;
-    ra.kp = x.kp;
-    ra.np = x.np;
-    ra.poff = poff;
-    ra.bstart = bstart;
-    const uint32_t e0 = rs[r];
-    small_row_body<ACC, NUMERIC>(ra, e0, (int)(rs[r + 1] - e0), rid[r], sh, x.np < (1ull << 32), w, lane, sm,
-                                 NUMERIC ? nullptr : cnt + r, NUMERIC ? coff[r] : 0, out_livs, out_vals);
+  const uint64_t nchunks = ((uint64_t)nrows + chunk_rows - 1) / chunk_rows;
+  const RowSpan span = xcd_row_span(nchunks, w);
+  for (uint64_t c = span.first; c < span.end; c += span.step) {
+    const uint64_t r0 = c * chunk_rows;
+    const int rows = (int)((uint64_t)nrows - r0 < (uint64_t)chunk_rows ? (uint64_t)nrows - r0 : (uint64_t)chunk_rows);
+    uint32_t m_s0 = 0, m_s1 = 0, m_sh = kShapeSkip, m_in = 0;
+    uint64_t m_id = 0, m_off = 0;
+    if (lane < rows) {
+      const uint64_t r = r0 + lane;
+      m_s0 = rs[r];
+      m_s1 = rs[r + 1];
+      m_id = rid[r];
+      m_in = rinst[r];
+      m_sh = fallback[m_in] ? kShapeSkip : shape[r];
+      if (NUMERIC) m_off = coff[r];
+    }
+    uint32_t my_cnt = 0;
+    int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+    uint32_t w_inst = 0xFFFFFFFFu;
+    uint32_t x_len = 0, x_bs = 0;
+    uint64_t x_jn = 0;
+    double x_av = 0.0;
+    for (int i = 0; i < rows; ++i) {
+      const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
+      if (sh == kShapeSkip) continue;
+      const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
+      const uint32_t xi = readlane_u32(m_in, i);
+      const uint64_t row = readlane_u64(m_id, i);
+      const BInst& x = in[xi];
+      const int t = (int)(e1 - e0);
+      if (xi != w_inst || (int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
+        w0 = e0;
+        w_inst = xi;
+        const int64_t g = w0 + lane;
+        if (g < x.eoff + x.nnz_a) {
+          x_len = (uint32_t)(poff[g + 1] - poff[g]);
+          x_bs = bstart[g];
+          const uint64_t liv = x.a_livs[g - x.eoff];
+          if (NUMERIC) {
+            x_jn = liv;
+            x_av = x.a_vals[g - x.eoff];
+          } else {
+            uint64_t j;
+            fd_divmod(x.kdiv, liv, j);
+            x_jn = j * x.np;
+          }
+        }
+      }
+      bool valid;
+      int ent;
+      uint64_t col;
+      double v;
+      window_products<NUMERIC>(x.b_livs, x.b_vals, x.np, x.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av,
+                               valid, ent, col, v);
+      RowOut o;
+      const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, x.np < (1ull << 32), w, lane, sm, o);
+      if (!NUMERIC) {
+        if (lane == i) my_cnt = d;
+      } else if (o.own) {
+        const uint64_t pos = readlane_u64(m_off, i) + o.rank;
+        out_livs[pos] = o.col + x.np * row;
+        out_vals[pos] = o.val;
+      }
+    }
+    if (!NUMERIC && lane < rows) cnt[r0 + lane] = my_cnt;
   }
 }
 
@@ -208,14 +260,26 @@ void KeptBuffers::release() {
   bufs.clear();
 }
 
+int batch_chunk_rows(lco_ctx ctx, uint64_t rows) {
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(kWave, rows / ((uint64_t)ctx->num_cus * 32)));
+}
+
+int batch_grid(lco_ctx ctx, uint64_t rows, int chunk_rows, int blocks_per_cu) {
+  const uint64_t chunks = (rows + chunk_rows - 1) / chunk_rows;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>((chunks + kRowWaves - 1) / kRowWaves,
+                                                       (uint64_t)ctx->num_cus * blocks_per_cu));
+}
+
 void batch_numeric(lco_ctx ctx, const BatchLaunch& L) {
   const BInst* in = static_cast<const BInst*>(L.inst);
   if (L.acc)
-    LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<true, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
-               L.shape, L.fallback, L.poff, L.bstart, L.rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
+    LCO_LAUNCH(ctx, "bt_small_num", (bt_chunk_kernel<true, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
+               L.shape, L.fallback, L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs,
+               L.out_vals);
   else
-    LCO_LAUNCH(ctx, "bt_small_num", (bt_small_kernel<false, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
-               L.shape, L.fallback, L.poff, L.bstart, L.rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
+    LCO_LAUNCH(ctx, "bt_small_num", (bt_chunk_kernel<false, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
+               L.shape, L.fallback, L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs,
+               L.out_vals);
 }
 
 std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs,
@@ -286,16 +350,16 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   uint64_t* cnt = s.get<uint64_t>(R + 1);
   uint64_t* coff = kept((uint64_t*)nullptr, R + 1);
   memset_async(ctx, cnt, 0, sizeof(uint64_t) * (R + 1));
-  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((R + kRowWaves - 1) / kRowWaves,
-                                                                 (uint64_t)ctx->num_cus * 64));
+  const int chunk_rows = batch_chunk_rows(ctx, R);
+  const int grid = batch_grid(ctx, R, chunk_rows, 16);
   if (acc)
-    LCO_LAUNCH(ctx, "bt_small_sym", (bt_small_kernel<true, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
-               fallback, poff, bstart, (uint32_t)R, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+    LCO_LAUNCH(ctx, "bt_small_sym", (bt_chunk_kernel<true, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
+               fallback, poff, bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                (double*)nullptr);
   else
-    LCO_LAUNCH(ctx, "bt_small_sym", (bt_small_kernel<false, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
-               fallback, poff, bstart, (uint32_t)R, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-               (double*)nullptr);
+    LCO_LAUNCH(ctx, "bt_small_sym", (bt_chunk_kernel<false, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
+               shape, fallback, poff, bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr,
+               (uint64_t*)nullptr, (double*)nullptr);
   scan_u64(ctx, cnt, coff, R, coff + R);
   uint64_t* ranges = s.get<uint64_t>(2 * count);
   LCO_LAUNCH(ctx, "bt_ranges", bt_ranges_kernel, grid_for(ctx, count, 256), 256, 0, d_in, count, rpos, coff, fallback,
@@ -316,6 +380,7 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
     BatchLaunch L;
     L.acc = acc;
     L.grid = grid;
+    L.chunk_rows = chunk_rows;
     L.rows = (uint32_t)R;
     L.inst = d_in;
     L.rs = rs;

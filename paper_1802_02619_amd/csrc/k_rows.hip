@@ -124,7 +124,8 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restr
 
 // ---------------------------------------------------------------- one wave per row, rows in chunks
 //
-// Each wave takes chunks of 64 consecutive rows.  The chunk's row metadata
+// Each wave takes chunks of up to 64 consecutive rows (fewer when there are too
+// few rows to give every resident wave a full chunk).  The chunk's row metadata
 // (starts, ids, shapes, output offsets) and a window of 64 consecutive A'
 // entries (product counts, B' row starts, LIVs, values) are read with one
 // coalesced load per array; a row then takes its entries' data from the window
@@ -133,73 +134,8 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restr
 // (rows are consecutive, so their entries are too).
 constexpr int kChunkRows = kWave;
 
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
-  return ((uint64_t)readlane_u32((uint32_t)(x >> 32), l) << 32) | readlane_u32((uint32_t)x, l);
-}
-
-template <bool NUMERIC>
-__device__ __forceinline__ void window_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                                int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_jn,
-                                                double x_av, bool& valid, int& ent, uint64_t& col, double& v) {
-  valid = false;
-  ent = 0;
-  col = kEmpty;
-  v = 0.0;
-  const int first = (int)((int64_t)e0 - w0);  // window lane of the row's first entry
-  if (sh != kShapeSearch) {
-    // entry-major lanes: lane = entry * W + position
-    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
-    const int src = (first + e) & (kWave - 1);
-    const uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
-    const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
-    const uint64_t jn = __shfl(x_jn, src, kWave);
-    const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
-    if (e < t && (uint32_t)k < len) {
-      const uint32_t q = bs + (uint32_t)k;
-      valid = true;
-      ent = e;
-      col = ra.b_livs[q] - (NUMERIC ? ra.np * (jn - ra.kp * row) : jn);
-      if (NUMERIC) v = av * ra.b_vals[q];
-    }
-    return;
-  }
-  // general small row: lane p takes product p, found by a binary search over the
-  // entries' inclusive product counts
-  const int src = (first + lane) & (kWave - 1);
-  uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
-  const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
-  const uint64_t jn = __shfl(x_jn, src, kWave);
-  const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
-  if (lane >= t) len = 0;
-  const uint32_t incl = wave_inclusive_scan(len);
-  const uint32_t rel = incl - len;
-  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
-  const uint32_t p = (uint32_t)lane;
-  int lo = 0, hi = t - 1;
-#pragma unroll
-  for (int it = 0; it < 6; ++it) {
-    const int mid = (lo + hi) >> 1;
-    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
-    if (lo < hi) {
-      if (x > p) hi = mid;
-      else lo = mid + 1;
-    }
-  }
-  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
-  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
-  const uint64_t jn_e = __shfl(jn, lo, kWave);
-  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
-  if (p < f) {
-    const uint32_t q = bs_e + (p - excl_e);
-    valid = true;
-    ent = lo;
-    col = ra.b_livs[q] - (NUMERIC ? ra.np * (jn_e - ra.kp * row) : jn_e);
-    if (NUMERIC) v = av_e * ra.b_vals[q];
-  }
-}
-
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint32_t nzr,
+__global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
                                                                 const uint8_t* __restrict__ shape,
                                                                 uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
@@ -213,11 +149,11 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
   const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
   const int w = threadIdx.x / kWave, lane = lane_id();
   const bool narrow = ra.np < (1ull << 32);
-  const uint64_t nchunks = ((uint64_t)nzr + kChunkRows - 1) / kChunkRows;
+  const uint64_t nchunks = ((uint64_t)nzr + chunk_rows - 1) / chunk_rows;
   const RowSpan span = xcd_row_span(nchunks, w);
   for (uint64_t c = span.first; c < span.end; c += span.step) {
-    const uint64_t r0 = c * kChunkRows;
-    const int rows = (int)((uint64_t)nzr - r0 < (uint64_t)kChunkRows ? (uint64_t)nzr - r0 : (uint64_t)kChunkRows);
+    const uint64_t r0 = c * chunk_rows;
+    const int rows = (int)((uint64_t)nzr - r0 < (uint64_t)chunk_rows ? (uint64_t)nzr - r0 : (uint64_t)chunk_rows);
     uint32_t m_s0 = 0, m_s1 = 0, m_sh = kShapeSkip;
     uint64_t m_id = 0, m_off = 0;
     if (lane < rows) {
@@ -262,7 +198,8 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
       int ent;
       uint64_t col;
       double v;
-      window_products<NUMERIC>(ra, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, valid, ent, col, v);
+      window_products<NUMERIC>(ra.b_livs, ra.b_vals, ra.np, ra.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av,
+                               valid, ent, col, v);
       RowOut o;
       const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
       if (!NUMERIC) {
@@ -441,7 +378,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
   uint64_t* coff = s.get<uint64_t>(nzr + 1);
   memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));
-  const uint64_t nchunks = (nzr + kChunkRows - 1) / kChunkRows;
+  // rows per chunk: up to 64, but enough chunks for every resident wave (32 per compute unit)
+  const uint64_t resident = (uint64_t)ctx->num_cus * 32;
+  const int chunk_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>(kChunkRows, nzr / resident));
+  const uint64_t nchunks = (nzr + chunk_rows - 1) / chunk_rows;
   const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nchunks + kRowWaves - 1) / kRowWaves,
                                                                        (uint64_t)ctx->num_cus * 16));
 #define LCO_ROW_SMALL(NUM, ...)                                                                                  \
@@ -451,7 +391,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM>), small_grid,     \
                     kRowThreads, 0, __VA_ARGS__);                                                                \
   } while (0)
-  LCO_ROW_SMALL(false, ra, (uint32_t)nzr, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
+  LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
   // long rows: expand, sort by (row rank, column), count distinct
   uint64_t* keys = nullptr;
   double* pvals = nullptr;
@@ -484,7 +424,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   if (nnz_c > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "contract: more than 2^32-1 output entries");
   lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
   try {
-    LCO_ROW_SMALL(true, ra, (uint32_t)nzr, (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    LCO_ROW_SMALL(true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
     if (n2)
       LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
                  off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,

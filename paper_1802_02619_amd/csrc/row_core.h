@@ -161,6 +161,77 @@ struct RowSmem {
   uint32_t (*own)[kWave];
 };
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
+  return ((uint64_t)readlane_u32((uint32_t)(x >> 32), l) << 32) | readlane_u32((uint32_t)x, l);
+}
+
+// The products of one small row from the entry window (lane l holds entry w0 + l:
+// its product count, B' row start, value, and its A' LIV (numeric pass) or
+// j * n' (symbolic pass: the LIV of its B' row's first position)); each lane
+// ends up with at most one product, as in gather_products.
+template <bool NUMERIC>
+__device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
+                                                uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row,
+                                                uint8_t sh, int lane, int64_t w0, uint32_t x_len, uint32_t x_bs,
+                                                uint64_t x_jn, double x_av, bool& valid, int& ent, uint64_t& col,
+                                                double& v) {
+  valid = false;
+  ent = 0;
+  col = kEmpty;
+  v = 0.0;
+  const int first = (int)((int64_t)e0 - w0);  // window lane of the row's first entry
+  if (sh != kShapeSearch) {
+    // entry-major lanes: lane = entry * W + position
+    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
+    const int src = (first + e) & (kWave - 1);
+    const uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
+    const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
+    const uint64_t jn = __shfl(x_jn, src, kWave);
+    const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+    if (e < t && (uint32_t)k < len) {
+      const uint32_t q = bs + (uint32_t)k;
+      valid = true;
+      ent = e;
+      col = b_livs[q] - (NUMERIC ? np * (jn - kp * row) : jn);
+      if (NUMERIC) v = av * b_vals[q];
+    }
+    return;
+  }
+  // general small row: lane p takes product p, found by a binary search over the
+  // entries' inclusive product counts
+  const int src = (first + lane) & (kWave - 1);
+  uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
+  const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
+  const uint64_t jn = __shfl(x_jn, src, kWave);
+  const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+  if (lane >= t) len = 0;
+  const uint32_t incl = wave_inclusive_scan(len);
+  const uint32_t rel = incl - len;
+  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
+  const uint32_t p = (uint32_t)lane;
+  int lo = 0, hi = t - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
+    if (lo < hi) {
+      if (x > p) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
+  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
+  const uint64_t jn_e = __shfl(jn, lo, kWave);
+  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
+  if (p < f) {
+    const uint32_t q = bs_e + (p - excl_e);
+    valid = true;
+    ent = lo;
+    col = b_livs[q] - (NUMERIC ? np * (jn_e - kp * row) : jn_e);
+    if (NUMERIC) v = av_e * b_vals[q];
+  }
+}
+
 // One lane's share of a small row's product: at most one output entry.
 struct RowOut {
   bool own = false;   // this lane holds an output entry

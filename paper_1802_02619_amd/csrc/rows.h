@@ -72,6 +72,7 @@ struct KeptBuffers {
 struct BatchLaunch {
   bool acc = true;
   int grid = 1;
+  int chunk_rows = 1;  // consecutive rows per wave visit
   uint32_t rows = 0;
   const void* inst = nullptr;  // device array of per-instance descriptors
   const uint32_t* rs = nullptr;
@@ -88,6 +89,9 @@ struct BatchLaunch {
 // dst[i] = src[idx[i]] for i < n, and out[i] = i (value-permutation helpers of batch plans).
 void gather_values(lco_ctx ctx, const double* src, const uint64_t* idx, int64_t n, double* dst);
 void fill_iota(lco_ctx ctx, uint64_t* out, int64_t n);
+// Rows per wave chunk and the grid of the batched row kernels for `rows` rows.
+int batch_chunk_rows(lco_ctx ctx, uint64_t rows);
+int batch_grid(lco_ctx ctx, uint64_t rows, int chunk_rows, int blocks_per_cu);
 // The numeric pass: every batched row recomputed from the operands' current values.
 void batch_numeric(lco_ctx ctx, const BatchLaunch& L);
 
