@@ -170,10 +170,12 @@ def test_colsparse_times_rowsparse_uses_doubly_compressed(lco_lib, gpu_ctx, orac
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
 
 
+@pytest.mark.parametrize("lc", [[0, 1, 4, 5], [0, 4, 1, 5]])
 @pytest.mark.parametrize("bits,draws", [(6, 3000), (10, 60000)])
-def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws):
+def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws, lc):
     """Scaled-down hyper-sparse Kronecker pair contracted over (3,4)x(1,2): index-sparse x
-    index-sparse -> SOP, with the second operand rearranged."""
+    index-sparse -> SOP, with the second operand rearranged; the output modes in order, or
+    interleaved (a general output-LIV key)."""
     ca, va = L.kronecker_hypersparse(bits, draws, seed=1)
     cb, vb = L.kronecker_hypersparse(bits, draws, seed=2)
     dims = [2**bits] * 4
@@ -182,7 +184,7 @@ def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws):
     gb = gpu_create(lco_lib, gpu_ctx, dims, cb, vb, flags)
     oa = oracle_mod.create(dims, ca, va, sum_duplicates=True)
     ob = oracle_mod.create(dims, cb, vb, sum_duplicates=True)
-    la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
+    la, lb = [0, 1, 2, 3], [2, 3, 4, 5]
     p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
     if bits == 10:
         assert lco_lib.ALGOS[p.algo] == "SOP" and p.permute_b == 1
