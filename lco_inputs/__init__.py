@@ -21,6 +21,11 @@ Workloads (all synthetic, seeded, shaped like the paper's benchmark operators):
   ``[0.57, 0.19, 0.19, 0.05]``; values uniform(-1, 1).  Duplicated coordinates
   are left in (the consumer sums them on construction).  This is the recursive
   quadrant model that the paper's R-TENSOR generalises (Section 5.2.1).
+* ``fd_first_derivative(n)`` -- the length-``n`` first-derivative FD matrix of the
+  paper's Section 2 as an order-2 tensor: O(h^2) central differences (-1/2, +1/2)
+  on interior rows, the O(h^2) one-sided forms (-3, 4, -1)/2 on the first row and
+  (1, -4, 3)/2 on the last.  Its products with Kronecker deltas build the
+  combinatorial Laplacian of the paper's Section 2 at ``n = 2**k - 1``.
 * ``random_sparse(rng, dims, nnz)`` -- distinct uniformly random coordinates.
 * ``diagonal(order, n)`` -- the purely diagonal tensor of the paper's Figure on
   hyper-sparsity of matricised tensors (all-zero except i=j=...).
@@ -44,6 +49,7 @@ import numpy as np
 __all__ = [
     "fd_laplacian",
     "kronecker_hypersparse",
+    "fd_first_derivative",
     "random_sparse",
     "diagonal",
     "batched_fd_instances",
@@ -135,6 +141,20 @@ def random_sparse(rng: np.random.Generator, dims, nnz: int, integer_values: bool
     else:
         v = rng.uniform(-1.0, 1.0, n)
     return coords, v
+
+
+def fd_first_derivative(n: int):
+    """Coordinates ``(nnz, 2)`` (row, column) and values of the ``n x n`` O(h^2)
+    first-derivative matrix (unit spacing), ``n >= 3``: 2n + 2 entries."""
+    if n < 3:
+        raise ValueError("the one-sided rows need n >= 3")
+    rows, cols, vals = [0, 0, 0], [0, 1, 2], [-1.5, 2.0, -0.5]
+    i = np.arange(1, n - 1, dtype=np.int64)
+    r = np.concatenate([np.array(rows), np.repeat(i, 2), np.full(3, n - 1)])
+    c = np.concatenate([np.array(cols), np.stack([i - 1, i + 1], axis=1).ravel(), np.array([n - 3, n - 2, n - 1])])
+    v = np.concatenate([np.array(vals), np.tile([-0.5, 0.5], n - 2), np.array([0.5, -2.0, 1.5])])
+    coords = np.ascontiguousarray(np.stack([r, c], axis=1).astype(np.uint64))
+    return coords, v.astype(np.float64)
 
 
 def diagonal(order: int, n: int, values=None):

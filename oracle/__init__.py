@@ -1,8 +1,8 @@
 """Python front-end of the LCO oracle -- TEST INFRASTRUCTURE ONLY.
 
 The oracle is the plain CPU definition of what the HIP library computes
-(construction, permutation and contraction of linearised-coordinate sparse
-tensors), written in ``lco_oracle.cpp`` with coordinate lists, std::stable_sort
+(construction, permutation, contraction and addition of linearised-coordinate
+sparse tensors), written in ``lco_oracle.cpp`` with coordinate lists, std::stable_sort
 and std::map.  Only the tests, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package; the product library never does.
 
@@ -82,6 +82,9 @@ def _load():
                                  ctypes.c_int, u64p, ctypes.c_int64, u64p, f64p, i32p,
                                  ctypes.c_int, i32p, ctypes.c_int]
     lib.ora_contract.restype = vp
+    lib.ora_add.argtypes = [ctypes.c_int, u64p, ctypes.c_int64, u64p, f64p, i32p,
+                            u64p, ctypes.c_int64, u64p, f64p, i32p, i32p, ctypes.c_double, ctypes.c_double]
+    lib.ora_add.restype = vp
     _lib = lib
     return lib
 
@@ -180,3 +183,16 @@ def contract(a: Tensor, a_labels, b: Tensor, b_labels, c_labels, mode: str = "ma
                              len(db), dbp, lb.shape[0], lbp, vbp, lbbp,
                              len(lc), lcp, 0 if mode == "map" else 1)
     return _take(h, with_absum=True)
+
+
+def add(a: Tensor, a_labels, b: Tensor, b_labels, c_labels, alpha: float = 1.0, beta: float = 1.0) -> Tensor:
+    """c = alpha*a + beta*b over the same labelled modes (Section 2; Section 3.2's
+    sum of the two Laplacian terms): b's and c's labels are permutations of a's."""
+    if a.order != b.order or len(a_labels) != a.order or len(b_labels) != a.order or len(c_labels) != a.order:
+        raise OracleError(1)
+    da, dap = _u64(a.dims); la, lap = _u64(a.livs); va, vap = _f64(a.vals); laa, laap = _i32(a_labels)
+    db, dbp = _u64(b.dims); lb, lbp = _u64(b.livs); vb, vbp = _f64(b.vals); lbb, lbbp = _i32(b_labels)
+    lc, lcp = _i32(c_labels)
+    h = _load().ora_add(len(da), dap, la.shape[0], lap, vap, laap, dbp, lb.shape[0], lbp, vbp, lbbp, lcp,
+                        float(alpha), float(beta))
+    return _take(h)

@@ -2,8 +2,9 @@
 //
 // A plain, slow, single-threaded CPU implementation of what the HIP library
 // computes: construction of linearised-coordinate (LCO) tensors, permutation
-// of their modes, and sparse tensor contraction.  Only the test-suite, the
-// smoke check and the benchmark's CPU-baseline leg may load this library.  It
+// of their modes, sparse tensor contraction and sparse tensor addition.  Only
+// the test-suite, the smoke check and the benchmark's CPU-baseline leg may load
+// this library.  It
 // shares no code, header or table with the HIP library: it is written straight
 // from the definitions in Harrison & Joseph, "High Performance Rearrangement
 // and Multiplication Routines for Sparse Tensor Arithmetic" (SISC), using
@@ -298,6 +299,65 @@ void* ora_contract(int oa, const uint64_t* da, int64_t na, const uint64_t* la, c
       res->absum.back() += std::fabs(prods[t].second);
     }
   }
+  return res;
+}
+
+// ---- addition (Section 2; the sum of the two terms of the combinatorial
+// Laplacian, whose second term must first be re-sorted, Section 3.2) ---------
+// The plain definition: decode every entry of either operand to coordinates,
+// map them to the output's modes through the labels, re-linearise, and
+// accumulate in a std::map: first alpha*a for every entry of a, then beta*b for
+// every entry of b (added to alpha*a when the position already holds it).
+// Input LIVs must be strictly increasing and in range.
+void* ora_add(int order, const uint64_t* da, int64_t na, const uint64_t* la, const double* va, const int* laba,
+              const uint64_t* db, int64_t nb, const uint64_t* lb, const double* vb, const int* labb,
+              const int* labc, double alpha, double beta) {
+  Result* res = new Result;
+  res->order = order;
+  if (order < 0 || na < 0 || nb < 0) { res->status = ORA_E_ARG; return res; }
+  auto find = [](int n, const int* lab, int x) {
+    for (int i = 0; i < n; ++i) if (lab[i] == x) return i;
+    return -1;
+  };
+  // the three label lists must name the same set of distinct labels
+  for (int i = 0; i < order; ++i) {
+    if (find(i, laba, laba[i]) >= 0 || find(i, labb, labb[i]) >= 0 || find(i, labc, labc[i]) >= 0) {
+      res->status = ORA_E_ARG;
+      return res;
+    }
+  }
+  std::vector<int> from_a(order), from_b(order);  // output mode r is a's mode from_a[r], b's mode from_b[r]
+  res->dims.resize(order);
+  for (int r = 0; r < order; ++r) {
+    from_a[r] = find(order, laba, labc[r]);
+    from_b[r] = find(order, labb, labc[r]);
+    if (from_a[r] < 0 || from_b[r] < 0) { res->status = ORA_E_ARG; return res; }
+    if (da[from_a[r]] != db[from_b[r]]) { res->status = ORA_E_SHAPE; return res; }
+    res->dims[r] = da[from_a[r]];
+  }
+  if (!dims_fit(order, da)) { res->status = ORA_E_OVERFLOW; return res; }
+  unsigned __int128 total = 1;
+  for (int r = 0; r < order; ++r) total *= da[r];
+  std::map<uint64_t, double> acc;
+  std::vector<uint64_t> c(order), cc(order);
+  for (int64_t i = 0; i < na; ++i) {
+    if ((unsigned __int128)la[i] >= total || (i > 0 && la[i] <= la[i - 1])) { res->status = ORA_E_UNSORTED; return res; }
+    delinearise(order, da, la[i], c.data());
+    for (int r = 0; r < order; ++r) cc[r] = c[from_a[r]];
+    acc[linearise(order, res->dims.data(), cc.data())] = alpha * va[i];
+  }
+  for (int64_t j = 0; j < nb; ++j) {
+    if ((unsigned __int128)lb[j] >= total || (j > 0 && lb[j] <= lb[j - 1])) { res->status = ORA_E_UNSORTED; return res; }
+    delinearise(order, db, lb[j], c.data());
+    for (int r = 0; r < order; ++r) cc[r] = c[from_b[r]];
+    const uint64_t out = linearise(order, res->dims.data(), cc.data());
+    auto it = acc.find(out);
+    if (it == acc.end()) acc[out] = beta * vb[j];
+    else it->second = it->second + beta * vb[j];
+  }
+  res->livs.reserve(acc.size());
+  res->vals.reserve(acc.size());
+  for (auto& kv : acc) { res->livs.push_back(kv.first); res->vals.push_back(kv.second); }
   return res;
 }
 

@@ -320,3 +320,140 @@ def test_kronecker_generator_recipe(oracle_mod):
     assert np.isclose(t.vals.sum(), vals.sum())
     dense = dense_from_coords([64] * 4, coords, vals)
     assert np.array_equal(np.count_nonzero(dense != 0) <= t.nnz, True)
+
+
+# ---------------------------------------------------------------- addition
+def _pattern_of(t):
+    return set(int(x) for x in t.livs)
+
+
+def _dense_pattern(t):
+    """Boolean array: the positions the tensor stores (explicit zeros included)."""
+    return dense_of(oracle_tensor_with_values(t, np.ones(t.nnz))) != 0
+
+
+def oracle_tensor_with_values(t, vals):
+    import oracle
+    return oracle.Tensor(t.dims, t.livs, np.asarray(vals, dtype=np.float64))
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 1.0), (1.0, -1.0), (0.5, 3.0)])
+def test_add_vs_dense_all_label_orders(oracle_mod, alpha, beta):
+    """Section 2 addition: c = alpha*a + beta*b where b's modes are named in any
+    order; dense brute force (numpy transposes) for every order of b's labels and
+    of c's labels, values and pattern (the union of the patterns, explicit zeros
+    included)."""
+    rng = np.random.default_rng(11)
+    dims = [3, 4, 5]
+    ca, va = L.random_sparse(rng, dims, 20, integer_values=True)
+    va[:3] = 0.0  # explicit zeros stay structural
+    a = oracle_mod.create(dims, ca, va)
+    labels = [7, 8, 9]
+    A = dense_of(a)
+    Apat = _dense_pattern(a)
+    for pb in itertools.permutations(range(3)):
+        b_labels = [labels[q] for q in pb]
+        b_dims = [dims[q] for q in pb]
+        cb, vb = L.random_sparse(rng, b_dims, 25, integer_values=True)
+        b = oracle_mod.create(b_dims, cb, vb)
+        # B[b coords] -> a's mode order: a mode q is b mode pb.index(q)
+        Bt = np.transpose(dense_of(b), [pb.index(q) for q in range(3)])
+        Bpat = np.transpose(_dense_pattern(b), [pb.index(q) for q in range(3)])
+        for pc in itertools.permutations(range(3)):
+            c_labels = [labels[q] for q in pc]
+            c = oracle_mod.add(a, labels, b, b_labels, c_labels, alpha, beta)
+            assert [int(x) for x in c.dims] == [dims[q] for q in pc]
+            assert np.all(np.diff(c.livs.astype(np.float64)) > 0)
+            want = np.transpose(alpha * A + beta * Bt, pc)
+            assert np.array_equal(dense_of(c), want)
+            assert np.array_equal(_dense_pattern(c), np.transpose(Apat | Bpat, pc))
+
+
+def test_add_cancellation_keeps_pattern_and_identities(oracle_mod):
+    """a - a keeps every position with value 0.0; a + b = b + a; adding an empty
+    tensor scales; a + a = 2a exactly."""
+    rng = np.random.default_rng(3)
+    dims = [6, 5, 4, 3]
+    ca, va = L.random_sparse(rng, dims, 60)
+    cb, vb = L.random_sparse(rng, dims, 70)
+    a = oracle_mod.create(dims, ca, va)
+    b = oracle_mod.create(dims, cb, vb)
+    lab = [0, 1, 2, 3]
+    z = oracle_mod.add(a, lab, a, lab, lab, 1.0, -1.0)
+    assert np.array_equal(z.livs, a.livs) and np.all(z.vals == 0.0)
+    two = oracle_mod.add(a, lab, a, lab, lab)
+    assert np.array_equal(two.vals, 2.0 * a.vals)
+    ab = oracle_mod.add(a, lab, b, lab, lab, 0.25, -3.0)
+    ba = oracle_mod.add(b, lab, a, lab, lab, -3.0, 0.25)
+    assert np.array_equal(ab.livs, ba.livs) and np.array_equal(ab.vals, ba.vals)
+    assert _pattern_of(ab) == _pattern_of(a) | _pattern_of(b)
+    empty = oracle_mod.create(dims, np.zeros((0, 4), np.uint64), np.zeros(0))
+    e = oracle_mod.add(empty, lab, a, lab, lab, 1.0, -2.0)
+    assert np.array_equal(e.livs, a.livs) and np.array_equal(e.vals, -2.0 * a.vals)
+
+
+def test_add_errors(oracle_mod):
+    a = oracle_mod.create([2, 3], [[0, 0]], [1.0])
+    b = oracle_mod.create([3, 2], [[0, 0]], [1.0])
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.add(a, [0, 1], b, [0, 1], [0, 1])  # same labels, different dims
+    assert e.value.code == 3
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.add(a, [0, 1], b, [1, 2], [0, 1])  # label sets differ
+    assert e.value.code == 1
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.add(a, [0, 0], b, [0, 1], [0, 1])  # repeated label
+    assert e.value.code == 1
+
+
+# ------------------------------------------- combinatorial Laplacian (Section 2)
+def test_fd_first_derivative_exact_on_quadratics():
+    """The O(h^2) central, forward and backward differences of the FD matrix of
+    Section 2 are exact on quadratics: D x^2 = 2x, D x = 1, D 1 = 0 (the last
+    row must be (1, -4, 3)/2 for this to hold)."""
+    for n in (3, 4, 7, 31):
+        c, v = L.fd_first_derivative(n)
+        assert len(v) == 2 * n + 2
+        D = dense_from_coords([n, n], c, v)
+        x = np.arange(n, dtype=np.float64)
+        assert np.array_equal(D @ (x * x), 2 * x)
+        assert np.array_equal(D @ x, np.ones(n))
+        assert np.array_equal(D @ np.ones(n), np.zeros(n))
+
+
+def combinatorial_laplacian_oracle(oracle_mod, n):
+    """The design tensor a_ijlk = d_ii' delta_jl d_i'k + d_jj' delta_ik d_j'l of
+    Section 2, executed left to right as binary products (two outer products with
+    Kronecker deltas, two hyper-sparse contractions) and one addition whose
+    second term is re-sorted into the first term's mode order."""
+    I, J, K, Lb, I2, J2 = 0, 1, 2, 3, 4, 5
+    cd, vd = L.fd_first_derivative(n)
+    d = oracle_mod.create([n, n], cd, vd)
+    ce, ve = L.diagonal(2, n, np.ones(n))
+    delta = oracle_mod.create([n, n], ce, ve)
+    by = oracle_mod.contract(d, [I, I2], delta, [J, Lb], [I, I2, J, Lb])
+    ty = oracle_mod.contract(by, [I, I2, J, Lb], d, [I2, K], [I, J, Lb, K])
+    bx = oracle_mod.contract(d, [J, J2], delta, [I, K], [J, J2, I, K])
+    tx = oracle_mod.contract(bx, [J, J2, I, K], d, [J2, Lb], [J, I, K, Lb])
+    a = oracle_mod.add(ty, [I, J, Lb, K], tx, [J, I, K, Lb], [I, J, Lb, K])
+    return by, ty, tx, a
+
+
+@pytest.mark.parametrize("n", [3, 7, 15])
+def test_combinatorial_laplacian_closed_form(oracle_mod, n):
+    """a = (D^2)_ik delta_jl + delta_ik (D^2)_jl: flattened with rows (i, j) and
+    columns (k, l) it is kron(D^2, I) + kron(I, D^2) (dense numpy); the pattern
+    is the union of the two terms' patterns."""
+    by, ty, tx, a = combinatorial_laplacian_oracle(oracle_mod, n)
+    c, v = L.fd_first_derivative(n)
+    D = dense_from_coords([n, n], c, v)
+    D2 = D @ D
+    E = np.eye(n)
+    want = (np.kron(D2, E) + np.kron(E, D2)).reshape(n, n, n, n)  # [i, j, k, l]
+    got = dense_of(a).transpose(0, 1, 3, 2)  # a is stored (i, j, l, k)
+    assert np.array_equal(got, want)
+    pat2 = (np.abs(D) != 0).astype(np.int64) @ (np.abs(D) != 0).astype(np.int64) != 0  # structural D^2
+    pat = (np.kron(pat2, E) + np.kron(E, pat2)) != 0
+    assert a.nnz == int(pat.sum())
+    assert by.nnz == (2 * n + 2) * n
+    assert ty.nnz == int(pat2.sum()) * n and tx.nnz == ty.nnz
