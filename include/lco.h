@@ -16,6 +16,9 @@
  *     and multiply -> map back, with the algorithm chosen from the paper's
  *     table of sparsity combinations (Section 5.2, Table "Multiplication
  *     possibilities based on sparse characteristics of operands").
+ *   - Addition (Sections 2 and 3.2): the sum of two tensors over the same
+ *     labelled modes, as a permutation of the operand not yet in the output's
+ *     order followed by a merge of the two sorted lists.
  *
  * Conventions shared by every entry point
  *   - Every function returns an lco_status; no exception crosses the ABI.  On
@@ -25,8 +28,8 @@
  *   - "device" pointers address HIP device memory of the context's device;
  *     "host" pointers address ordinary host memory.
  *   - All device work is enqueued on the context's stream.  Entry points that
- *     must learn a data-dependent size (lco_create, lco_contract) synchronise
- *     that stream before returning; lco_permute does not.
+ *     must learn a data-dependent size (lco_create, lco_contract, lco_add)
+ *     synchronise that stream before returning; lco_permute does not.
  *   - Tensors are owned by the caller and released with lco_destroy, which must
  *     happen before the context that made them is destroyed.  Inputs are never
  *     modified.  An input may come from any context on the same device; work
@@ -191,6 +194,27 @@ typedef struct {
  * exactly 2^64), LCO_E_OOM. */
 lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
                         int c_order, const int* c_labels, uint32_t flags, lco_tensor* out);
+
+/* ----------------------------------------------------------------- addition */
+
+/* Sparse addition (Section 2: the design tensor there is a sum of two products;
+ * Section 3.2: before two terms can be added, one must be re-sorted into the
+ * other's lexicographical order).  c = alpha*a + beta*b, where a and b have the
+ * same order and `a_labels`, `b_labels` and `c_labels` (host, that many entries
+ * each) name the same set of distinct labels; modes with the same label must
+ * have the same dimension.  Output mode r is the mode labelled c_labels[r]; the
+ * output is sorted in its default order.  An operand whose label order differs
+ * from c_labels is first permuted (as by lco_permute); the two sorted lists are
+ * then merged.  An LIV present in both operands gets alpha*a + beta*b (two
+ * rounded products, then one rounded sum); an LIV present in one operand gets
+ * that operand's value times its coefficient.  The pattern is the union of the
+ * two patterns, whatever the values (a - a keeps every position, at 0.0).
+ * Synchronises once to learn the output size.  Errors: LCO_E_ARG (NULL
+ * argument, different orders, repeated labels, label lists naming different
+ * sets), LCO_E_SHAPE (same label, different dimensions), LCO_E_UNSUPPORTED
+ * (more than 2^32-1 entries in the two operands together), LCO_E_OOM. */
+lco_status lco_add(lco_ctx ctx, double alpha, lco_tensor a, const int* a_labels, double beta, lco_tensor b,
+                   const int* b_labels, const int* c_labels, lco_tensor* out);
 
 /* One product of a batch (the arguments of lco_contract). */
 typedef struct {

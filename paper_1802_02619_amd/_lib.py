@@ -16,7 +16,8 @@ import threading
 __all__ = [
     "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
-    "lco_contract", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read", "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
+    "lco_contract", "lco_add", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read",
+    "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
@@ -146,6 +147,7 @@ def load_library():
             "lco_vals": (vp, [vp]),
             "lco_permute": (i32, [vp, vp, pi32, pvp]),
             "lco_contract": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, pvp]),
+            "lco_add": (i32, [vp, ctypes.c_double, vp, pi32, ctypes.c_double, vp, pi32, pi32, pvp]),
             "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
             "lco_contract_batch": (i32, [vp, i32, ctypes.POINTER(ContractDesc), ctypes.POINTER(ctypes.c_void_p)]),
             "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -347,6 +349,16 @@ def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_label
     h = ctypes.c_void_p()
     _check(L.lco_contract(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
                           _i32arr(c_labels), int(flags), ctypes.byref(h)))
+    return Tensor(ctx, h)
+
+
+def lco_add(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, alpha: float = 1.0,
+            beta: float = 1.0) -> Tensor:
+    """c = alpha*a + beta*b over the same labelled modes (output mode order: c_labels)."""
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(L.lco_add(ctx.handle, float(alpha), a.handle, _i32arr(a_labels), float(beta), b.handle,
+                     _i32arr(b_labels), _i32arr(c_labels), ctypes.byref(h)))
     return Tensor(ctx, h)
 
 

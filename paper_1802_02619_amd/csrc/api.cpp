@@ -527,6 +527,21 @@ lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tens
   LCO_CATCH
 }
 
+lco_status lco_add(lco_ctx ctx, double alpha, lco_tensor a, const int* a_labels, double beta, lco_tensor b,
+                   const int* b_labels, const int* c_labels, lco_tensor* out) {
+  LCO_TRY
+  if (!out) fail(LCO_E_ARG, "lco_add: out is NULL");
+  *out = nullptr;
+  if (!ctx || !a || !b) fail(LCO_E_ARG, "lco_add: ctx or tensor is NULL");
+  if (a->ctx->device != ctx->device || b->ctx->device != ctx->device)
+    fail(LCO_E_ARG, "lco_add: tensor lives on another device");
+  AddDetail d = plan_add(a->order, a->dims, a_labels, b->order, b->dims, b_labels, c_labels);
+  LCO_HIP(hipSetDevice(ctx->device));
+  *out = add_run(ctx, alpha, a, beta, b, d);
+  return LCO_OK;
+  LCO_CATCH
+}
+
 lco_status lco_plan_info(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
                          int c_order, const int* c_labels, uint32_t flags, lco_plan* out) {
   LCO_TRY

@@ -65,6 +65,19 @@ lco_tensor contract_run(lco_ctx ctx, const lco_tensor_s* a, const lco_tensor_s* 
   return out;
 }
 
+// Addition: operands whose mode order differs from the output's are permuted
+// first (Section 3.2: one term is re-sorted into the other's order), then the
+// two sorted lists are merged.
+lco_tensor add_run(lco_ctx ctx, double alpha, const lco_tensor_s* a, double beta, const lco_tensor_s* b,
+                   const AddDetail& d) {
+  Owned ta, tb;
+  const lco_tensor_s* A = a;
+  const lco_tensor_s* B = b;
+  if (d.permute_a && a->nnz) A = ta.t = permuted(ctx, a, d.perm_a);
+  if (d.permute_b && b->nnz) B = tb.t = permuted(ctx, b, d.perm_b);
+  return add_merge(ctx, alpha, A, beta, B, d.order, d.c_dims);
+}
+
 }  // namespace lco
 
 // ---------------------------------------------------------------- batched C-ABI

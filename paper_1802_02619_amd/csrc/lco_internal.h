@@ -173,6 +173,16 @@ struct ContractDetail {
 };
 ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
                              const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags);
+// Addition of two tensors over the same labelled modes: each operand is brought
+// into the output's mode order (output mode r is operand mode perm[r]).
+struct AddDetail {
+  int order = 0;
+  uint64_t c_dims[LCO_MAX_ORDER] = {};
+  int perm_a[LCO_MAX_ORDER] = {}, perm_b[LCO_MAX_ORDER] = {};
+  bool permute_a = false, permute_b = false;
+};
+AddDetail plan_add(int oa, const uint64_t* da, const int* la, int ob, const uint64_t* db, const int* lb,
+                   const int* lc);
 
 // ------------------------------------------------------------------ kernels (launchers)
 constexpr int kMaxOrder = LCO_MAX_ORDER;
@@ -219,5 +229,14 @@ int default_digit_cap();
 // permutation of a tensor's storage according to a plan
 void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, uint64_t* out_livs,
                      double* out_vals);
+// a new tensor holding `in` permuted (output mode r is input mode perm[r])
+lco_tensor permuted(lco_ctx ctx, const lco_tensor_s* in, const int* perm);
+// c = alpha*a + beta*b of two sorted tensors in the same mode order (the merge
+// of their LIV lists); returns a new tensor with dimensions `dims`
+lco_tensor add_merge(lco_ctx ctx, double alpha, const lco_tensor_s* a, double beta, const lco_tensor_s* b, int order,
+                     const uint64_t* dims);
+// lco_add after planning: permutes the operands that need it, then merges
+lco_tensor add_run(lco_ctx ctx, double alpha, const lco_tensor_s* a, double beta, const lco_tensor_s* b,
+                   const AddDetail& d);
 
 }  // namespace lco

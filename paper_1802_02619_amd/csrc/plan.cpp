@@ -340,6 +340,35 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
   return d;
 }
 
+AddDetail plan_add(int oa, const uint64_t* da, const int* la, int ob, const uint64_t* db, const int* lb,
+                   const int* lc) {
+  check_dims(oa, da, "add operand a");
+  check_dims(ob, db, "add operand b");
+  if (oa != ob) fail(LCO_E_ARG, "add: operands of different orders");
+  if (oa && (!la || !lb || !lc)) fail(LCO_E_ARG, "add: labels are NULL");
+  auto find = [](int n, const int* l, int x) {
+    for (int i = 0; i < n; ++i) if (l[i] == x) return i;
+    return -1;
+  };
+  for (int i = 0; i < oa; ++i) {
+    if (find(i, la, la[i]) >= 0 || find(i, lb, lb[i]) >= 0 || find(i, lc, lc[i]) >= 0)
+      fail(LCO_E_ARG, "add: repeated label");
+  }
+  AddDetail d;
+  d.order = oa;
+  for (int r = 0; r < oa; ++r) {
+    const int ia = find(oa, la, lc[r]), ib = find(ob, lb, lc[r]);
+    if (ia < 0 || ib < 0) fail(LCO_E_ARG, "add: the label lists name different sets of modes");
+    if (da[ia] != db[ib]) fail(LCO_E_SHAPE, "add: modes with the same label differ in dimension");
+    d.perm_a[r] = ia;
+    d.perm_b[r] = ib;
+    d.c_dims[r] = da[ia];
+    d.permute_a |= ia != r;
+    d.permute_b |= ib != r;
+  }
+  return d;
+}
+
 }  // namespace lco
 
 // ---------------------------------------------------------------- C-ABI (host-only)
