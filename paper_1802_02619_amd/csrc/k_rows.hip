@@ -11,6 +11,9 @@
 // of the contracted index starting from 0.0.
 //
 // Work split: the non-empty rows of A' are binned by their product count f(i).
+//  - at most 4 A' entries and f(i) <= 16: one lane per row (k-way merge of the
+//    entries' B' rows).
+//  - one A' entry and f(i) > 16: a wave copies the scaled B' row.
 //  - f(i) <= 64 and at most 64 A' entries: one wave per row.  CSR/DCSR keep an
 //    LDS hash table (column -> slot) as the sparse accumulator, accumulate in
 //    registers (slot s lives in lane s mod 64) in product order, then sort the
@@ -94,10 +97,12 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_
 }
 
 // Writes the shape code of every row and collects the long rows (more than 64
-// products or entries) in `list2` with their product counts `f2` (list order is
-// arbitrary; each long row's result depends only on its own products).
+// products or entries, except single-entry rows) in `list2` with their product
+// counts `f2` (list order is arbitrary; each long row's result depends only on
+// its own products).  `*tiny` / `*copy` are set when some row is of that class.
 __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ n2, uint32_t* __restrict__ list2,
-                                    uint64_t* __restrict__ f2, uint8_t* __restrict__ shape) {
+                                    uint64_t* __restrict__ f2, uint8_t* __restrict__ shape,
+                                    uint32_t* __restrict__ tiny, uint32_t* __restrict__ copy) {
   const uint64_t nzr = *ra.nzr_a;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
     if ((uint64_t)r >= nzr) break;
@@ -109,7 +114,13 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restr
       mx = l > mx ? l : mx;
     }
     uint8_t sh = kShapeSkip;
-    if (f > 0 && small_row(f, e1 - e0)) {
+    if (f > 0 && e1 - e0 <= (uint32_t)kTinyEntries && f <= (uint64_t)kTinyProducts) {
+      sh = kShapeTiny;
+      *tiny = 1u;
+    } else if (f > 0 && e1 - e0 == 1) {
+      sh = kShapeCopy;
+      *copy = 1u;
+    } else if (f > 0 && small_row(f, e1 - e0)) {
       uint32_t lw = 0;
       while ((1ull << lw) < mx) ++lw;
       sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
@@ -174,7 +185,7 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
     double x_av = 0.0;
     for (int i = 0; i < rows; ++i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
-      if (sh == kShapeSkip) continue;
+      if (sh > kShapeSearch) continue;  // no products, a long row, or a row of the lane or copy kernels
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
       const uint64_t row = readlane_u64(m_id, i);
       const int t = (int)(e1 - e0);
@@ -211,6 +222,107 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
       }
     }
     if (!NUMERIC && lane < rows) cnt[r0 + lane] = my_cnt;
+  }
+}
+
+// ---------------------------------------------------------------- tiny rows: one lane per row
+//
+// A row with at most kTinyEntries entries and kTinyProducts products is merged
+// by one lane: the entries' B' rows are ascending in column, so a k-way merge
+// visits the row's columns in ascending order, and at each column the entries
+// that hold it are added in entry order (ascending contracted index) from 0.0.
+template <bool NUMERIC>
+__global__ __launch_bounds__(256) void row_tiny_kernel(RowArgs ra, uint32_t nzr, const uint8_t* __restrict__ shape,
+                                                       uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff,
+                                                       uint64_t* __restrict__ out_livs,
+                                                       double* __restrict__ out_vals) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nzr; r += gridDim.x * blockDim.x) {
+    if (shape[r] != kShapeTiny) continue;
+    const uint32_t e0 = ra.row_start[r];
+    const int t = (int)(ra.row_start[r + 1] - e0);
+    const uint64_t row = ra.row_id[r];
+    uint32_t p[kTinyEntries], end[kTinyEntries];
+    uint64_t jn[kTinyEntries], col[kTinyEntries];
+    double av[kTinyEntries];
+#pragma unroll
+    for (int e = 0; e < kTinyEntries; ++e) {
+      p[e] = 0;
+      end[e] = 0;
+      jn[e] = 0;
+      col[e] = 0;
+      av[e] = 0.0;
+      if (e < t) {
+        const uint32_t ge = e0 + e;
+        p[e] = ra.bstart[ge];
+        end[e] = p[e] + (uint32_t)ra.elen[ge];
+        jn[e] = (ra.a_livs[ge] - ra.kp * row) * ra.np;
+        if (NUMERIC) av[e] = ra.a_vals[ge];
+        if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
+      }
+    }
+    const uint64_t base = NUMERIC ? coff[r] : 0;
+    uint32_t d = 0;
+    for (int step = 0; step < kTinyProducts; ++step) {
+      bool any = false;
+      uint64_t m = 0;
+#pragma unroll
+      for (int e = 0; e < kTinyEntries; ++e) {
+        if (p[e] < end[e] && (!any || col[e] < m)) {
+          m = col[e];
+          any = true;
+        }
+      }
+      if (!any) break;
+      double sum = 0.0;
+#pragma unroll
+      for (int e = 0; e < kTinyEntries; ++e) {
+        if (p[e] < end[e] && col[e] == m) {
+          if (NUMERIC) sum += av[e] * ra.b_vals[p[e]];
+          ++p[e];
+          if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
+        }
+      }
+      if (NUMERIC) {
+        out_livs[base + d] = m + ra.np * row;
+        out_vals[base + d] = sum;
+      }
+      ++d;
+    }
+    if (!NUMERIC) cnt[r] = d;
+  }
+}
+
+// ---------------------------------------------------------------- single-entry rows: scaled copies
+//
+// A row with one A' entry (and more than kTinyProducts products) has as
+// products that entry's B' row scaled, already ascending in column and without
+// repeats: each output is 0.0 + a*b.  Symbolic pass: one thread per row writes
+// the count.  Numeric pass: one wave per row (rows strided over the waves of
+// the grid) copies the row with coalesced loads and stores.
+template <bool NUMERIC>
+__global__ __launch_bounds__(256) void row_copy_kernel(RowArgs ra, uint32_t nzr, const uint8_t* __restrict__ shape,
+                                                       uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff,
+                                                       uint64_t* __restrict__ out_livs,
+                                                       double* __restrict__ out_vals) {
+  if (!NUMERIC) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nzr; r += gridDim.x * blockDim.x)
+      if (shape[r] == kShapeCopy) cnt[r] = ra.elen[ra.row_start[r]];
+    return;
+  }
+  const int lane = lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t r = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; r < nzr; r += waves) {
+    if (shape[r] != kShapeCopy) continue;
+    const uint32_t e0 = ra.row_start[r];
+    const uint64_t row = ra.row_id[r];
+    const uint32_t len = (uint32_t)ra.elen[e0], bs = ra.bstart[e0];
+    const uint64_t jn = (ra.a_livs[e0] - ra.kp * row) * ra.np;
+    const double a = ra.a_vals[e0];
+    const uint64_t base = coff[r];
+    for (uint32_t q = lane; q < len; q += kWave) {
+      out_livs[base + q] = (ra.b_livs[bs + q] - jn) + ra.np * row;
+      out_vals[base + q] = 0.0 + a * ra.b_vals[bs + q];
+    }
   }
 }
 
@@ -358,11 +470,16 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint64_t* f2 = s.get<uint64_t>(na);
   memset_async(ctx, n2_dev, 0, sizeof(uint64_t));
   uint8_t* shape = s.get<uint8_t>(na);
+  uint64_t* flags_dev = s.get<uint64_t>(2);  // some row is tiny; some row is a copy
+  memset_async(ctx, flags_dev, 0, 2 * sizeof(uint64_t));
   LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, n2_dev, list2, f2,
-             shape);
-  const uint64_t* rb1[2] = {arows.count, n2_dev};
-  const uint64_t* h = readback(ctx, rb1, 2);
+             shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1));
+  const uint64_t* rb1[4] = {arows.count, n2_dev, flags_dev, flags_dev + 1};
+  const uint64_t* h = readback(ctx, rb1, 4);
   const uint64_t nzr = h[0], n2 = h[1];
+  const bool tiny = h[2] != 0, copy = h[3] != 0;
+  const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);
+  const int copy_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + 3) / 4, (uint64_t)ctx->num_cus * 8));
   uint64_t f2_total = 0;
   uint64_t* off2 = nullptr;
   if (n2) {
@@ -392,6 +509,12 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
                     kRowThreads, 0, __VA_ARGS__);                                                                \
   } while (0)
   LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
+  if (tiny)
+    LCO_LAUNCH(ctx, "row_tiny_sym", row_tiny_kernel<false>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
+               (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
+  if (copy)
+    LCO_LAUNCH(ctx, "row_copy_sym", row_copy_kernel<false>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
+               (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
   // long rows: expand, sort by (row rank, column), count distinct
   uint64_t* keys = nullptr;
   double* pvals = nullptr;
@@ -425,6 +548,12 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
   try {
     LCO_ROW_SMALL(true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    if (tiny)
+      LCO_LAUNCH(ctx, "row_tiny_num", row_tiny_kernel<true>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
+                 (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    if (copy)
+      LCO_LAUNCH(ctx, "row_copy_num", row_copy_kernel<true>, copy_grid, 256, 0, ra, (uint32_t)nzr,
+                 (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
     if (n2)
       LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
                  off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,

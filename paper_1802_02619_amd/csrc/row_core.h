@@ -77,7 +77,11 @@ __device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
 
 // Per-row shape codes of the one-wave kernel.
 constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
+constexpr uint8_t kShapeTiny = 8;      // at most kTinyEntries entries and kTinyProducts products: one lane per row
+constexpr uint8_t kShapeCopy = 9;      // one entry (more than kTinyProducts products): the row is a scaled B' row
 constexpr uint8_t kShapeSkip = 0xFF;   // no products, or a long row
+constexpr int kTinyEntries = 4;
+constexpr int kTinyProducts = 16;
 // Rows with at most 64 products and 64 entries run one wave per row.  When the
 // row's entries times W (the next power of two at least its longest B' row) fit
 // the 64 lanes, lane = entry * W + position ("entry-major"): each lane knows its

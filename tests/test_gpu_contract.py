@@ -139,6 +139,41 @@ def test_long_rows_global_path(lco_lib, gpu_ctx, oracle_mod):
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [2, 0], exact=True)
 
 
+def test_row_classes_mixed(lco_lib, gpu_ctx, oracle_mod):
+    """Every row class of the row engine in one product: single-entry rows whose
+    B' row is short or long (more than 64 products: the scaled-copy class),
+    rows of 2-4 entries with at most 16 products (one lane per row), rows of the
+    one-wave classes, and long rows; values include signed zeros (an output of
+    one product -0.0 must come out +0.0, as a sum started from 0.0)."""
+    rng = np.random.default_rng(31)
+    m, k, n = 400, 120, 700
+    b_rows = []
+    for j in range(k):
+        ln = [1, 2, 3, 5, 9, 17, 40, 70, 150][j % 9]
+        cols = rng.choice(n, ln, replace=False)
+        b_rows += [(j, c) for c in cols]
+    cb = np.array(b_rows, dtype=np.uint64)
+    vb = rng.integers(-3, 4, len(cb)).astype(np.float64)
+    vb[vb == 0] = -0.0
+    a_rows = []
+    for i in range(m):
+        t = [1, 1, 2, 3, 4, 6, 30][i % 7]
+        cols = rng.choice(k, t, replace=False)
+        a_rows += [(i, c) for c in cols]
+    ca = np.array(a_rows, dtype=np.uint64)
+    va = rng.integers(-2, 3, len(ca)).astype(np.float64)
+    va[va == 0] = 0.5
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [0, 2], exact=True)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [2, 0], exact=True)
+    # outer products: every row is one entry times the other operand's only row
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [2, 3], [0, 1, 2, 3], exact=True,
+            algos=("auto", "CSR", "CSC", "CSRNA", "DCSR"))
+    for t in (ga, gb):
+        t.destroy()
+
+
 # ---------------------------------------------------------------- hyper-sparse cells of the table
 def test_rowsparse_times_colsparse_uses_no_accumulator(lco_lib, gpu_ctx, oracle_mod):
     """a_ijk b_lmk (Section 5.2.4): A row-sparse, B column-sparse -> CSCNA/CSRNA."""
