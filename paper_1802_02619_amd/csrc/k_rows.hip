@@ -99,10 +99,12 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_
 // Writes the shape code of every row and collects the long rows (more than 64
 // products or entries, except single-entry rows) in `list2` with their product
 // counts `f2` (list order is arbitrary; each long row's result depends only on
-// its own products).  `*tiny` / `*copy` are set when some row is of that class.
+// its own products).  `*tiny` / `*copy` / `*wave` are set when some row is of
+// that class (`wave`: a row of the one-wave kernel).
 __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ n2, uint32_t* __restrict__ list2,
                                     uint64_t* __restrict__ f2, uint8_t* __restrict__ shape,
-                                    uint32_t* __restrict__ tiny, uint32_t* __restrict__ copy) {
+                                    uint32_t* __restrict__ tiny, uint32_t* __restrict__ copy,
+                                    uint32_t* __restrict__ wave) {
   const uint64_t nzr = *ra.nzr_a;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
     if ((uint64_t)r >= nzr) break;
@@ -121,6 +123,7 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restr
       sh = kShapeCopy;
       *copy = 1u;
     } else if (f > 0 && small_row(f, e1 - e0)) {
+      *wave = 1u;
       uint32_t lw = 0;
       while ((1ull << lw) < mx) ++lw;
       sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
@@ -231,64 +234,104 @@ __global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint
 // by one lane: the entries' B' rows are ascending in column, so a k-way merge
 // visits the row's columns in ascending order, and at each column the entries
 // that hold it are added in entry order (ascending contracted index) from 0.0.
+// Each wave takes 64 consecutive rows.  When all of them are tiny (or have no
+// output) and their outputs fit kTinyStage entries, the outputs form one
+// contiguous range: they are staged in LDS and stored with coalesced writes.
+constexpr int kTinyStage = 512;
+
+template <bool NUMERIC>
+__device__ __forceinline__ uint32_t tiny_merge(const RowArgs& ra, uint32_t r, uint64_t base, bool stage, uint64_t* sk,
+                                               double* sv, uint64_t* __restrict__ out_livs,
+                                               double* __restrict__ out_vals) {
+  const uint32_t e0 = ra.row_start[r];
+  const int t = (int)(ra.row_start[r + 1] - e0);
+  const uint64_t row = ra.row_id[r];
+  uint32_t p[kTinyEntries], end[kTinyEntries];
+  uint64_t jn[kTinyEntries], col[kTinyEntries];
+  double av[kTinyEntries];
+#pragma unroll
+  for (int e = 0; e < kTinyEntries; ++e) {
+    p[e] = 0;
+    end[e] = 0;
+    jn[e] = 0;
+    col[e] = 0;
+    av[e] = 0.0;
+    if (e < t) {
+      const uint32_t ge = e0 + e;
+      p[e] = ra.bstart[ge];
+      end[e] = p[e] + (uint32_t)ra.elen[ge];
+      jn[e] = (ra.a_livs[ge] - ra.kp * row) * ra.np;
+      if (NUMERIC) av[e] = ra.a_vals[ge];
+      if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
+    }
+  }
+  uint32_t d = 0;
+  for (int step = 0; step < kTinyProducts; ++step) {
+    bool any = false;
+    uint64_t m = 0;
+#pragma unroll
+    for (int e = 0; e < kTinyEntries; ++e) {
+      if (p[e] < end[e] && (!any || col[e] < m)) {
+        m = col[e];
+        any = true;
+      }
+    }
+    if (!any) break;
+    double sum = 0.0;
+#pragma unroll
+    for (int e = 0; e < kTinyEntries; ++e) {
+      if (p[e] < end[e] && col[e] == m) {
+        if (NUMERIC) sum += av[e] * ra.b_vals[p[e]];
+        ++p[e];
+        if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
+      }
+    }
+    if (NUMERIC) {
+      if (stage) {
+        sk[base + d] = m + ra.np * row;
+        sv[base + d] = sum;
+      } else {
+        out_livs[base + d] = m + ra.np * row;
+        out_vals[base + d] = sum;
+      }
+    }
+    ++d;
+  }
+  return d;
+}
+
 template <bool NUMERIC>
 __global__ __launch_bounds__(256) void row_tiny_kernel(RowArgs ra, uint32_t nzr, const uint8_t* __restrict__ shape,
                                                        uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff,
                                                        uint64_t* __restrict__ out_livs,
                                                        double* __restrict__ out_vals) {
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nzr; r += gridDim.x * blockDim.x) {
-    if (shape[r] != kShapeTiny) continue;
-    const uint32_t e0 = ra.row_start[r];
-    const int t = (int)(ra.row_start[r + 1] - e0);
-    const uint64_t row = ra.row_id[r];
-    uint32_t p[kTinyEntries], end[kTinyEntries];
-    uint64_t jn[kTinyEntries], col[kTinyEntries];
-    double av[kTinyEntries];
-#pragma unroll
-    for (int e = 0; e < kTinyEntries; ++e) {
-      p[e] = 0;
-      end[e] = 0;
-      jn[e] = 0;
-      col[e] = 0;
-      av[e] = 0.0;
-      if (e < t) {
-        const uint32_t ge = e0 + e;
-        p[e] = ra.bstart[ge];
-        end[e] = p[e] + (uint32_t)ra.elen[ge];
-        jn[e] = (ra.a_livs[ge] - ra.kp * row) * ra.np;
-        if (NUMERIC) av[e] = ra.a_vals[ge];
-        if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
-      }
+  __shared__ uint64_t s_key[NUMERIC ? 4 : 1][NUMERIC ? kTinyStage : 1];
+  __shared__ double s_val[NUMERIC ? 4 : 1][NUMERIC ? kTinyStage : 1];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t r0 = (blockIdx.x * (blockDim.x / kWave) + w) * kWave; r0 < nzr; r0 += waves * kWave) {
+    const uint32_t r = r0 + lane;
+    const bool in = r < nzr;
+    const bool tiny = in && shape[r] == kShapeTiny;
+    if (!NUMERIC) {
+      if (tiny) cnt[r] = tiny_merge<false>(ra, r, 0, false, nullptr, nullptr, nullptr, nullptr);
+      continue;
     }
-    const uint64_t base = NUMERIC ? coff[r] : 0;
-    uint32_t d = 0;
-    for (int step = 0; step < kTinyProducts; ++step) {
-      bool any = false;
-      uint64_t m = 0;
-#pragma unroll
-      for (int e = 0; e < kTinyEntries; ++e) {
-        if (p[e] < end[e] && (!any || col[e] < m)) {
-          m = col[e];
-          any = true;
-        }
+    const uint32_t rl = r0 + kWave < nzr ? r0 + kWave : nzr;
+    const uint64_t wbase = coff[r0], span = coff[rl] - wbase;
+    const bool quiet = !in || tiny || coff[r + 1] == coff[r];
+    const bool stage = span <= (uint64_t)kTinyStage && __ballot(quiet) == ~0ull;
+    if (tiny)
+      tiny_merge<true>(ra, r, stage ? coff[r] - wbase : coff[r], stage, s_key[NUMERIC ? w : 0],
+                       s_val[NUMERIC ? w : 0], out_livs, out_vals);
+    if (stage) {
+      wave_lds_sync();
+      for (uint32_t q = lane; q < (uint32_t)span; q += kWave) {
+        out_livs[wbase + q] = s_key[NUMERIC ? w : 0][q];
+        out_vals[wbase + q] = s_val[NUMERIC ? w : 0][q];
       }
-      if (!any) break;
-      double sum = 0.0;
-#pragma unroll
-      for (int e = 0; e < kTinyEntries; ++e) {
-        if (p[e] < end[e] && col[e] == m) {
-          if (NUMERIC) sum += av[e] * ra.b_vals[p[e]];
-          ++p[e];
-          if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
-        }
-      }
-      if (NUMERIC) {
-        out_livs[base + d] = m + ra.np * row;
-        out_vals[base + d] = sum;
-      }
-      ++d;
+      wave_lds_sync();
     }
-    if (!NUMERIC) cnt[r] = d;
   }
 }
 
@@ -470,15 +513,15 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint64_t* f2 = s.get<uint64_t>(na);
   memset_async(ctx, n2_dev, 0, sizeof(uint64_t));
   uint8_t* shape = s.get<uint8_t>(na);
-  uint64_t* flags_dev = s.get<uint64_t>(2);  // some row is tiny; some row is a copy
-  memset_async(ctx, flags_dev, 0, 2 * sizeof(uint64_t));
+  uint64_t* flags_dev = s.get<uint64_t>(3);  // some row is tiny; a copy; of the one-wave kernel
+  memset_async(ctx, flags_dev, 0, 3 * sizeof(uint64_t));
   LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, n2_dev, list2, f2,
-             shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1));
-  const uint64_t* rb1[4] = {arows.count, n2_dev, flags_dev, flags_dev + 1};
-  const uint64_t* h = readback(ctx, rb1, 4);
+             shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
+  const uint64_t* rb1[5] = {arows.count, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
+  const uint64_t* h = readback(ctx, rb1, 5);
   const uint64_t nzr = h[0], n2 = h[1];
-  const bool tiny = h[2] != 0, copy = h[3] != 0;
-  const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);
+  const bool tiny = h[2] != 0, copy = h[3] != 0, wave = h[4] != 0;
+  const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);  // 64 rows per wave and sweep
   const int copy_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + 3) / 4, (uint64_t)ctx->num_cus * 8));
   uint64_t f2_total = 0;
   uint64_t* off2 = nullptr;
@@ -508,7 +551,9 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM>), small_grid,     \
                     kRowThreads, 0, __VA_ARGS__);                                                                \
   } while (0)
-  LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
+  if (wave)
+    LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr,
+                  (uint64_t*)nullptr, (double*)nullptr);
   if (tiny)
     LCO_LAUNCH(ctx, "row_tiny_sym", row_tiny_kernel<false>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
                (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
@@ -547,7 +592,9 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   if (nnz_c > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "contract: more than 2^32-1 output entries");
   lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
   try {
-    LCO_ROW_SMALL(true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
+    if (wave)
+      LCO_ROW_SMALL(true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr,
+                    (const uint64_t*)coff, C->livs, C->vals);
     if (tiny)
       LCO_LAUNCH(ctx, "row_tiny_num", row_tiny_kernel<true>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
                  (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);

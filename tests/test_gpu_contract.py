@@ -174,6 +174,27 @@ def test_row_classes_mixed(lco_lib, gpu_ctx, oracle_mod):
         t.destroy()
 
 
+@pytest.mark.parametrize("b_len", [1, 2, 4])
+def test_tiny_rows_staged_and_direct(lco_lib, gpu_ctx, oracle_mod, b_len):
+    """Rows of at most 4 entries and 16 products only (one lane per row): with
+    short B' rows a wave's 64 rows have few outputs and are staged through LDS;
+    with 4 x 4 disjoint products a wave's outputs exceed the staging buffer and
+    are written directly.  Also a ragged last group of rows."""
+    rng = np.random.default_rng(40 + b_len)
+    m, k = 64 * 37 + 13, 4 * 64
+    n = 4 * k
+    cb = np.array([(j, (j * 4 + q) % n) for j in range(k) for q in range(b_len)], dtype=np.uint64)
+    vb = rng.integers(-4, 5, len(cb)).astype(np.float64)
+    ca = np.array([(i, (i * 4 + e) % k) for i in range(m) for e in range(1 + i % 4)], dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [0, 2], exact=True,
+            algos=("auto", "CSR", "CSRNA", "DCSR"))
+    for t in (ga, gb):
+        t.destroy()
+
+
 # ---------------------------------------------------------------- hyper-sparse cells of the table
 def test_rowsparse_times_colsparse_uses_no_accumulator(lco_lib, gpu_ctx, oracle_mod):
     """a_ijk b_lmk (Section 5.2.4): A row-sparse, B column-sparse -> CSCNA/CSRNA."""
