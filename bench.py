@@ -587,6 +587,63 @@ def app_leg(lco, ctx, torch, np, L, n: int, reps: int):
     return out
 
 
+def rp_leg(lco, ctx, torch, np, L, n: int, reps: int):
+    """The paper's permutation experiment (Section 4.2, Table rp_timings): all 23 non-identity permutations
+    of the fourth-order combinatorial Laplacian a_ijkl (Section 2) at n = 2^11.5 (rounded), built on the
+    device by the library itself.  Each permutation is timed end to end (median); effective GB/s counts
+    32 bytes per non-zero (read LIV + value, write LIV + value)."""
+    import itertools
+    I, J, K, LL, I2, J2 = 0, 1, 2, 3, 4, 5
+
+    def up(c, v):
+        return lco.lco_create(ctx, [n, n], torch.from_numpy(c.view(np.int64).reshape(-1).copy()).to("cuda:0"),
+                              torch.from_numpy(v).to("cuda:0"), lco.LCO_COORDS)
+
+    d = up(*L.fd_first_derivative(n))
+    delta = up(*L.diagonal(2, n, np.ones(n)))
+    by = lco.lco_contract(ctx, d, [I, I2], delta, [J, LL], [I, I2, J, LL])
+    ty = lco.lco_contract(ctx, by, [I, I2, J, LL], d, [I2, K], [I, J, LL, K])
+    by.destroy()
+    bx = lco.lco_contract(ctx, d, [J, J2], delta, [I, K], [J, J2, I, K])
+    tx = lco.lco_contract(ctx, bx, [J, J2, I, K], d, [J2, LL], [J, I, K, LL])
+    bx.destroy()
+    a = lco.lco_add(ctx, ty, [I, J, LL, K], tx, [J, I, K, LL], [I, J, K, LL])
+    for t in (ty, tx, d, delta):
+        t.destroy()
+    nnz = a.nnz
+    rows = []
+    for perm in itertools.permutations(range(4)):
+        if perm == (0, 1, 2, 3):
+            continue
+        plan = lco.lco_plan_permute([n] * 4, list(perm), nnz).as_dict()
+        P = lco.lco_permute(ctx, a, list(perm))
+        ctx.synchronize()
+        P.destroy()
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = lco.lco_permute(ctx, a, list(perm))
+            ctx.synchronize()
+            t.append((time.perf_counter() - t0) * 1e3)
+            P.destroy()
+        ms = statistics.median(t)
+        rows.append({"perm": "{" + ",".join(map(str, perm)) + "}", "ms": ms,
+                     "effective_GBps": 32.0 * nnz / (ms * 1e-3) / 1e9, "method": plan["method"],
+                     "key_bits": plan["key_bits"], "passes": plan["passes"]})
+    a.destroy()
+    by_perm = {r["perm"]: r for r in rows}
+    ms_sorted = sorted(r["ms"] for r in rows)
+    paper = {"{3,1,2,0}": 3.54, "{2,1,3,0}": 3.45, "{1,0,2,3}": 1.38}
+    return {"workload": f"combinatorial Laplacian a_ijkl (Section 2), n = {n} (2^11.5 rounded), "
+                        "all 23 non-identity permutations",
+            "n": n, "nnz": nnz, "reps": reps,
+            "min_ms": ms_sorted[0], "median_ms": ms_sorted[len(ms_sorted) // 2], "max_ms": ms_sorted[-1],
+            "paper_rows": {p: {"ms": by_perm[p]["ms"], "effective_GBps": by_perm[p]["effective_GBps"],
+                               "paper_RP_s_E8400": paper[p]} for p in paper},
+            "perms": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,6 +654,8 @@ def main():
     ap.add_argument("--hyper-reps", type=int, default=5, help="repetitions of the hyper-sparse leg (0: skip)")
     ap.add_argument("--app-n", type=int, default=2047, help="image side of the combinatorial Laplacian leg")
     ap.add_argument("--app-reps", type=int, default=5, help="repetitions of the Laplacian leg (0: skip)")
+    ap.add_argument("--rp-n", type=int, default=2896, help="side of the Laplacian in the permutation-table leg")
+    ap.add_argument("--rp-reps", type=int, default=3, help="repetitions per permutation in that leg (0: skip)")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -607,6 +666,7 @@ def main():
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--app-only", action="store_true", help="run only the combinatorial Laplacian leg")
+    ap.add_argument("--rp-only", action="store_true", help="run only the permutation-table leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -628,6 +688,9 @@ def main():
     if args.app_only:
         print(json.dumps({"laplacian": app_leg(lco, ctx, torch, np, L, args.app_n, max(1, args.app_reps))}),
               flush=True)
+        return
+    if args.rp_only:
+        print(json.dumps({"rp_table": rp_leg(lco, ctx, torch, np, L, args.rp_n, max(1, args.rp_reps))}), flush=True)
         return
     coords, vals = L.fd_laplacian(SIDE, 3)
     idx_d = torch.from_numpy(coords.view(np.int64).reshape(-1).copy()).to("cuda:0")
@@ -731,6 +794,8 @@ def main():
         out["hyper_sparse"] = hyper_leg(lco, ctx, torch, np, L, args.hyper_reps)
     if args.app_reps > 0:
         out["laplacian"] = app_leg(lco, ctx, torch, np, L, args.app_n, args.app_reps)
+    if args.rp_reps > 0:
+        out["rp_table"] = rp_leg(lco, ctx, torch, np, L, args.rp_n, args.rp_reps)
     if args.batch_count > 0:
         out["batched"] = batched_leg(lco, ctx, torch, np, L, args.batch_count, args.batch_reps)
     if args.serve_seconds > 0:

@@ -269,7 +269,17 @@ __device__ int64_t seg_start_at_or_after(const uint64_t* __restrict__ livs, int6
   if (x >= n) return n;
   const uint64_t s = fd_div(seg_div, livs[x]);
   if (x == 0 || fd_div(seg_div, livs[x - 1]) != s) return x;
-  int64_t lo = x, hi = n;  // livs[lo] lies in segment s; the answer lies in (lo, hi]
+  // gallop forward to bracket the segment's end, then bisect: the number of
+  // dependent loads grows with the log of the segment's length, not of n
+  int64_t lo = x, hi = n, step = 1;  // livs[lo] lies in segment s; the answer lies in (lo, hi]
+  while (lo + step < n) {
+    if (fd_div(seg_div, livs[lo + step]) != s) {
+      hi = lo + step;
+      break;
+    }
+    lo += step;
+    step *= 2;
+  }
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
     if (fd_div(seg_div, livs[mid]) == s) lo = mid;
@@ -320,6 +330,101 @@ __global__ __launch_bounds__(kLdsThreads) void rx_segmented_kernel(
   for (int i = threadIdx.x; i < valid; i += kLdsThreads) {
     out_livs[s0 + i] = s_liv[i];
     out_vals[s0 + i] = s_val[i];
+  }
+}
+
+// Segmented permutation for short segments: every entry of a segment of at
+// most kSmallSeg entries finds its place directly, as the segment's start plus
+// the number of the segment's entries with a smaller (key, input position).
+// Segments stay where they are (they are the leading resting modes), so one
+// read and one write per entry suffice.  Tiles hold the segments that start in
+// a nominal range of kSegTile / 2 entries.  Sets *overflow if a tile exceeds
+// kSegTile entries or holds a longer segment.
+constexpr int kSegThreads = 512;
+constexpr int kSegItems = 8;
+constexpr int kSegTile = kSegThreads * kSegItems;  // 4096
+constexpr int kSmallSeg = 32;
+
+__global__ __launch_bounds__(kSegThreads) void rx_smallseg_kernel(
+    const uint64_t* __restrict__ livs, const double* __restrict__ vals, int64_t n, ShuffleParams sp,
+    FastDiv seg_div, FastDiv key_div, uint64_t key_range, int64_t nominal, uint64_t* __restrict__ out_livs,
+    double* __restrict__ out_vals, uint32_t* __restrict__ overflow) {
+  __shared__ uint64_t s_a[kSegTile];  // tile-relative keys, then the output LIVs
+  __shared__ uint64_t s_b[kSegTile];  // tile-relative segment ids, then the output values
+  __shared__ int64_t bounds[2];
+  __shared__ int too_long;
+  if (threadIdx.x < 2)
+    bounds[threadIdx.x] = seg_start_at_or_after(livs, n, seg_div, ((int64_t)blockIdx.x + threadIdx.x) * nominal);
+  if (threadIdx.x == 0) too_long = 0;
+  __syncthreads();
+  const int64_t s0 = bounds[0], s1 = bounds[1];
+  const int64_t len64 = s1 - s0;
+  if (len64 <= 0) return;
+  if (len64 > kSegTile) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  const int len = (int)len64;
+  const uint64_t seg_first = fd_div(seg_div, livs[s0]);
+  const uint64_t key_base = seg_first * key_range;
+  uint64_t lv[kSegItems], key[kSegItems], sg[kSegItems];
+  double vv[kSegItems];
+#pragma unroll
+  for (int it = 0; it < kSegItems; ++it) {
+    const int e = threadIdx.x + it * kSegThreads;
+    lv[it] = 0;
+    key[it] = 0;
+    sg[it] = 0;
+    vv[it] = 0.0;
+    if (e < len) {
+      const uint64_t old = livs[s0 + e];
+      lv[it] = shuffle_liv(sp, old);
+      vv[it] = vals[s0 + e];
+      sg[it] = fd_div(seg_div, old) - seg_first;
+      key[it] = fd_div(key_div, lv[it]) - key_base;
+      s_a[e] = key[it];
+      s_b[e] = sg[it];
+    }
+  }
+  __syncthreads();
+  int pos[kSegItems];
+#pragma unroll
+  for (int it = 0; it < kSegItems; ++it) {
+    const int e = threadIdx.x + it * kSegThreads;
+    pos[it] = 0;
+    if (e < len) {
+      int lo = e, hi = e + 1;
+      while (lo > 0 && e - lo < kSmallSeg && s_b[lo - 1] == sg[it]) --lo;
+      while (hi < len && hi - lo <= kSmallSeg && s_b[hi] == sg[it]) ++hi;
+      if (hi - lo > kSmallSeg || (lo > 0 && s_b[lo - 1] == sg[it])) {
+        too_long = 1;
+      } else {
+        int r = lo;
+        for (int j = lo; j < hi; ++j) {
+          const uint64_t kj = s_a[j];
+          r += (kj < key[it] || (kj == key[it] && j < e)) ? 1 : 0;
+        }
+        pos[it] = r;
+      }
+    }
+  }
+  __syncthreads();
+  if (too_long) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+#pragma unroll
+  for (int it = 0; it < kSegItems; ++it) {
+    const int e = threadIdx.x + it * kSegThreads;
+    if (e < len) {
+      s_a[pos[it]] = lv[it];
+      s_b[pos[it]] = (uint64_t)__double_as_longlong(vv[it]);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < len; i += kSegThreads) {
+    out_livs[s0 + i] = s_a[i];
+    out_vals[s0 + i] = __longlong_as_double((long long)s_b[i]);
   }
 }
 
@@ -445,10 +550,19 @@ void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_val
 
 bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
                        double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
-                       const FastDiv& key_div, uint64_t key_range) {
+                       const FastDiv& key_div, uint64_t key_range, bool small_first) {
   if (n <= 0) return true;
   Scratch s(ctx);
   uint64_t* word = s.get<uint64_t>(1);  // the kernel ORs its flag into the low half
+  if (small_first) {
+    memset_async(ctx, word, 0, sizeof(uint64_t));
+    const int64_t nominal = kSegTile / 2;
+    const int64_t tiles = (n + nominal - 1) / nominal;
+    LCO_LAUNCH(ctx, "rx_smallseg", rx_smallseg_kernel, tiles, kSegThreads, 0, in_livs, in_vals, n, shuffle, seg_div,
+               key_div, key_range, nominal, out_livs, out_vals, (uint32_t*)word);
+    const uint64_t* words[1] = {word};
+    if (readback(ctx, words, 1)[0] == 0) return true;
+  }
   memset_async(ctx, word, 0, sizeof(uint64_t));
   const int64_t nominal = kLdsTile / 2;
   const int64_t tiles = (n + nominal - 1) / nominal;
@@ -478,8 +592,10 @@ void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, 
       radix_sort_pairs(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp, kp, plan.sort_bits, cap);
       return;
     case 3:
-      if (segmented_permute(ctx, in->livs, in->vals, out_livs, out_vals, n, sp, make_fastdiv(plan.pub.seg_div),
-                            kp.key_div, plan.pub.key_range))
+      // segments larger than a tile on average: some segment is, and the tile sort would only give up
+      if (plan.avg_segment <= (double)kLdsTile &&
+          segmented_permute(ctx, in->livs, in->vals, out_livs, out_vals, n, sp, make_fastdiv(plan.pub.seg_div),
+                            kp.key_div, plan.pub.key_range, plan.avg_segment <= 8.0))
         return;
       radix_sort_pairs(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp, kp, plan.sort_bits, cap);
       return;

@@ -152,6 +152,7 @@ struct RpDetail {
   uint64_t new_dims[LCO_MAX_ORDER];
   uint64_t new_weight_of_input_mode[LCO_MAX_ORDER];  // W'_{perm^-1[q]}
   int sort_bits;                                     // bits sorted by the chosen method
+  double avg_segment = 0;                            // non-zeros per possible segment (segmented method)
 };
 RpDetail plan_permute(int order, const uint64_t* dims, const int* perm, int64_t nnz, int digit_cap);
 
@@ -221,9 +222,12 @@ void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_val
 void shuffle_copy(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
                   double* out_vals, int64_t n, const ShuffleParams* shuffle);
 // Segmented permutation: returns false (and does nothing) if a segment exceeds the tile capacity.
+// With `small_first`, segments are first assumed to hold at most 32 entries each
+// and are ranked directly; a longer segment sends the whole permutation to the
+// tile sort.
 bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
                        double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
-                       const FastDiv& key_div, uint64_t key_range);
+                       const FastDiv& key_div, uint64_t key_range, bool small_first);
 int default_digit_cap();
 
 // permutation of a tensor's storage according to a plan

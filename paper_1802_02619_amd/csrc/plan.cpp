@@ -120,6 +120,7 @@ RpDetail plan_permute(int order, const uint64_t* dims, const int* perm, int64_t 
   } else {
     pub.method = 3;  // falls back to 4 at run time when a segment exceeds a tile
     d.sort_bits = bits_of_range(above);
+    d.avg_segment = (double)nnz / (double)nseg;
   }
   if (digit_cap < 1) digit_cap = 8;
   pub.passes = d.sort_bits ? (d.sort_bits + digit_cap - 1) / digit_cap : 0;

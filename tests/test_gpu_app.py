@@ -110,3 +110,59 @@ def test_design_tensor_full_size_closed_form(lco_lib, gpu_ctx):
     print(f"nnz by={by.nnz} ty={ty.nnz} a={a.nnz}", flush=True)
     for t in (by, ty, bx, tx, a, d, delta):
         t.destroy()
+
+
+def design_tensor_ijkl(lco, ctx, n):
+    """a_ijkl (modes in the order i, j, k, l), as the permutation experiment of Section 4.2 uses it."""
+    d, delta = operands(lco, ctx, n)
+    by, ty, bx, tx, a = design_tensor(lco, ctx, d, delta)
+    a2 = lco.lco_add(ctx, ty, [I, J, LL, K], tx, [J, I, K, LL], [I, J, K, LL])
+    for t in (by, ty, bx, tx, a, d, delta):
+        t.destroy()
+    return a2
+
+
+def test_design_tensor_permutations_vs_oracle(lco_lib, gpu_ctx, oracle_mod):
+    import itertools
+    n = 15
+    a = design_tensor_ijkl(lco_lib, gpu_ctx, n)
+    _, livs, vals = a.to_numpy()
+    oa = oracle_mod.Tensor(np.array([n] * 4, np.uint64), livs, vals)
+    for perm in itertools.permutations(range(4)):
+        print(f"permute design tensor n={n} perm={perm}", flush=True)
+        p = lco_lib.lco_permute(gpu_ctx, a, list(perm))
+        same(p, oracle_mod.permute(oa, list(perm)), str(perm))
+        p.destroy()
+    a.destroy()
+
+
+def test_design_tensor_permutations_full_size(lco_lib, gpu_ctx):
+    """n = 2896 (2^11.5 rounded, the size of the paper's permutation table): every
+    permutation followed by its inverse gives the tensor back bit for bit and a
+    strictly increasing LIV list; the three permutations of the table are also
+    checked entry by entry against numpy (decode, move coordinates, re-linearise,
+    sort)."""
+    import itertools
+    n = 2896
+    print(f"permute design tensor n={n}", flush=True)
+    a = design_tensor_ijkl(lco_lib, gpu_ctx, n)
+    _, livs, vals = a.to_numpy()
+    nn = np.uint64(n)
+    coords = [(livs // nn**q) % nn for q in range(4)]
+    for perm in itertools.permutations(range(4)):
+        if perm == (0, 1, 2, 3):
+            continue
+        inv = [perm.index(q) for q in range(4)]
+        p = lco_lib.lco_permute(gpu_ctx, a, list(perm))
+        back = lco_lib.lco_permute(gpu_ctx, p, inv)
+        _, pl, pv = p.to_numpy()
+        _, bl, bv = back.to_numpy()
+        assert np.all(pl[1:] > pl[:-1]), perm
+        assert np.array_equal(bl, livs) and np.array_equal(bv.view(np.uint64), vals.view(np.uint64)), perm
+        if perm in ((3, 1, 2, 0), (2, 1, 3, 0), (1, 0, 2, 3)):
+            want = coords[perm[0]] + nn * (coords[perm[1]] + nn * (coords[perm[2]] + nn * coords[perm[3]]))
+            o = np.argsort(want, kind="stable")
+            assert np.array_equal(pl, want[o]) and np.array_equal(pv.view(np.uint64), vals[o].view(np.uint64))
+        p.destroy()
+        back.destroy()
+    a.destroy()

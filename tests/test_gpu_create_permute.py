@@ -111,6 +111,47 @@ def test_permute_segmented_paths(lco_lib, gpu_ctx, oracle_mod):
     big = [400, 300, 3]                 # regions of constant mode 2 hold ~67k entries
     coords, vals = L.random_sparse(rng, big, 200000)
     _perm_case(lco_lib, gpu_ctx, oracle_mod, big, coords, vals, [(1, 0, 2)])
+    # regions of 2,300 entries on average, but one of 9,000: the tile sort is tried, gives up, and the
+    # global passes run
+    dims = [100, 100, 10]
+    c0, _ = L.random_sparse(rng, [100, 100], 9000)
+    c1, _ = L.random_sparse(rng, [100, 100, 9], 21000)
+    coords = np.concatenate([np.concatenate([c0, np.zeros((9000, 1), np.uint64)], axis=1),
+                             c1 + np.array([0, 0, 1], dtype=np.uint64)])
+    vals = rng.uniform(-1, 1, len(coords))
+    lco_lib.lco_timing_reset(gpu_ctx)
+    lco_lib.lco_timing_enable(gpu_ctx, True)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(1, 0, 2)])
+    lco_lib.lco_timing_enable(gpu_ctx, False)
+    launched = {k for k in lco_lib.lco_timing_kernels(gpu_ctx) if lco_lib.lco_timing_query(gpu_ctx, k)[0]}
+    lco_lib.lco_timing_reset(gpu_ctx)
+    assert {"rx_segmented", "rx_scatter"} <= launched
+
+
+def test_permute_short_segments(lco_lib, gpu_ctx, oracle_mod):
+    """Segments of constant leading resting modes that hold a few entries each are
+    ranked directly: a ragged last tile, equal keys inside a segment (a trailing
+    resting mode below the key: the sort must be stable), and a tensor whose
+    segments are short on average but one holds 60 entries (the tile sort takes
+    over)."""
+    rng = np.random.default_rng(12)
+    dims = [6, 5, 70, 90]  # 6300 segments of constant (mode 2, mode 3), ~4.8 entries each
+    coords, vals = L.random_sparse(rng, dims, 30001)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(1, 0, 2, 3)])
+    dims = [3, 4, 5, 40, 50]  # key (mode 2, mode 1) above the resting mode 0
+    coords, vals = L.random_sparse(rng, dims, 12000)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(0, 2, 1, 3, 4), (2, 1, 0, 3, 4)])
+    full = np.array([(a, b, c, 7, 9) for a in range(3) for b in range(4) for c in range(5)], dtype=np.uint64)
+    keep = ~((coords[:, 3] == 7) & (coords[:, 4] == 9))
+    coords = np.concatenate([coords[keep], full])
+    vals = np.concatenate([vals[keep], rng.uniform(-1, 1, len(full))])
+    lco_lib.lco_timing_reset(gpu_ctx)
+    lco_lib.lco_timing_enable(gpu_ctx, True)
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(0, 2, 1, 3, 4)])
+    lco_lib.lco_timing_enable(gpu_ctx, False)
+    launched = {k for k in lco_lib.lco_timing_kernels(gpu_ctx) if lco_lib.lco_timing_query(gpu_ctx, k)[0]}
+    lco_lib.lco_timing_reset(gpu_ctx)
+    assert {"rx_smallseg", "rx_segmented"} <= launched  # the direct ranking gave up, the tile sort ran
 
 
 def test_permute_size_one_modes_and_empty(lco_lib, gpu_ctx, oracle_mod):
