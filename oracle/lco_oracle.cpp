@@ -17,7 +17,9 @@
 //  * Permutation uses transpose semantics: output mode r is input mode perm[r];
 //    the output is sorted in the default order of the permuted dimensions.
 //  * Contraction follows Einstein notation (Section 2, y_ij = a_ijkl x_kl):
-//    labels shared by the operands and absent from the output are summed; each
+//    labels shared by the operands and absent from the output are summed; a
+//    label in both operands and in the output is entrywise (the product is
+//    taken only between entries that agree on it, and it is not summed); each
 //    output entry accumulates its products in ascending order of the first
 //    operand's LIV, and for each first-operand entry in ascending order of the
 //    second operand's LIV, starting from 0.0.  Every structural non-zero (any
@@ -223,13 +225,18 @@ void* ora_contract(int oa, const uint64_t* da, int64_t na, const uint64_t* la, c
   for (int i = 0; i < oa; ++i) if (find(i, laba, laba[i]) >= 0) { res->status = ORA_E_UNSUPPORTED; return res; }
   for (int i = 0; i < ob; ++i) if (find(i, labb, labb[i]) >= 0) { res->status = ORA_E_UNSUPPORTED; return res; }
   for (int i = 0; i < oc; ++i) if (find(i, labc, labc[i]) >= 0) { res->status = ORA_E_ARG; return res; }
-  // output sources: (operand, mode)
+  // output sources: (operand, mode); an entrywise label is read from the first operand
   std::vector<int> src_op(oc), src_mode(oc);
+  std::vector<int> ea, eb;  // entrywise labels: mode in a, mode in b
+  std::vector<uint64_t> ed;
   res->dims.resize(oc);
   for (int r = 0; r < oc; ++r) {
     int ia = find(oa, laba, labc[r]), ib = find(ob, labb, labc[r]);
-    if (ia >= 0 && ib >= 0) { res->status = ORA_E_UNSUPPORTED; return res; }  // entrywise
     if (ia < 0 && ib < 0) { res->status = ORA_E_ARG; return res; }
+    if (ia >= 0 && ib >= 0) {
+      if (da[ia] != db[ib]) { res->status = ORA_E_SHAPE; return res; }
+      ea.push_back(ia); eb.push_back(ib); ed.push_back(da[ia]);
+    }
     src_op[r] = ia >= 0 ? 0 : 1;
     src_mode[r] = ia >= 0 ? ia : ib;
     res->dims[r] = ia >= 0 ? da[ia] : db[ib];
@@ -247,9 +254,11 @@ void* ora_contract(int oa, const uint64_t* da, int64_t na, const uint64_t* la, c
   }
   for (int j = 0; j < ob; ++j)
     if (find(oc, labc, labb[j]) < 0 && find(oa, laba, labb[j]) < 0) { res->status = ORA_E_UNSUPPORTED; return res; }
+  // the join key: contracted labels (in a's order), then entrywise labels
+  for (size_t t = 0; t < ea.size(); ++t) { ka.push_back(ea[t]); kb.push_back(eb[t]); kd.push_back(ed[t]); }
   const int nk = (int)ka.size();
-  // index the second operand by its contracted coordinates; entries are pushed
-  // in ascending LIV order, so each list is ascending
+  // index the second operand by its join coordinates; entries are pushed in
+  // ascending LIV order, so each list is ascending
   std::map<uint64_t, std::vector<int64_t>> bidx;
   std::vector<uint64_t> bco((size_t)nb * ob);
   std::vector<uint64_t> kc(nk);

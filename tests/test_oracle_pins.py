@@ -198,6 +198,51 @@ def test_all_matchings_vs_einsum(oracle_mod, n):
         assert np.array_equal(got_patt, patt)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_entrywise_labels_vs_einsum(oracle_mod, n):
+    """Every matching of the modes of two order-n tensors, each matched pair either
+    summed (contracted) or kept in the output (entrywise: the product pairs only
+    entries that agree on it, as numpy einsum does with a label in both inputs and
+    the output), in two output orders; values and structural pattern."""
+    rng = np.random.default_rng(40 + n)
+    letters = "abcdefghij"
+    cases = 0
+    for match in matchings(n):
+        for roles in itertools.product((0, 1), repeat=len(match)):  # 1: entrywise
+            dims_a = [int(x) for x in rng.integers(1, 5, n)]
+            dims_b = [int(x) for x in rng.integers(1, 5, n)]
+            for (ia, ib) in match:
+                dims_b[ib] = dims_a[ia]
+            ca, va = L.random_sparse(rng, dims_a, 14, integer_values=True)
+            cb, vb = L.random_sparse(rng, dims_b, 14, integer_values=True)
+            a = oracle_mod.create(dims_a, ca, va)
+            b = oracle_mod.create(dims_b, cb, vb)
+            la = list(range(n))
+            lb = [n + j for j in range(n)]
+            for (ia, ib) in match:
+                lb[ib] = la[ia]
+            matched_a = {ia: r for (ia, _), r in zip(match, roles)}
+            matched_b = {ib for _, ib in match}
+            lc = [la[i] for i in range(n) if i not in matched_a or matched_a[i] == 1] + \
+                 [lb[j] for j in range(n) if j not in matched_b]
+            for order in (lc, lc[::-1]):
+                c = oracle_mod.contract(a, la, b, lb, order)
+                spec = "".join(letters[x] for x in la) + "," + "".join(letters[x] for x in lb) + "->" + \
+                    "".join(letters[x] for x in order)
+                Da = dense_from_coords(dims_a, ca, va)
+                Db = dense_from_coords(dims_b, cb, vb)
+                assert np.array_equal(dense_of(c), np.einsum(spec, Da, Db)), (match, roles, order)
+                patt = np.einsum(spec, (Da != 0).astype(np.float64), (Db != 0).astype(np.float64)) > 0
+                got_patt = np.zeros_like(patt)
+                if c.nnz and patt.ndim:
+                    got_patt[np.unravel_index(c.livs.astype(np.int64), patt.shape, order="F")] = True
+                elif c.nnz:
+                    got_patt[()] = True
+                assert np.array_equal(got_patt, patt), (match, roles, order)
+                cases += 1
+    assert cases == 2 * sum(2 ** len(m) for m in matchings(n))
+
+
 def test_map_and_sort_modes_agree(oracle_mod):
     rng = np.random.default_rng(3)
     dims = [7, 5, 6]
@@ -218,8 +263,11 @@ def test_contract_errors(oracle_mod):
         oracle_mod.contract(a, [0, 1], b, [1, 2], [0, 2])
     assert e.value.code == 3  # contracted dims 4 vs 5
     with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.contract(a, [0, 1], b, [2, 3], [0, 2, 3])
+    assert e.value.code == 7  # a label of a in neither b nor the output (a summed free label)
+    with pytest.raises(oracle_mod.OracleError) as e:
         oracle_mod.contract(a, [0, 1], b, [0, 2], [0, 1, 2])
-    assert e.value.code == 7  # entrywise label
+    assert e.value.code == 3  # entrywise label with dims 3 vs 5
 
 
 def test_diagonal_products(oracle_mod):
