@@ -175,23 +175,28 @@ typedef struct {
   int permute_a, permute_b;         /* 1 if that operand is rearranged before multiplying */
   int permute_c;                    /* 1 if the product is rearranged into c_labels order */
   int num_contracted;               /* number of contracted labels */
+  int num_entrywise;                /* number of entrywise labels (in a, b and the output) */
 } lco_plan;
 
 /* Einstein-notation product (Section 2; Section 5.2's three steps).
  * `a_labels` / `b_labels` (host) name the modes of a and b; `c_labels` (host,
  * c_order entries, 0 <= c_order) name the output modes in output order.  A
  * label in both inputs and not in the output is contracted; a label in exactly
- * one input and in the output is free.  Each output entry sums its products in
- * ascending order of the contracted index (contracted modes linearised in the
- * order they occur in a), starting from 0.0; every structural non-zero is kept.
+ * one input and in the output is free; a label in both inputs and in the output
+ * is entrywise: entries are multiplied only where they agree on it, and it is
+ * not summed (batched products such as c_hik = a_hij b_hjk; the product is then
+ * block diagonal, and the operand on the engine's row side is re-sorted into
+ * that form).  Each output entry sums its products in ascending order of the
+ * contracted index (contracted modes linearised in the order they occur in a),
+ * starting from 0.0; every structural non-zero is kept.
  * flags & LCO_FORCE_MASK forces an lco_algo instead of the table's choice.
  * Synchronises the stream once per data-dependent size (output nnz; product
  * count for the outer-product and long-row paths).
  * Errors: LCO_E_ARG (labels malformed, label repeated within an operand or in
- * the output), LCO_E_SHAPE, LCO_E_OVERFLOW (output dimension product > 2^64),
- * LCO_E_UNSUPPORTED (a label in both inputs and the output -- entrywise
- * product --, a free label absent from the output, or a matricised side of
- * exactly 2^64), LCO_E_OOM. */
+ * the output), LCO_E_SHAPE (contracted or entrywise modes of different
+ * dimensions), LCO_E_OVERFLOW (output dimension product > 2^64),
+ * LCO_E_UNSUPPORTED (a free label absent from the output, a matricised side of
+ * 2^64 or more, or a block-diagonal operand form beyond 2^64), LCO_E_OOM. */
 lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tensor b, const int* b_labels,
                         int c_order, const int* c_labels, uint32_t flags, lco_tensor* out);
 
@@ -229,12 +234,13 @@ typedef struct {
 
 /* Batched products: outs[i] receives the product of descs[i], bit-identical to
  * what lco_contract returns for the same arguments.  Instances whose plan is
- * CSR/CSC/CSRNA/CSCNA (after any operand rearrangement) and whose rows of A'
- * each have at most 64 products run together, every phase as one launch over
- * all of them, with two stream synchronisations for the whole batch; outputs of
- * those instances share one device allocation that is released with the last
- * of them.  Other instances (doubly compressed, outer product, long rows) run
- * through the per-call path.  Errors are those of lco_contract; on error no
+ * CSR/CSC/CSRNA/CSCNA (after any operand rearrangement), that have no
+ * entrywise label and whose rows of A' each have at most 64 products run
+ * together, every phase as one launch over all of them, with two stream
+ * synchronisations for the whole batch; outputs of those instances share one
+ * device allocation that is released with the last of them.  Other instances
+ * (doubly compressed, outer product, entrywise, long rows) run through the
+ * per-call path.  Errors are those of lco_contract; on error no
  * output handle survives. */
 lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs);
 /* How many instances of the last lco_contract_batch call ran batched / per call. */

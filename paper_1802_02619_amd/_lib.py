@@ -52,7 +52,7 @@ class Plan(ctypes.Structure):
                 ("nnz_a", ctypes.c_int64), ("nnz_b", ctypes.c_int64),
                 ("a_class", ctypes.c_int), ("b_class", ctypes.c_int), ("algo", ctypes.c_int),
                 ("permute_a", ctypes.c_int), ("permute_b", ctypes.c_int), ("permute_c", ctypes.c_int),
-                ("num_contracted", ctypes.c_int)]
+                ("num_contracted", ctypes.c_int), ("num_entrywise", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

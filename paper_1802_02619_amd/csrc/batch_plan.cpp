@@ -159,10 +159,10 @@ lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc
       plans[i] = plan_contract(x.a->order, x.a->dims, x.a_labels, x.a->nnz, x.b->order, x.b->dims, x.b_labels,
                                x.b->nnz, x.c_order, x.c_labels, x.flags);
       const int algo = plans[i].pub.algo;
-      if (!plans[i].empty && algo != LCO_ALG_CSR && algo != LCO_ALG_CSC && algo != LCO_ALG_CSRNA &&
-          algo != LCO_ALG_CSCNA)
+      if (!plans[i].empty && ((algo != LCO_ALG_CSR && algo != LCO_ALG_CSC && algo != LCO_ALG_CSRNA &&
+                               algo != LCO_ALG_CSCNA) || plans[i].n_entrywise))
         fail(LCO_E_UNSUPPORTED, "lco_batch_plan_create: instance " + std::to_string(i) +
-                                    " is not a singly compressed row or column product");
+                                    " is not a singly compressed row or column product without entrywise modes");
     }
     // operands in the layout each product needs (one rearranged copy per tensor and order)
     std::map<std::pair<const void*, std::vector<int>>, lco_tensor> rearranged;

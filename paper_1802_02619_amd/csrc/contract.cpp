@@ -30,27 +30,49 @@ lco_tensor permuted(lco_ctx ctx, const lco_tensor_s* in, const int* perm) {
   return t;
 }
 
+// An operand re-sorted into its block-diagonal matricised form (entrywise modes
+// counted with its rows and with its columns): the LIV shuffle takes arbitrary
+// weights, and the sort runs over the whole new LIV.  The result is a plain
+// array of (LIV, value) pairs handed to the engines (its "dims" are the two
+// matricised sides).
+lco_tensor block_diagonal(lco_ctx ctx, const lco_tensor_s* in, const ContractDetail& d) {
+  lco_tensor t = new_tensor(ctx, 2, d.dup_dims, in->nnz);
+  try {
+    if (in->nnz) {
+      const ShuffleParams sp = make_shuffle(in->order, in->dims, d.dup_weight);
+      KeyParams kp;
+      radix_sort_pairs(ctx, in->livs, in->vals, t->livs, t->vals, in->nnz, &sp, kp, d.dup_bits,
+                       default_digit_cap());
+    }
+  } catch (...) {
+    lco_destroy(t);
+    throw;
+  }
+  return t;
+}
+
 lco_tensor contract_run(lco_ctx ctx, const lco_tensor_s* a, const lco_tensor_s* b, const ContractDetail& d) {
   if (d.empty) return new_tensor(ctx, d.order_c, d.c_dims, 0);
   Owned ta, tb;
   const lco_tensor_s* A = a;
   const lco_tensor_s* B = b;
-  if (d.pub.permute_a) A = ta.t = permuted(ctx, a, d.perm_a);
-  if (d.pub.permute_b) B = tb.t = permuted(ctx, b, d.perm_b);
-  const uint64_t m = d.pub.m, k = d.pub.k, n = d.pub.n;
+  if (d.dup == 1) A = ta.t = block_diagonal(ctx, a, d);
+  else if (d.pub.permute_a) A = ta.t = permuted(ctx, a, d.perm_a);
+  if (d.dup == 2) B = tb.t = block_diagonal(ctx, b, d);
+  else if (d.pub.permute_b) B = tb.t = permuted(ctx, b, d.perm_b);
   Owned natural;
   switch (d.pub.algo) {
     case LCO_ALG_CSR:
     case LCO_ALG_DCSR:
     case LCO_ALG_CSRNA:
-      natural.t = row_engine(ctx, A, B, m, k, n, d.pub.algo != LCO_ALG_DCSR, d.pub.algo != LCO_ALG_CSRNA,
+      natural.t = row_engine(ctx, A, B, d.em, d.ek, d.en, d.pub.algo != LCO_ALG_DCSR, d.pub.algo != LCO_ALG_CSRNA,
                              d.order_c, d.natural_dims);
       break;
     case LCO_ALG_CSC:
     case LCO_ALG_DCSC:
     case LCO_ALG_CSCNA:
       // column by column: C^T = B^T A^T row by row over the same arrays
-      natural.t = row_engine(ctx, B, A, n, k, m, d.pub.algo != LCO_ALG_DCSC, d.pub.algo != LCO_ALG_CSCNA,
+      natural.t = row_engine(ctx, B, A, d.em, d.ek, d.en, d.pub.algo != LCO_ALG_DCSC, d.pub.algo != LCO_ALG_CSCNA,
                              d.order_c, d.natural_dims);
       break;
     case LCO_ALG_SOP:
@@ -115,7 +137,7 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
       const int algo = d.pub.algo;
       const bool rowwise = algo == LCO_ALG_CSR || algo == LCO_ALG_CSRNA;
       const bool colwise = algo == LCO_ALG_CSC || algo == LCO_ALG_CSCNA;
-      if (!rowwise && !colwise) {
+      if ((!rowwise && !colwise) || d.n_entrywise) {
         percall.push_back(i);
         continue;
       }

@@ -178,7 +178,7 @@ int grid_for(lco_ctx ctx, int64_t n, int threads) {
 
 lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, const ContractDetail& d) {
   const int64_t na = A->nnz, nb = B->nnz;
-  const uint64_t m = d.pub.m, n = d.pub.n;
+  const uint64_t m = d.em, n = d.en;  // A' is m (free and entrywise) by k, B' is k by n (free)
   Scratch s(ctx);
   SopArgs sa;
   std::memset(&sa, 0, sizeof(sa));

@@ -171,6 +171,19 @@ struct ContractDetail {
   uint64_t free_a_dims[LCO_MAX_ORDER], free_b_dims[LCO_MAX_ORDER];
   uint64_t free_a_cweight[LCO_MAX_ORDER], free_b_cweight[LCO_MAX_ORDER];  // weight in the C LIV
   bool sop_simple_key = false;  // C LIV == i + m * j
+  // Entrywise modes (in a, b and the output): the product is block diagonal.
+  // The operand on the engine's row side (dup = 1: a, 2: b) is re-sorted by its
+  // block-diagonal matricised LIV, in which each entrywise mode appears with its
+  // rows and with its columns: the LIV is sum_q coord_q * dup_weight[q], below
+  // 2^dup_bits; the other operand is permuted as usual (perm_a / perm_b).
+  int n_entrywise = 0;
+  int dup = 0;
+  uint64_t dup_weight[LCO_MAX_ORDER];
+  uint64_t dup_dims[2];  // (contracted x E, rows x E) of the re-sorted operand
+  int dup_bits = 0;
+  // sizes handed to the engine: rows of its left operand, contracted, columns
+  // of its right operand (entrywise modes counted on the left only)
+  uint64_t em, ek, en;
 };
 ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
                              const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags);

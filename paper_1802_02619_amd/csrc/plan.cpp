@@ -165,9 +165,11 @@ static int family(int algo) {  // 0: column-by-column, 1: row-by-row, 2: outer p
 namespace {
 
 struct Layouts {
-  int pa[LCO_MAX_ORDER], pb[LCO_MAX_ORDER];
+  int pa[2 * LCO_MAX_ORDER], pb[2 * LCO_MAX_ORDER];  // operand modes, least significant first
   int natural[LCO_MAX_ORDER];  // natural product layout as a list of C positions
-  int na, nb, nc;
+  int na, nb, nc;              // layout lengths (an operand with entrywise modes lists them twice)
+  int dup = 0;                 // 1: A is block diagonal (entrywise modes twice), 2: B
+  uint64_t em = 0, ek = 0, en = 0;
   int cost;
   bool need_a, need_b, need_c;
 };
@@ -199,16 +201,25 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
   ContractDetail d;
   std::memset(&d, 0, sizeof(d));
   d.order_a = oa; d.order_b = ob; d.order_c = oc;
-  // free modes in output order
+  // output modes: free in a, free in b, or entrywise (in a, b and the output)
   int fa_c[LCO_MAX_ORDER], fb_c[LCO_MAX_ORDER];  // operand mode index, in C order
   int fa_cpos[LCO_MAX_ORDER], fb_cpos[LCO_MAX_ORDER];
-  int nfa = 0, nfb = 0;
+  int ea_c[LCO_MAX_ORDER], eb_c[LCO_MAX_ORDER], e_cpos[LCO_MAX_ORDER];
+  int nfa = 0, nfb = 0, ne = 0;
+  u128 cprod = 1;
   for (int r = 0; r < oc; ++r) {
     const int ia = find(oa, la, lc[r]), ib = find(ob, lb, lc[r]);
-    if (ia >= 0 && ib >= 0) fail(LCO_E_UNSUPPORTED, "contract: entrywise label (in a, b and the output)");
     if (ia < 0 && ib < 0) fail(LCO_E_ARG, "contract: output label not found in a or b");
-    if (ia >= 0) { fa_cpos[nfa] = r; fa_c[nfa++] = ia; d.c_dims[r] = da[ia]; }
-    else { fb_cpos[nfb] = r; fb_c[nfb++] = ib; d.c_dims[r] = db[ib]; }
+    if (ia >= 0 && ib >= 0) {
+      if (da[ia] != db[ib]) fail(LCO_E_SHAPE, "contract: entrywise modes differ in dimension");
+      ea_c[ne] = ia; eb_c[ne] = ib; e_cpos[ne++] = r; d.c_dims[r] = da[ia];
+    } else if (ia >= 0) {
+      fa_cpos[nfa] = r; fa_c[nfa++] = ia; d.c_dims[r] = da[ia];
+    } else {
+      fb_cpos[nfb] = r; fb_c[nfb++] = ib; d.c_dims[r] = db[ib];
+    }
+    cprod *= d.c_dims[r];
+    if (cprod > kTwo64) fail(LCO_E_OVERFLOW, "contract: output dimension product exceeds 2^64");
   }
   // contracted labels, in a's order and in b's order
   int ka_a[LCO_MAX_ORDER], ka_b[LCO_MAX_ORDER], nk = 0;  // kappa_A: (a index, b index)
@@ -230,49 +241,89 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
       if (i >= 0 && find(oc, lc, lb[j]) < 0) { kb_a[t] = i; kb_b[t] = j; ++t; }
     }
   }
-  u128 m = 1, k = 1, n = 1;
-  for (int t = 0; t < nfa; ++t) m *= da[fa_c[t]];
+  // entrywise modes in a's order and in b's order: (mode in a, mode in b, output position)
+  int eo_a[3][LCO_MAX_ORDER], eo_b[3][LCO_MAX_ORDER];
+  {
+    int t = 0;
+    for (int i = 0; i < oa; ++i)
+      for (int e = 0; e < ne; ++e)
+        if (ea_c[e] == i) { eo_a[0][t] = ea_c[e]; eo_a[1][t] = eb_c[e]; eo_a[2][t++] = e_cpos[e]; }
+    t = 0;
+    for (int j = 0; j < ob; ++j)
+      for (int e = 0; e < ne; ++e)
+        if (eb_c[e] == j) { eo_b[0][t] = ea_c[e]; eo_b[1][t] = eb_c[e]; eo_b[2][t++] = e_cpos[e]; }
+  }
+  // Matricised sizes.  With entrywise modes the product is block diagonal, one
+  // block per entrywise index: A is (free a x E) by (contracted x E), B is
+  // (contracted x E) by (free b x E).
+  u128 m = 1, k = 1, n = 1, h = 1, mf = 1, nf = 1;
+  for (int t = 0; t < nfa; ++t) mf *= da[fa_c[t]];
   for (int t = 0; t < nk; ++t) k *= da[ka_a[t]];
-  for (int t = 0; t < nfb; ++t) n *= db[fb_c[t]];
-  if (m * n > kTwo64) fail(LCO_E_OVERFLOW, "contract: output dimension product exceeds 2^64");
+  for (int t = 0; t < nfb; ++t) nf *= db[fb_c[t]];
+  for (int e = 0; e < ne; ++e) h *= da[ea_c[e]];
+  m = mf * h;
+  n = nf * h;
+  k = k * h;
   if (m >= kTwo64 || k >= kTwo64 || n >= kTwo64)
-    fail(LCO_E_UNSUPPORTED, "contract: a matricised side of exactly 2^64");
+    fail(LCO_E_UNSUPPORTED, "contract: a matricised side of 2^64 or more");
   lco_plan& pub = d.pub;
   pub.m = (uint64_t)m; pub.k = (uint64_t)k; pub.n = (uint64_t)n;
   pub.nnz_a = na; pub.nnz_b = nb;
   pub.num_contracted = nk;
+  pub.num_entrywise = ne;
   pub.a_class = classify(pub.m, pub.k, na);
   pub.b_class = classify(pub.k, pub.n, nb);
-  d.n_free_a = nfa; d.n_free_b = nfb; d.n_contracted = nk;
+  d.n_free_a = nfa; d.n_free_b = nfb; d.n_contracted = nk; d.n_entrywise = ne;
 
-  // Layout of each family for a given contracted order, and its rearrangement cost.
+  // Layout of each family for a given contracted order, and its rearrangement
+  // cost.  The operand that plays the engine's row side holds the entrywise
+  // modes twice (once with its rows, once with its columns, so that it is block
+  // diagonal); the other holds them once, after the contracted modes.
   auto layouts = [&](int fam, const int* kap_a, const int* kap_b) {
     Layouts L;
-    L.na = oa; L.nb = ob; L.nc = oc;
+    L.nc = oc;
     int ia = 0, ib = 0, ic = 0;
-    if (fam == 0) {  // column-major A (free, contracted), B (contracted, free)
+    const int(*eo)[LCO_MAX_ORDER] = fam == 0 ? eo_a : eo_b;  // entrywise order: that of the plain operand
+    if (fam == 0) {  // column by column: A (free, contracted, E) plain; B (contracted, E, free, E)
       for (int t = 0; t < nfa; ++t) L.pa[ia++] = fa_c[t];
       for (int t = 0; t < nk; ++t) L.pa[ia++] = kap_a[t];
+      for (int e = 0; e < ne; ++e) L.pa[ia++] = eo[0][e];
       for (int t = 0; t < nk; ++t) L.pb[ib++] = kap_b[t];
+      for (int e = 0; e < ne; ++e) L.pb[ib++] = eo[1][e];
       for (int t = 0; t < nfb; ++t) L.pb[ib++] = fb_c[t];
+      if (ne) for (int e = 0; e < ne; ++e) L.pb[ib++] = eo[1][e];
       for (int t = 0; t < nfa; ++t) L.natural[ic++] = fa_cpos[t];
       for (int t = 0; t < nfb; ++t) L.natural[ic++] = fb_cpos[t];
-    } else if (fam == 1) {  // row-major A (contracted, free), B (free, contracted)
+      L.dup = ne ? 2 : 0;
+      L.em = (uint64_t)n; L.ek = (uint64_t)k; L.en = (uint64_t)mf;
+    } else if (fam == 1) {  // row by row: A (contracted, E, free, E); B (free, contracted, E) plain
       for (int t = 0; t < nk; ++t) L.pa[ia++] = kap_a[t];
+      for (int e = 0; e < ne; ++e) L.pa[ia++] = eo[0][e];
       for (int t = 0; t < nfa; ++t) L.pa[ia++] = fa_c[t];
+      if (ne) for (int e = 0; e < ne; ++e) L.pa[ia++] = eo[0][e];
       for (int t = 0; t < nfb; ++t) L.pb[ib++] = fb_c[t];
       for (int t = 0; t < nk; ++t) L.pb[ib++] = kap_b[t];
+      for (int e = 0; e < ne; ++e) L.pb[ib++] = eo[1][e];
       for (int t = 0; t < nfb; ++t) L.natural[ic++] = fb_cpos[t];
       for (int t = 0; t < nfa; ++t) L.natural[ic++] = fa_cpos[t];
-    } else {  // outer product: column-major A and row-major B, free modes in their own order
+      L.dup = ne ? 1 : 0;
+      L.em = (uint64_t)m; L.ek = (uint64_t)k; L.en = (uint64_t)nf;
+    } else {  // outer product: A (free and E in a's order, contracted, E); B (free, contracted, E) plain
       for (int i = 0; i < oa; ++i) if (find(oc, lc, la[i]) >= 0) L.pa[ia++] = i;
       for (int t = 0; t < nk; ++t) L.pa[ia++] = kap_a[t];
-      for (int j = 0; j < ob; ++j) if (find(oc, lc, lb[j]) >= 0) L.pb[ib++] = j;
+      for (int e = 0; e < ne; ++e) L.pa[ia++] = eo[0][e];
+      for (int j = 0; j < ob; ++j) if (find(oc, lc, lb[j]) >= 0 && find(oa, la, lb[j]) < 0) L.pb[ib++] = j;
       for (int t = 0; t < nk; ++t) L.pb[ib++] = kap_b[t];
+      for (int e = 0; e < ne; ++e) L.pb[ib++] = eo[1][e];
       for (int r = 0; r < oc; ++r) L.natural[r] = r;  // the sort key is the output LIV itself
+      L.dup = ne ? 1 : 0;
+      L.em = (uint64_t)m; L.ek = (uint64_t)k; L.en = (uint64_t)nf;
     }
-    L.need_a = !is_identity(L.pa, oa);
-    L.need_b = !is_identity(L.pb, ob);
+    for (int e = 0; e < ne && fam != 2; ++e) L.natural[ic++] = eo[2][e];  // in the layout's entrywise order
+    L.na = ia;
+    L.nb = ib;
+    L.need_a = L.dup == 1 || !is_identity(L.pa, oa);
+    L.need_b = L.dup == 2 || !is_identity(L.pb, ob);
     L.need_c = !is_identity(L.natural, oc);
     L.cost = (int)L.need_a + (int)L.need_b + (int)L.need_c;
     return L;
@@ -302,8 +353,28 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
   pub.algo = algo;
   const int fam = family(algo);
   Layouts L = best(fam);
-  std::memcpy(d.perm_a, L.pa, sizeof(int) * oa);
-  std::memcpy(d.perm_b, L.pb, sizeof(int) * ob);
+  d.em = L.em; d.ek = L.ek; d.en = L.en;
+  d.dup = L.dup;
+  if (L.dup) {
+    // the block-diagonal operand: weight of each of its modes in its matricised LIV
+    const int* lay = L.dup == 1 ? L.pa : L.pb;
+    const int len = L.dup == 1 ? L.na : L.nb;
+    const uint64_t* dd = L.dup == 1 ? da : db;
+    u128 w = 1;
+    for (int r = 0; r < len; ++r) {
+      d.dup_weight[lay[r]] += (uint64_t)w;
+      w *= dd[lay[r]];
+      if (w > kTwo64) fail(LCO_E_UNSUPPORTED, "contract: block-diagonal form of an operand exceeds 2^64");
+    }
+    d.dup_bits = bits_of_range(w);
+    d.dup_dims[0] = (uint64_t)k;
+    d.dup_dims[1] = (uint64_t)(w / k);
+  } else {
+    std::memcpy(d.perm_a, L.pa, sizeof(int) * oa);
+    std::memcpy(d.perm_b, L.pb, sizeof(int) * ob);
+  }
+  if (L.dup == 2) std::memcpy(d.perm_a, L.pa, sizeof(int) * oa);
+  if (L.dup == 1) std::memcpy(d.perm_b, L.pb, sizeof(int) * ob);
   pub.permute_a = L.need_a;
   pub.permute_b = L.need_b;
   pub.permute_c = L.need_c;
@@ -313,7 +384,7 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
     for (int s = 0; s < oc; ++s)
       if (L.natural[s] == r) d.perm_c[r] = s;
   if (fam == 2) {
-    // output-LIV weights of the free modes as laid out in the rearranged operands
+    // output-LIV weights of the free (and entrywise) modes of A and the free modes of B
     uint64_t wc[LCO_MAX_ORDER];
     uint64_t w = 1;
     for (int r = 0; r < oc; ++r) { wc[r] = w; w *= d.c_dims[r]; }
@@ -327,10 +398,10 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
       d.free_a_cweight[t++] = wc[r];
       if (r != expect++) simple = false;
     }
+    d.n_free_a = t;
     t = 0;
-    for (int j = 0; j < ob; ++j) {
+    for (int j = 0; j < nfb; ++j) {
       const int r = find(oc, lc, lb[L.pb[j]]);
-      if (r < 0) continue;
       d.free_b_dims[t] = db[L.pb[j]];
       d.free_b_cweight[t++] = wc[r];
       if (r != expect++) simple = false;

@@ -162,13 +162,17 @@ def test_batch_plan_execute_and_graph_replays(lco_lib, gpu_ctx):
         t.destroy()
 
 
-def test_batch_plan_rejects_outer_product(lco_lib, gpu_ctx):
+def test_batch_plan_rejects_outer_product_and_entrywise(lco_lib, gpu_ctx):
     ops = []
     for seed in (1, 2):
         c, v = L.kronecker_hypersparse(5, 1 << 9, seed)
         ops.append(gpu_create(lco_lib, gpu_ctx, [32] * 4, c, v, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES))
     with pytest.raises(lco_lib.LcoError) as e:
         lco_lib.BatchPlan(gpu_ctx, [(ops[0], [0, 1, 2, 3], ops[1], [2, 3, 4, 5], [0, 1, 4, 5])])
+    assert e.value.code == 7
+    # an entrywise label (block-diagonal product) is not planned either
+    with pytest.raises(lco_lib.LcoError) as e:
+        lco_lib.BatchPlan(gpu_ctx, [(ops[0], [0, 1, 2, 3], ops[1], [0, 1, 2, 4], [0, 1, 3, 4])])
     assert e.value.code == 7
     for t in ops:
         t.destroy()

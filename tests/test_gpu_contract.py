@@ -114,6 +114,80 @@ def test_all_matchings_every_algorithm(lco_lib, gpu_ctx, oracle_mod, n):
         gb.destroy()
 
 
+@pytest.mark.parametrize("n", [2, 3])
+def test_entrywise_matchings_every_algorithm(lco_lib, gpu_ctx, oracle_mod, n):
+    """Every matching of the modes of two order-n tensors with at least one pair
+    entrywise (in a, b and the output): every algorithm, several output orders."""
+    import itertools
+    rng = np.random.default_rng(60 + n)
+    k = 0
+    for match in matchings(n):
+        for roles in itertools.product((0, 1), repeat=len(match)):
+            if not any(roles):
+                continue
+            dims_a = [int(x) for x in rng.integers(2, 7, n)]
+            dims_b = [int(x) for x in rng.integers(2, 7, n)]
+            for (ia, ib) in match:
+                dims_b[ib] = dims_a[ia]
+            ca, va = L.random_sparse(rng, dims_a, 40, integer_values=True)
+            cb, vb = L.random_sparse(rng, dims_b, 40, integer_values=True)
+            ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, dims_a, ca, va)
+            gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, dims_b, cb, vb)
+            la = list(range(n))
+            lb = [n + j for j in range(n)]
+            for (ia, ib) in match:
+                lb[ib] = la[ia]
+            role = {ia: r for (ia, _), r in zip(match, roles)}
+            lc = [la[i] for i in range(n) if role.get(i, 1) == 1] + \
+                 [lb[j] for j in range(n) if j not in {y for _, y in match}]
+            k += 1
+            if k % 3 == 1:
+                lc = lc[::-1]
+            elif k % 3 == 2 and len(lc) > 2:
+                lc = lc[1:] + lc[:1]
+            run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
+            ga.destroy()
+            gb.destroy()
+
+
+def test_entrywise_batched_matrix_products(lco_lib, gpu_ctx, oracle_mod):
+    """c_hik = a_hij b_hjk: 48 sparse 60x50 by 50x40 products at once (random FP64,
+    several tiles), the Hadamard product c_ij = a_ij b_ij, per-batch dot products
+    c_h = a_hi b_hi, and the batch label in other positions and output orders."""
+    rng = np.random.default_rng(77)
+    H, I_, J_, K_ = 48, 60, 50, 40
+    ca, va = L.random_sparse(rng, [H, I_, J_], 20000)
+    cb, vb = L.random_sparse(rng, [H, J_, K_], 20000)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [H, I_, J_], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [H, J_, K_], cb, vb)
+    plan = lco_lib.lco_plan_info(gpu_ctx, ga, [0, 1, 2], gb, [0, 2, 3], [0, 1, 3])
+    assert plan.num_entrywise == 1 and plan.num_contracted == 1
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [0, 2, 3], [0, 1, 3])
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [0, 2, 3], [3, 1, 0])
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [0, 2, 3], [1, 3, 0])
+    # the batch mode last in a, first in b
+    gt = lco_lib.lco_permute(gpu_ctx, ga, [1, 2, 0])
+    ot = oracle_mod.permute(oa, [1, 2, 0])
+    run_all(lco_lib, gpu_ctx, oracle_mod, gt, ot, [1, 2, 0], gb, ob, [0, 2, 3], [1, 3, 0])
+    # Hadamard product (nothing contracted) and dot products per batch index
+    cx, vx = L.random_sparse(rng, [H, I_], 1500)
+    cy, vy = L.random_sparse(rng, [H, I_], 1500)
+    gx, ox = pair(lco_lib, gpu_ctx, oracle_mod, [H, I_], cx, vx)
+    gy, oy = pair(lco_lib, gpu_ctx, oracle_mod, [H, I_], cy, vy)
+    run_all(lco_lib, gpu_ctx, oracle_mod, gx, ox, [0, 1], gy, oy, [0, 1], [0, 1])
+    run_all(lco_lib, gpu_ctx, oracle_mod, gx, ox, [0, 1], gy, oy, [0, 1], [0])
+    gyt = lco_lib.lco_permute(gpu_ctx, gy, [1, 0])
+    run_all(lco_lib, gpu_ctx, oracle_mod, gx, ox, [0, 1], gyt, oracle_mod.permute(oy, [1, 0]), [1, 0], [1, 0])
+    # a batch of instances with an entrywise label runs per call, bit-identical
+    outs = lco_lib.lco_contract_batch(gpu_ctx, [(ga, [0, 1, 2], gb, [0, 2, 3], [0, 1, 3]),
+                                                (gx, [0, 1], gy, [0, 1], [0])])
+    one = lco_lib.lco_contract(gpu_ctx, ga, [0, 1, 2], gb, [0, 2, 3], [0, 1, 3])
+    assert np.array_equal(outs[0].to_numpy()[1], one.to_numpy()[1])
+    assert np.array_equal(outs[0].to_numpy()[2].view(np.uint64), one.to_numpy()[2].view(np.uint64))
+    for t in outs + [one, ga, gb, gt, gx, gy, gyt]:
+        t.destroy()
+
+
 # ---------------------------------------------------------------- random FP64, multi-tile
 @pytest.mark.parametrize("seed", [0, 1])
 def test_random_fp64_every_algorithm(lco_lib, gpu_ctx, oracle_mod, seed):
@@ -283,7 +357,7 @@ def test_edge_cases(lco_lib, gpu_ctx, oracle_mod):
         assert l_.tolist() == [0] and v_.tolist() == [0.0], name
     # errors are reported before any device work
     with pytest.raises(lco_lib.LcoError) as e:
-        lco_lib.lco_contract(gpu_ctx, ga, [0, 1], gb, [0, 2], [0, 1, 2])
+        lco_lib.lco_contract(gpu_ctx, ga, [0, 1], gb, [1, 2], [0])  # label 2 of b summed alone
     assert e.value.code == 7
     with pytest.raises(lco_lib.LcoError) as e:
         lco_lib.lco_contract(gpu_ctx, ga, [0, 1], ga, [1, 2], [0, 2])

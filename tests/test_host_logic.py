@@ -209,9 +209,15 @@ def test_plan_forced_algorithm_and_errors(lib):
     with pytest.raises(lib.LcoError) as e:
         lib.lco_plan_contract([5, 6], [0, 1], 10, [7, 7], [1, 2], 10, [0, 2])
     assert e.value.code == 3
+    # an entrywise label (in a, b and the output): block-diagonal sizes
+    p = lib.lco_plan_contract([5, 6], [0, 1], 10, [6, 7], [1, 2], 10, [0, 1, 2])
+    assert (p.num_entrywise, p.num_contracted, p.m, p.k, p.n) == (1, 0, 5 * 6, 6, 7 * 6)
     with pytest.raises(lib.LcoError) as e:
-        lib.lco_plan_contract([5, 6], [0, 1], 10, [6, 7], [1, 2], 10, [0, 1, 2])
+        lib.lco_plan_contract([5, 6], [0, 1], 10, [6, 7], [1, 2], 10, [0, 1])  # label 2 of b is in neither a nor the output
     assert e.value.code == 7
+    with pytest.raises(lib.LcoError) as e:
+        lib.lco_plan_contract([5, 6], [0, 1], 10, [7, 7], [1, 2], 10, [0, 1, 2])  # entrywise dims 6 vs 7
+    assert e.value.code == 3
     with pytest.raises(lib.LcoError) as e:
         lib.lco_plan_contract([5, 6], [0, 0], 10, [6, 7], [1, 2], 10, [2])
     assert e.value.code == 1
