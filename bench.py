@@ -644,6 +644,95 @@ def rp_leg(lco, ctx, torch, np, L, n: int, reps: int):
             "perms": rows}
 
 
+def calibrate_leg(lco, ctx, torch, np, L, reps: int):
+    """The paper's hyper-sparsity sweeps (Sections 5.2.3-5.2.5) repeated on this GPU with R-TENSORs
+    (Section 5.2.1): column-sparsity (a_ijk b_ljk, CSC vs DCSC), row-sparsity (a_ijk b_lmk, CSC vs CSCNA) and
+    index-sparsity (M x N x N tensors with M = N^2, a_ijk b_ljk, CSC vs SOP).  Each point times both forced
+    algorithms end to end (median of `reps`); the crossover is where the alternative starts to win for good."""
+    dev = torch.device("cuda", 0)
+
+    def make(bits, draws, seed, extra=0):
+        c, v = L.rtensor(bits, draws, seed, first_extra_bits=extra)
+        dims = [1 << (bits + extra), 1 << bits, 1 << bits]
+        t = lco.lco_create(ctx, dims, torch.from_numpy(c.view(np.int64).reshape(-1).copy()).to(dev),
+                           torch.from_numpy(v).to(dev), lco.LCO_COORDS | lco.LCO_SUM_DUPLICATES)
+        return t
+
+    def timed(a, la, b, lb, lc, algo, on=None):
+        on = on or ctx
+        f = 0 if algo == "auto" else lco.ALGO_IDS[algo]
+        lco.lco_contract(on, a, la, b, lb, lc, f).destroy()
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = lco.lco_contract(on, a, la, b, lb, lc, f)
+            on.synchronize()
+            t.append((time.perf_counter() - t0) * 1e3)
+            c.destroy()
+        return statistics.median(t)
+
+    tuned_ctx = lco.lco_ctx_create(0)
+    lco.lco_ctx_set_crossovers(tuned_ctx, *lco.MI355X_CROSSOVERS)
+    totals = {"paper_ms": 0.0, "mi355x_ms": 0.0}
+
+    def crossover(rows):
+        rows = sorted(rows, key=lambda r: r["sparsity"])
+        for i in range(len(rows)):
+            if all(r["ratio"] > 1.0 for r in rows[i:]):
+                if i == 0:
+                    return rows[0]["sparsity"]
+                return (rows[i - 1]["sparsity"] * rows[i]["sparsity"]) ** 0.5
+        return None
+
+    exps = {
+        "column_sparsity": {"spec": "a_ijk b_ljk", "alt": "DCSC", "draws": (400_000, 700_000, 1_000_000),
+                            "bits": range(9, 15), "extra": 0, "lab": ([0, 1, 2], [3, 1, 2], [0, 3]),
+                            "paper_crossover": 10, "paper_threshold": 3},
+        "row_sparsity": {"spec": "a_ijk b_lmk", "alt": "CSCNA", "draws": (100_000, 200_000, 300_000),
+                         "bits": range(8, 14), "extra": 0, "lab": ([0, 1, 2], [3, 4, 2], [0, 1, 3, 4]),
+                         "paper_crossover": 3, "paper_threshold": 3},
+        "index_sparsity": {"spec": "a_ijk b_ljk, M x N x N with M = N^2", "alt": "SOP", "draws": (50_000, 100_000),
+                           "bits": range(7, 13), "extra": None, "lab": ([0, 1, 2], [3, 1, 2], [0, 3]),
+                           "paper_crossover": 6, "paper_threshold": 3},
+    }
+    out = {}
+    seed = 100
+    for name, e in exps.items():
+        rows = []
+        la, lb, lc = e["lab"]
+        for draws in e["draws"]:
+            for bits in e["bits"]:
+                extra = bits if e["extra"] is None else e["extra"]
+                a = make(bits, draws, seed, extra)
+                b = make(bits, draws, seed + 1, extra)
+                seed += 2
+                plan = lco.lco_plan_info(ctx, a, la, b, lb, lc).as_dict()
+                sp = (plan["k"] if name == "column_sparsity" else plan["m"]) / max(1, a.nnz)
+                t_csc = timed(a, la, b, lb, lc, "CSC")
+                t_alt = timed(a, la, b, lb, lc, e["alt"])
+                t_paper = timed(a, la, b, lb, lc, "auto")
+                t_tuned = timed(a, la, b, lb, lc, "auto", tuned_ctx)
+                totals["paper_ms"] += t_paper
+                totals["mi355x_ms"] += t_tuned
+                tuned = lco.lco_plan_info(tuned_ctx, a, la, b, lb, lc).as_dict()
+                rows.append({"draws": draws, "bits": bits, "nnz_a": a.nnz, "sparsity": sp, "csc_ms": t_csc,
+                             "alt_ms": t_alt, "ratio": t_csc / t_alt, "selected": plan["algo_name"],
+                             "selected_mi355x": tuned["algo_name"], "auto_ms": t_paper, "auto_mi355x_ms": t_tuned})
+                print(f"calibration {name} draws={draws} bits={bits} sparsity={sp:.2f} "
+                      f"CSC {t_csc:.3f} ms {e['alt']} {t_alt:.3f} ms", file=sys.stderr, flush=True)
+                a.destroy()
+                b.destroy()
+        out[name] = {"product": e["spec"], "alternative": e["alt"], "crossover": crossover(rows),
+                     "paper_crossover_E8400": e["paper_crossover"], "paper_threshold": e["paper_threshold"],
+                     "points": rows}
+    tuned_ctx.destroy()
+    out["selector_total"] = {**totals, "crossovers_paper": list(lco.PAPER_CROSSOVERS),
+                             "crossovers_mi355x": list(lco.MI355X_CROSSOVERS),
+                             "note": "sum over every sweep point of the automatic choice's median time"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -667,6 +756,9 @@ def main():
                     help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--app-only", action="store_true", help="run only the combinatorial Laplacian leg")
     ap.add_argument("--rp-only", action="store_true", help="run only the permutation-table leg")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run only the selector calibration sweeps (R-TENSORs, Sections 5.2.3-5.2.5)")
+    ap.add_argument("--calibrate-reps", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -688,6 +780,9 @@ def main():
     if args.app_only:
         print(json.dumps({"laplacian": app_leg(lco, ctx, torch, np, L, args.app_n, max(1, args.app_reps))}),
               flush=True)
+        return
+    if args.calibrate:
+        print(json.dumps({"calibration": calibrate_leg(lco, ctx, torch, np, L, args.calibrate_reps)}), flush=True)
         return
     if args.rp_only:
         print(json.dumps({"rp_table": rp_leg(lco, ctx, torch, np, L, args.rp_n, max(1, args.rp_reps))}), flush=True)

@@ -87,6 +87,33 @@ lco_status lco_ctx_set_stream(lco_ctx ctx, void* hip_stream);
 /* Block until all work enqueued by the context has finished. */
 lco_status lco_ctx_synchronize(lco_ctx ctx);
 
+/* Crossovers of the selector.  The paper's table (Section 5.2) picks a cell
+ * and an orientation from the operands' hyper-sparsity classes (ratio of a
+ * matricised dimension to the non-zeros above 3).  Sections 5.2.3-5.2.5
+ * measure where each specialised algorithm actually starts to win against CSC
+ * (about 10 for DCSC, 3 for CSCNA, 6 for SOP on the paper's CPU).  With
+ * crossovers set, a chosen DCSC/DCSR gives way to CSC/CSR (same orientation)
+ * while the operand's relevant hyper-sparsity (A's columns, B's rows) is at most
+ * `doubly_compressed`; CSCNA/CSRNA to CSC/CSR while A's rows / B's columns are at
+ * most `no_accumulator`; SOP to CSC or CSR (fewest rearrangements) while the
+ * smallest of the four ratios is at most `outer_product`.  The default, 3 for
+ * all three, is the paper's table unchanged.  Every algorithm sums each output
+ * in the same order, so only the speed changes.  Applies to lco_contract,
+ * lco_plan_info, batches and batch plans made on this context.  Errors:
+ * LCO_E_ARG (NULL, or a value below 3 or not finite). */
+lco_status lco_ctx_set_crossovers(lco_ctx ctx, double doubly_compressed, double no_accumulator,
+                                  double outer_product);
+lco_status lco_ctx_get_crossovers(lco_ctx ctx, double* doubly_compressed, double* no_accumulator,
+                                  double* outer_product);
+/* Crossovers measured on MI355X with the paper's R-TENSOR sweeps (the
+ * benchmark's calibration leg): DCSC overtakes CSC above a column-sparsity of
+ * about 16; SOP overtakes CSC above an index-sparsity of about 59; CSCNA and CSC
+ * take the same time at every row-sparsity (the accumulator is a per-row LDS
+ * table here, not a dense array of the row count), so NA keeps the paper's 3. */
+#define LCO_MI355X_DC_CROSSOVER 16.0
+#define LCO_MI355X_NA_CROSSOVER 3.0
+#define LCO_MI355X_SOP_CROSSOVER 59.0
+
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels (off by default; costs two events per
  * launch).  lco_timing_query sums over all launches of kernels whose name

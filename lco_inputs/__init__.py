@@ -26,6 +26,12 @@ Workloads (all synthetic, seeded, shaped like the paper's benchmark operators):
   on interior rows, the O(h^2) one-sided forms (-3, 4, -1)/2 on the first row and
   (1, -4, 3)/2 on the last.  Its products with Kronecker deltas build the
   combinatorial Laplacian of the paper's Section 2 at ``n = 2**k - 1``.
+* ``rtensor(bits, draws, seed)`` -- the third-order R-TENSOR of the paper's
+  Section 5.2.1 (the R-MAT model generalised to octants): per bit level one
+  octant is drawn with the base edge probabilities of Table r_tensor_probs
+  ((1,1,1): .3, (2,2,2): .2, the six others .5/6 each), jittered once per tensor
+  by uniform(-.1, .1) additions and renormalised; ``first_extra_bits`` extends the
+  first mode (the M x N x N tensors with M = N^2 of the outer-product tests).
 * ``random_sparse(rng, dims, nnz)`` -- distinct uniformly random coordinates.
 * ``diagonal(order, n)`` -- the purely diagonal tensor of the paper's Figure on
   hyper-sparsity of matricised tensors (all-zero except i=j=...).
@@ -51,6 +57,8 @@ __all__ = [
     "kronecker_hypersparse",
     "fd_first_derivative",
     "random_sparse",
+    "rtensor",
+    "RTENSOR_PROBS",
     "diagonal",
     "batched_fd_instances",
     "fd_laplacian_torch",
@@ -60,6 +68,8 @@ __all__ = [
 ]
 
 KRON_PROBS = (0.57, 0.19, 0.19, 0.05)
+# octants (1,1,1), (1,1,2), (1,2,1), (1,2,2), (2,1,1), (2,1,2), (2,2,1), (2,2,2)
+RTENSOR_PROBS = (0.3,) + (0.5 / 6,) * 6 + (0.2,)
 
 
 def fd_laplacian(side: int, dim: int):
@@ -105,6 +115,39 @@ def kronecker_hypersparse(bits: int, draws: int, seed: int, probs=KRON_PROBS):
             q = np.searchsorted(cum, u, side="right").astype(np.uint64)
             coords[:, m0] |= (q >> np.uint64(1)) << np.uint64(b)
             coords[:, m1] |= (q & np.uint64(1)) << np.uint64(b)
+    vals = rng.uniform(-1.0, 1.0, draws)
+    return coords, vals
+
+
+def rtensor(bits: int, draws: int, seed: int, first_extra_bits: int = 0, probs=RTENSOR_PROBS,
+            jitter: float = 0.1):
+    """Coordinates ``(draws, 3)`` and values of an R-TENSOR with ``2**bits`` per mode
+    (the first mode ``2**(bits + first_extra_bits)``).
+
+    The probabilities get one uniform(-jitter, jitter) addition each, negative
+    results are clipped to 0, and they are renormalised to sum to 1.  For each bit
+    level ``b`` (low to high) a uniform number picks octant ``o`` (index 4x + 2y + z
+    of the octant (x+1, y+1, z+1)), which sets bit ``b`` of the three coordinates to
+    x, y, z.  The extra high bits of the first mode are set with the first mode's
+    marginal probability of its upper half.  Values are uniform in (-1, 1).
+    Duplicate coordinates are kept (the consumer sums them on construction).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.asarray(probs, dtype=np.float64) + rng.uniform(-jitter, jitter, 8)
+    p = np.clip(p, 0.0, None)
+    p /= p.sum()
+    cum = np.cumsum(p)
+    coords = np.zeros((draws, 3), dtype=np.uint64)
+    one = np.uint64(1)
+    for b in range(bits):
+        o = np.searchsorted(cum, rng.random(draws), side="right").astype(np.uint64)
+        o = np.minimum(o, np.uint64(7))
+        coords[:, 0] |= ((o >> np.uint64(2)) & one) << np.uint64(b)
+        coords[:, 1] |= ((o >> one) & one) << np.uint64(b)
+        coords[:, 2] |= (o & one) << np.uint64(b)
+    p_hi = float(p[4:].sum())
+    for b in range(first_extra_bits):
+        coords[:, 0] |= (rng.random(draws) < p_hi).astype(np.uint64) << np.uint64(bits + b)
     vals = rng.uniform(-1.0, 1.0, draws)
     return coords, vals
 

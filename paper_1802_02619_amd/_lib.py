@@ -19,6 +19,7 @@ __all__ = [
     "lco_contract", "lco_add", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read",
     "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
+    "lco_ctx_set_crossovers", "lco_ctx_get_crossovers", "MI355X_CROSSOVERS", "PAPER_CROSSOVERS",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
     "LCO_ALG_CSRNA", "LCO_ALG_SOP", "LCO_SPARSE", "LCO_ROW_SPARSE", "LCO_COL_SPARSE", "LCO_INDEX_SPARSE",
@@ -148,6 +149,9 @@ def load_library():
             "lco_permute": (i32, [vp, vp, pi32, pvp]),
             "lco_contract": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, pvp]),
             "lco_add": (i32, [vp, ctypes.c_double, vp, pi32, ctypes.c_double, vp, pi32, pi32, pvp]),
+            "lco_ctx_set_crossovers": (i32, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "lco_ctx_get_crossovers": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
             "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
             "lco_contract_batch": (i32, [vp, i32, ctypes.POINTER(ContractDesc), ctypes.POINTER(ctypes.c_void_p)]),
             "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -350,6 +354,23 @@ def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_label
     _check(L.lco_contract(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
                           _i32arr(c_labels), int(flags), ctypes.byref(h)))
     return Tensor(ctx, h)
+
+
+# selector crossovers (doubly compressed, no accumulator, outer product): the paper's table as is, and
+# those measured on MI355X (LCO_MI355X_*_CROSSOVER in include/lco.h)
+PAPER_CROSSOVERS = (3.0, 3.0, 3.0)
+MI355X_CROSSOVERS = (16.0, 3.0, 59.0)
+
+
+def lco_ctx_set_crossovers(ctx: Context, doubly_compressed: float, no_accumulator: float, outer_product: float):
+    _check(load_library().lco_ctx_set_crossovers(ctx.handle, float(doubly_compressed), float(no_accumulator),
+                                                 float(outer_product)))
+
+
+def lco_ctx_get_crossovers(ctx: Context):
+    d, n, o = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().lco_ctx_get_crossovers(ctx.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(o)))
+    return (d.value, n.value, o.value)
 
 
 def lco_add(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, alpha: float = 1.0,

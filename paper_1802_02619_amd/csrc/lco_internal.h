@@ -68,6 +68,8 @@ struct lco_ctx_s {
   int64_t batch_stats[2] = {0, 0};  // last batch on this context: instances batched, run per call
   // batch-plan autotuner: (size bucket, selected branch) -> (branch, blocks per CU)
   std::map<int, std::pair<int, int>> tune;
+  // selector crossovers: doubly compressed, no accumulator, outer product
+  double cross[3] = {3.0, 3.0, 3.0};
 };
 
 namespace lco {
@@ -185,8 +187,11 @@ struct ContractDetail {
   // of its right operand (entrywise modes counted on the left only)
   uint64_t em, ek, en;
 };
+// `cross`: hyper-sparsity up to which the doubly-compressed, no-accumulator and
+// outer-product algorithms give way to CSC/CSR (NULL: never, the paper's table)
 ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
-                             const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags);
+                             const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags,
+                             const double* cross = nullptr);
 // Addition of two tensors over the same labelled modes: each operand is brought
 // into the output's mode order (output mode r is operand mode perm[r]).
 struct AddDetail {

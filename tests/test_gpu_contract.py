@@ -269,6 +269,54 @@ def test_tiny_rows_staged_and_direct(lco_lib, gpu_ctx, oracle_mod, b_len):
         t.destroy()
 
 
+def test_selector_crossovers(lco_lib, gpu_ctx, oracle_mod):
+    """With the crossovers measured on MI355X, a column-sparsity of 8 takes CSC
+    instead of DCSC and an index-sparsity of 20 takes CSC or CSR instead of SOP,
+    with bit-identical results; a column-sparsity of 64 keeps DCSC; the paper's
+    table returns with the defaults; bad values are rejected."""
+    rng = np.random.default_rng(90)
+    ctx2 = lco_lib.lco_ctx_create(0)
+    try:
+        assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.PAPER_CROSSOVERS
+        cases = []
+        # a_ijk b_ljk: A is N x N^2 with N^2 / nnz = 8 (A column-sparse, B row-sparse)
+        ca, va = L.random_sparse(rng, [64, 64, 64], 512)
+        cb, vb = L.random_sparse(rng, [64, 64, 64], 512)
+        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], True))
+        # the same with N^2 / nnz = 64: DCSC stays
+        ca, va = L.random_sparse(rng, [64, 64, 64], 64)
+        cb, vb = L.random_sparse(rng, [64, 64, 64], 64)
+        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], False))
+        # square N^2 x N^2 operands with index-sparsity 20
+        ca, va = L.random_sparse(rng, [4096, 64, 64], 205)
+        cb, vb = L.random_sparse(rng, [4096, 64, 64], 205)
+        cases.append(([4096, 64, 64], ca, va, [4096, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], True))
+        for da, ca, va, db, cb, vb, la, lb, lc, moves in cases:
+            ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, da, ca, va)
+            gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, db, cb, vb)
+            ref = oracle_mod.contract(oa, la, ob, lb, lc)
+            lco_lib.lco_ctx_set_crossovers(ctx2, *lco_lib.PAPER_CROSSOVERS)
+            paper = lco_lib.lco_plan_info(ctx2, ga, la, gb, lb, lc).as_dict()
+            got_p = lco_lib.lco_contract(ctx2, ga, la, gb, lb, lc)
+            lco_lib.lco_ctx_set_crossovers(ctx2, *lco_lib.MI355X_CROSSOVERS)
+            tuned = lco_lib.lco_plan_info(ctx2, ga, la, gb, lb, lc).as_dict()
+            got_t = lco_lib.lco_contract(ctx2, ga, la, gb, lb, lc)
+            print("crossovers", paper["algo_name"], "->", tuned["algo_name"], flush=True)
+            assert (paper["algo_name"] != tuned["algo_name"]) == moves
+            assert tuned["algo_name"] in (("CSC", "CSR") if moves else (paper["algo_name"],))
+            check(got_p, ref, exact=True)
+            check(got_t, ref, exact=True)
+            for t in (got_p, got_t, ga, gb):
+                t.destroy()
+        for bad in [(2.0, 3.0, 3.0), (3.0, -1.0, 3.0), (3.0, 3.0, float("inf")), (float("nan"), 3.0, 3.0)]:
+            with pytest.raises(lco_lib.LcoError) as e:
+                lco_lib.lco_ctx_set_crossovers(ctx2, *bad)
+            assert e.value.code == 1
+        assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.MI355X_CROSSOVERS
+    finally:
+        ctx2.destroy()
+
+
 # ---------------------------------------------------------------- hyper-sparse cells of the table
 def test_rowsparse_times_colsparse_uses_no_accumulator(lco_lib, gpu_ctx, oracle_mod):
     """a_ijk b_lmk (Section 5.2.4): A row-sparse, B column-sparse -> CSCNA/CSRNA."""

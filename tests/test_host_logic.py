@@ -242,3 +242,11 @@ def test_orientation_rule_prefers_fewer_rearrangements(lib):
     assert (r.permute_a + r.permute_b + r.permute_c) == 1 and lib.ALGOS[r.algo] == "CSC"
     r = lib.lco_plan_contract([4, 6, 5], [0, 1, 4], 30, [6], [1], 5, [0, 4])      # m = 20, n = 1
     assert (r.permute_a + r.permute_b + r.permute_c) == 1 and lib.ALGOS[r.algo] == "CSR"
+
+
+def test_crossover_constants_match_header(lib):
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lco.h")).read()
+    got = tuple(float(re.search(r"#define LCO_MI355X_%s_CROSSOVER ([0-9.]+)" % k, hdr).group(1))
+                for k in ("DC", "NA", "SOP"))
+    assert got == lib.MI355X_CROSSOVERS
+    assert lib.PAPER_CROSSOVERS == (3.0, 3.0, 3.0)

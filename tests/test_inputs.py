@@ -57,3 +57,22 @@ def test_serving_trace_shape():
     t20, c20, p20 = L.serving_trace(20.0)
     assert np.array_equal(t20, t[:len(t20)]) and np.array_equal(c20, cls[:len(t20)])  # a prefix
     assert np.array_equal(p20, p[:len(t20)]) and t[len(t20)] >= 20.0
+
+
+def test_rtensor_recipe():
+    """Octant draws: each mode's bit is 1 with the marginal of the jittered
+    probabilities (about .5/6*3 + .2 = .45 before jitter), levels independent;
+    seeded; the first mode's extra bits extend its range."""
+    c, v = L.rtensor(10, 1 << 16, seed=3)
+    assert c.shape == (1 << 16, 3) and c.max() < 1024 and np.all(np.abs(v) < 1)
+    for m in range(3):
+        frac = ((c[:, m] >> 4) & 1).mean()
+        assert 0.2 < frac < 0.7
+    assert abs(((c[:, 0] >> 2) & 1).mean() - ((c[:, 0] >> 7) & 1).mean()) < 0.02  # same law at every level
+    c2, _ = L.rtensor(10, 1 << 16, seed=3)
+    assert np.array_equal(c, c2)
+    c3, _ = L.rtensor(6, 1 << 14, seed=4, first_extra_bits=6)
+    assert c3[:, 0].max() >= 64 and c3[:, 0].max() < 4096 and c3[:, 1].max() < 64
+    # no jitter: the marginal of the first mode's bit is exactly .5/6*3 + .2
+    c4, _ = L.rtensor(1, 1 << 18, seed=5, jitter=0.0)
+    assert abs((c4[:, 0] & 1).mean() - (0.25 + 0.2)) < 0.005
