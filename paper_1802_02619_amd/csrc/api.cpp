@@ -183,8 +183,14 @@ static void check_device_error(lco_ctx ctx, uint32_t word) {
 }
 
 const uint64_t* readback(lco_ctx ctx, const uint64_t* const* dev_words, int count) {
-  for (int i = 0; i < count; ++i)
-    LCO_HIP(hipMemcpyAsync(ctx->pinned + i, dev_words[i], sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+  // one copy per run of consecutive device words
+  for (int i = 0; i < count;) {
+    int j = i + 1;
+    while (j < count && dev_words[j] == dev_words[j - 1] + 1) ++j;
+    LCO_HIP(hipMemcpyAsync(ctx->pinned + i, dev_words[i], sizeof(uint64_t) * (j - i), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    i = j;
+  }
   LCO_HIP(hipMemcpyAsync((uint32_t*)(ctx->pinned + 63), ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
                          ctx->stream));
   LCO_HIP(hipStreamSynchronize(ctx->stream));

@@ -508,13 +508,13 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   ra.bstart = bstart;
   ra.elen = len;
   // row shapes; long rows collected with their product counts
-  uint64_t* n2_dev = s.get<uint64_t>(1);
+  // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
+  uint64_t* n2_dev = s.get<uint64_t>(4);
+  uint64_t* flags_dev = n2_dev + 1;
   uint32_t* list2 = s.get<uint32_t>(na);
   uint64_t* f2 = s.get<uint64_t>(na);
-  memset_async(ctx, n2_dev, 0, sizeof(uint64_t));
+  memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
   uint8_t* shape = s.get<uint8_t>(na);
-  uint64_t* flags_dev = s.get<uint64_t>(3);  // some row is tiny; a copy; of the one-wave kernel
-  memset_async(ctx, flags_dev, 0, 3 * sizeof(uint64_t));
   LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, n2_dev, list2, f2,
              shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
   const uint64_t* rb1[5] = {arows.count, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
