@@ -353,9 +353,18 @@ __global__ __launch_bounds__(kSegThreads) void rx_smallseg_kernel(
   __shared__ uint64_t s_b[kSegTile];  // tile-relative segment ids, then the output values
   __shared__ int64_t bounds[2];
   __shared__ int too_long;
+  if (threadIdx.x == 0) {
+    // a segment holding both ends of a 33-entry stretch at the nominal cut is too long (two loads)
+    const int64_t x = (int64_t)blockIdx.x * nominal;
+    too_long = x + kSmallSeg < n && fd_div(seg_div, livs[x]) == fd_div(seg_div, livs[x + kSmallSeg]);
+  }
+  __syncthreads();
+  if (too_long) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
   if (threadIdx.x < 2)
     bounds[threadIdx.x] = seg_start_at_or_after(livs, n, seg_div, ((int64_t)blockIdx.x + threadIdx.x) * nominal);
-  if (threadIdx.x == 0) too_long = 0;
   __syncthreads();
   const int64_t s0 = bounds[0], s1 = bounds[1];
   const int64_t len64 = s1 - s0;
@@ -366,6 +375,11 @@ __global__ __launch_bounds__(kSegThreads) void rx_smallseg_kernel(
   }
   const int len = (int)len64;
   const uint64_t seg_first = fd_div(seg_div, livs[s0]);
+  // give up at once when the tile's first segment is already too long (one load)
+  if (len > kSmallSeg && fd_div(seg_div, livs[s0 + kSmallSeg]) == seg_first) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
   const uint64_t key_base = seg_first * key_range;
   uint64_t lv[kSegItems], key[kSegItems], sg[kSegItems];
   double vv[kSegItems];
