@@ -128,7 +128,7 @@ __global__ void bt_classify_kernel(const uint32_t* __restrict__ rs, const uint32
 // window holds entries of one instance only; a row of another instance, or
 // entries outside the window, move it.
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void bt_chunk_kernel(
+__global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void bt_chunk_kernel(
     const BInst* __restrict__ in, const uint32_t* __restrict__ rs, const uint64_t* __restrict__ rid,
     const uint32_t* __restrict__ rinst, const uint8_t* __restrict__ shape, const uint32_t* __restrict__ fallback,
     const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, int chunk_rows,

@@ -145,11 +145,12 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restr
 // coalesced load per array; a row then takes its entries' data from the window
 // by lane shuffles, so the only global loads that depend on the row are those
 // of its rows of B'.  The window moves forward when a row's entries leave it
-// (rows are consecutive, so their entries are too).
+// (rows are consecutive, so their entries are too).  The symbolic pass waits on
+// memory more than it computes, so it is held to 8 waves per SIMD (64 VGPRs).
 constexpr int kChunkRows = kWave;
 
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
+__global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
                                                                 const uint8_t* __restrict__ shape,
                                                                 uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
