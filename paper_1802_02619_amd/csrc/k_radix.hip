@@ -186,10 +186,11 @@ __global__ __launch_bounds__(kRxThreads) void rx_scatter_kernel(
 
 // ---------------------------------------------------------------- LDS-resident sorts
 
-// Sorts up to kLdsTile elements held in registers (element order (wave, item,
-// lane)) by bits [0, bits) of key(x) = x / key_div - key_base, stably, leaving
-// the result in s_liv / s_val positions [0, valid).
-__device__ __forceinline__ void lds_sort(uint64_t (&lv)[kLdsItems], double (&vv)[kLdsItems], int valid, int bits,
+// Sorts up to kLdsThreads * ITEMS elements held in registers (element order
+// (wave, item, lane)) by bits [0, bits) of key(x) = x / key_div - key_base,
+// stably, leaving the result in s_liv / s_val positions [0, valid).
+template <int ITEMS = kLdsItems>
+__device__ __forceinline__ void lds_sort(uint64_t (&lv)[ITEMS], double (&vv)[ITEMS], int valid, int bits,
                                          int digit_cap, const FastDiv& key_div, uint64_t key_base,
                                          uint32_t (*cnt)[kRxBins], uint32_t* dstart, uint32_t* wsum,
                                          uint64_t* s_liv, double* s_val) {
@@ -197,10 +198,10 @@ __device__ __forceinline__ void lds_sort(uint64_t (&lv)[kLdsItems], double (&vv)
   const int passes = bits > 0 ? (bits + digit_cap - 1) / digit_cap : 0;
   const int dbits = passes ? (bits + passes - 1) / passes : 1;
   const uint32_t mask = (1u << dbits) - 1u;
-  const int ebase = wave * kLdsItems * kWave + lane;
+  const int ebase = wave * ITEMS * kWave + lane;
   if (passes == 0) {
 #pragma unroll
-    for (int it = 0; it < kLdsItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
       const int e = ebase + it * kWave;
       s_liv[e] = lv[it];
       s_val[e] = vv[it];
@@ -209,22 +210,22 @@ __device__ __forceinline__ void lds_sort(uint64_t (&lv)[kLdsItems], double (&vv)
     return;
   }
   for (int p = 0; p < passes; ++p) {
-    uint32_t dg[kLdsItems], pos[kLdsItems];
+    uint32_t dg[ITEMS], pos[ITEMS];
 #pragma unroll
-    for (int it = 0; it < kLdsItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
       const int e = ebase + it * kWave;
       dg[it] = e < valid ? digit_of(fd_div(key_div, lv[it]) - key_base, p * dbits, mask) : mask;
     }
-    block_rank<kLdsWaves, kLdsItems>(dg, pos, dbits, cnt, dstart, wsum);
+    block_rank<kLdsWaves, ITEMS>(dg, pos, dbits, cnt, dstart, wsum);
 #pragma unroll
-    for (int it = 0; it < kLdsItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
       s_liv[pos[it]] = lv[it];
       s_val[pos[it]] = vv[it];
     }
     __syncthreads();
     if (p + 1 < passes) {
 #pragma unroll
-      for (int it = 0; it < kLdsItems; ++it) {
+      for (int it = 0; it < ITEMS; ++it) {
         const int e = ebase + it * kWave;
         lv[it] = s_liv[e];
         vv[it] = s_val[e];
@@ -291,22 +292,26 @@ __device__ int64_t seg_start_at_or_after(const uint64_t* __restrict__ livs, int6
 // Segmented radix permutation: tiles hold whole segments of constant leading
 // resting modes (Section 4.1: such regions sort independently), each sorted in
 // LDS by the tile-relative key.  Sets *overflow if a tile exceeds capacity.
-__global__ __launch_bounds__(kLdsThreads) void rx_segmented_kernel(
+// Two tile sizes: kLdsThreads x 8 (64 KB of LDS, two blocks per compute unit)
+// and kLdsThreads x 16 (one block per compute unit).
+template <int ITEMS>
+__global__ __launch_bounds__(kLdsThreads, ITEMS <= kLdsItems / 2 ? 4 : 1) void rx_segmented_kernel(
     const uint64_t* __restrict__ livs, const double* __restrict__ vals, int64_t n, ShuffleParams sp,
     FastDiv seg_div, FastDiv key_div, uint64_t key_range, int64_t nominal, int digit_cap,
     uint64_t* __restrict__ out_livs, double* __restrict__ out_vals, uint32_t* __restrict__ overflow) {
+  constexpr int kTile = kLdsThreads * ITEMS;
   __shared__ uint32_t cnt[kLdsWaves][kRxBins];
   __shared__ uint32_t dstart[kRxBins];
   __shared__ uint32_t wsum[kLdsWaves + 1];
-  __shared__ uint64_t s_liv[kLdsTile];
-  __shared__ double s_val[kLdsTile];
+  __shared__ uint64_t s_liv[kTile];
+  __shared__ double s_val[kTile];
   __shared__ int64_t bounds[2];
   if (threadIdx.x < 2) bounds[threadIdx.x] = seg_start_at_or_after(livs, n, seg_div, ((int64_t)blockIdx.x + threadIdx.x) * nominal);
   __syncthreads();
   const int64_t s0 = bounds[0], s1 = bounds[1];
   const int64_t len = s1 - s0;
   if (len <= 0) return;
-  if (len > kLdsTile) {
+  if (len > kTile) {
     if (threadIdx.x == 0) atomicOr(overflow, 1u);
     return;
   }
@@ -317,16 +322,16 @@ __global__ __launch_bounds__(kLdsThreads) void rx_segmented_kernel(
   const uint64_t range_max = (seg_last - seg_first + 1) * key_range - 1;
   const int bits = range_max ? 64 - __builtin_clzll(range_max) : 0;
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const int ebase = wave * kLdsItems * kWave + lane;
-  uint64_t lv[kLdsItems];
-  double vv[kLdsItems];
+  const int ebase = wave * ITEMS * kWave + lane;
+  uint64_t lv[ITEMS];
+  double vv[ITEMS];
 #pragma unroll
-  for (int it = 0; it < kLdsItems; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const int e = ebase + it * kWave;
     lv[it] = e < valid ? shuffle_liv(sp, livs[s0 + e]) : 0;
     vv[it] = e < valid ? vals[s0 + e] : 0.0;
   }
-  lds_sort(lv, vv, valid, bits, digit_cap, key_div, key_base, cnt, dstart, wsum, s_liv, s_val);
+  lds_sort<ITEMS>(lv, vv, valid, bits, digit_cap, key_div, key_base, cnt, dstart, wsum, s_liv, s_val);
   for (int i = threadIdx.x; i < valid; i += kLdsThreads) {
     out_livs[s0 + i] = s_liv[i];
     out_vals[s0 + i] = s_val[i];
@@ -564,7 +569,7 @@ void radix_sort_pairs(lco_ctx ctx, const uint64_t* in_livs, const double* in_val
 
 bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
                        double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
-                       const FastDiv& key_div, uint64_t key_range, bool small_first) {
+                       const FastDiv& key_div, uint64_t key_range, bool small_first, bool half_first) {
   if (n <= 0) return true;
   Scratch s(ctx);
   uint64_t* word = s.get<uint64_t>(1);  // the kernel ORs its flag into the low half
@@ -577,10 +582,21 @@ bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_va
     const uint64_t* words[1] = {word};
     if (readback(ctx, words, 1)[0] == 0) return true;
   }
+  // the half-size tile first when segments are expected to fit it
+  if (half_first) {
+    memset_async(ctx, word, 0, sizeof(uint64_t));
+    const int64_t nominal = kLdsTile / 4;
+    const int64_t tiles = (n + nominal - 1) / nominal;
+    LCO_LAUNCH(ctx, "rx_segmented", rx_segmented_kernel<kLdsItems / 2>, tiles, kLdsThreads, 0, in_livs, in_vals, n,
+               shuffle, seg_div, key_div, key_range, nominal, default_digit_cap(), out_livs, out_vals,
+               (uint32_t*)word);
+    const uint64_t* words[1] = {word};
+    if (readback(ctx, words, 1)[0] == 0) return true;
+  }
   memset_async(ctx, word, 0, sizeof(uint64_t));
   const int64_t nominal = kLdsTile / 2;
   const int64_t tiles = (n + nominal - 1) / nominal;
-  LCO_LAUNCH(ctx, "rx_segmented", rx_segmented_kernel, tiles, kLdsThreads, 0, in_livs, in_vals, n, shuffle,
+  LCO_LAUNCH(ctx, "rx_segmented", rx_segmented_kernel<kLdsItems>, tiles, kLdsThreads, 0, in_livs, in_vals, n, shuffle,
              seg_div, key_div, key_range, nominal, default_digit_cap(), out_livs, out_vals, (uint32_t*)word);
   const uint64_t* words[1] = {word};
   const uint64_t* r = readback(ctx, words, 1);
@@ -609,7 +625,8 @@ void permute_storage(lco_ctx ctx, const lco_tensor_s* in, const RpDetail& plan, 
       // segments larger than a tile on average: some segment is, and the tile sort would only give up
       if (plan.avg_segment <= (double)kLdsTile &&
           segmented_permute(ctx, in->livs, in->vals, out_livs, out_vals, n, sp, make_fastdiv(plan.pub.seg_div),
-                            kp.key_div, plan.pub.key_range, plan.avg_segment <= 8.0))
+                            kp.key_div, plan.pub.key_range, plan.avg_segment <= 8.0,
+                            plan.avg_segment <= (double)kLdsTile / 4))
         return;
       radix_sort_pairs(ctx, in->livs, in->vals, out_livs, out_vals, n, &sp, kp, plan.sort_bits, cap);
       return;

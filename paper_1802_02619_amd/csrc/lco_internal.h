@@ -242,10 +242,11 @@ void shuffle_copy(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, u
 // Segmented permutation: returns false (and does nothing) if a segment exceeds the tile capacity.
 // With `small_first`, segments are first assumed to hold at most 32 entries each
 // and are ranked directly; a longer segment sends the whole permutation to the
-// tile sort.
+// tile sort.  With `half_first`, the tile sort first tries half-size tiles
+// (4096 entries) and falls back to full ones (8192) when a tile overflows.
 bool segmented_permute(lco_ctx ctx, const uint64_t* in_livs, const double* in_vals, uint64_t* out_livs,
                        double* out_vals, int64_t n, const ShuffleParams& shuffle, const FastDiv& seg_div,
-                       const FastDiv& key_div, uint64_t key_range, bool small_first);
+                       const FastDiv& key_div, uint64_t key_range, bool small_first, bool half_first);
 int default_digit_cap();
 
 // permutation of a tensor's storage according to a plan

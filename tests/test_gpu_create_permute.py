@@ -128,6 +128,22 @@ def test_permute_segmented_paths(lco_lib, gpu_ctx, oracle_mod):
     assert {"rx_segmented", "rx_scatter"} <= launched
 
 
+def test_permute_segment_tiles_half_then_full(lco_lib, gpu_ctx, oracle_mod):
+    """Segments of 4,000 and 100 entries alternating: half-size tiles (4096) are
+    tried first and overflow where a short segment starts next to a long one;
+    full-size tiles (8192) then hold them."""
+    rng = np.random.default_rng(13)
+    dims = [70, 70, 40]
+    parts = []
+    for m2 in range(0, 40, 2):
+        n_here = 4000 if (m2 // 2) % 2 == 0 else 100
+        c, _ = L.random_sparse(rng, [70, 70], n_here)
+        parts.append(np.concatenate([c, np.full((len(c), 1), m2, np.uint64)], axis=1))
+    coords = np.concatenate(parts)
+    vals = rng.uniform(-1, 1, len(coords))
+    _perm_case(lco_lib, gpu_ctx, oracle_mod, dims, coords, vals, [(1, 0, 2)])
+
+
 def test_permute_short_segments(lco_lib, gpu_ctx, oracle_mod):
     """Segments of constant leading resting modes that hold a few entries each are
     ranked directly: a ragged last tile, equal keys inside a segment (a trailing
