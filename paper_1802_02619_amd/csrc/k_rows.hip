@@ -101,39 +101,121 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_
 // counts `f2` (list order is arbitrary; each long row's result depends only on
 // its own products).  `*tiny` / `*copy` / `*wave` are set when some row is of
 // that class (`wave`: a row of the one-wave kernel).
-__global__ void row_classify_kernel(RowArgs ra, int64_t upper, uint64_t* __restrict__ n2, uint32_t* __restrict__ list2,
-                                    uint64_t* __restrict__ f2, uint8_t* __restrict__ shape,
-                                    uint32_t* __restrict__ tiny, uint32_t* __restrict__ copy,
-                                    uint32_t* __restrict__ wave) {
+// The class of row r (entries [e0, e1)); `classes` enables the tiny and copy
+// classes.  A long row reports its product count through *f_long (else 0).
+__device__ __forceinline__ uint8_t classify_row(const RowArgs& ra, uint32_t e0, uint32_t e1, bool classes,
+                                                uint64_t* f_long) {
+  uint64_t f = 0, mx = 0;
+  for (uint32_t e = e0; e < e1; ++e) {
+    const uint64_t l = ra.elen[e];
+    f += l;
+    mx = l > mx ? l : mx;
+  }
+  *f_long = 0;
+  if (f == 0) return kShapeSkip;
+  if (classes && e1 - e0 <= (uint32_t)kTinyEntries && f <= (uint64_t)kTinyProducts) return kShapeTiny;
+  if (classes && e1 - e0 == 1) return kShapeCopy;
+  if (small_row(f, e1 - e0)) {
+    uint32_t lw = 0;
+    while ((1ull << lw) < mx) ++lw;
+    return ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
+  }
+  *f_long = f;
+  return kShapeSkip;
+}
+
+__global__ void row_classify_kernel(RowArgs ra, int64_t upper, bool classes, uint64_t* __restrict__ n2,
+                                    uint32_t* __restrict__ list2, uint64_t* __restrict__ f2,
+                                    uint8_t* __restrict__ shape, uint32_t* __restrict__ tiny,
+                                    uint32_t* __restrict__ copy, uint32_t* __restrict__ wave) {
   const uint64_t nzr = *ra.nzr_a;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
     if ((uint64_t)r >= nzr) break;
-    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
-    uint64_t f = 0, mx = 0;
-    for (uint32_t e = e0; e < e1; ++e) {
-      const uint64_t l = ra.elen[e];
-      f += l;
-      mx = l > mx ? l : mx;
-    }
-    uint8_t sh = kShapeSkip;
-    if (f > 0 && e1 - e0 <= (uint32_t)kTinyEntries && f <= (uint64_t)kTinyProducts) {
-      sh = kShapeTiny;
-      *tiny = 1u;
-    } else if (f > 0 && e1 - e0 == 1) {
-      sh = kShapeCopy;
-      *copy = 1u;
-    } else if (f > 0 && small_row(f, e1 - e0)) {
-      *wave = 1u;
-      uint32_t lw = 0;
-      while ((1ull << lw) < mx) ++lw;
-      sh = ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
-    } else if (f > 0) {
+    uint64_t f;
+    const uint8_t sh = classify_row(ra, ra.row_start[r], ra.row_start[r + 1], classes, &f);
+    if (sh == kShapeTiny) *tiny = 1u;
+    else if (sh == kShapeCopy) *copy = 1u;
+    else if (sh <= kShapeSearch) *wave = 1u;
+    else if (f) {
       const uint64_t i = atomicAdd((unsigned long long*)n2, 1ull);
       list2[i] = (uint32_t)r;
       f2[i] = f;
     }
     shape[r] = sh;
   }
+}
+
+// ---------------------------------------------------------------- small products: all setup in one block
+//
+// For small operands (singly compressed B') the setup phases run in one block:
+// the rows of A' (heads, a block scan, compaction), the row pointers of B',
+// each A' entry's product count and B' row start, and the row classes.  The
+// kernel writes its counters itself: words[0] rows of A', [1] long rows, [2..4]
+// some row is tiny / a copy / of the one-wave kernel.
+constexpr int kSetupThreads = 1024;
+constexpr int64_t kClassMinEntries = 65536;  // A' entries from which the tiny and copy classes are used
+constexpr int64_t kSetupMaxEntries = 16384;
+constexpr uint64_t kSetupMaxRowPtr = 65536;
+
+__global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
+    RowArgs ra, FastDiv ndiv, bool classes, uint32_t* __restrict__ row_start, uint64_t* __restrict__ row_id,
+    uint64_t* __restrict__ words, uint32_t* __restrict__ bptr, uint64_t* __restrict__ elen,
+    uint32_t* __restrict__ bstart, uint32_t* __restrict__ list2, uint64_t* __restrict__ f2,
+    uint8_t* __restrict__ shape) {
+  __shared__ uint32_t wsum[kSetupThreads / kWave + 1];
+  __shared__ uint32_t s_cnt[4];  // long rows, tiny, copy, wave
+  const int64_t na = ra.nnz_a, nb = ra.nnz_b;
+  const int tid = threadIdx.x;
+  if (tid < 4) s_cnt[tid] = 0;
+  // row pointers of B'
+  for (int64_t e = tid; e <= nb; e += kSetupThreads) {
+    const uint64_t lo = e == 0 ? 0 : fd_div(ndiv, ra.b_livs[e - 1]) + 1;
+    const uint64_t hi = e == nb ? ra.kp : fd_div(ndiv, ra.b_livs[e]);
+    for (uint64_t r = lo; r <= hi; ++r) bptr[r] = (uint32_t)e;
+  }
+  // rows of A': each thread counts the row heads of a contiguous run of entries
+  const int64_t per = (na + kSetupThreads - 1) / kSetupThreads;
+  const int64_t e0 = (int64_t)tid * per < na ? (int64_t)tid * per : na;
+  const int64_t e1 = e0 + per < na ? e0 + per : na;
+  uint32_t heads = 0;
+  for (int64_t e = e0; e < e1; ++e)
+    heads += (e == 0 || fd_div(ra.kdiv, ra.a_livs[e]) != fd_div(ra.kdiv, ra.a_livs[e - 1])) ? 1u : 0u;
+  uint32_t nzr;
+  uint32_t r = block_exclusive_scan(heads, wsum, nzr);
+  for (int64_t e = e0; e < e1; ++e) {
+    const uint64_t row = fd_div(ra.kdiv, ra.a_livs[e]);
+    if (e == 0 || row != fd_div(ra.kdiv, ra.a_livs[e - 1])) {
+      row_start[r] = (uint32_t)e;
+      row_id[r] = row;
+      ++r;
+    }
+  }
+  if (tid == 0) row_start[nzr] = (uint32_t)na;
+  __syncthreads();
+  // each A' entry: its B' row
+  for (int64_t e = tid; e < na; e += kSetupThreads) {
+    uint64_t j;
+    fd_divmod(ra.kdiv, ra.a_livs[e], j);
+    bstart[e] = bptr[j];
+    elen[e] = bptr[j + 1] - bptr[j];
+  }
+  __syncthreads();
+  // row classes
+  for (uint32_t rr = tid; rr < nzr; rr += kSetupThreads) {
+    uint64_t f;
+    const uint8_t sh = classify_row(ra, row_start[rr], row_start[rr + 1], classes, &f);
+    if (sh == kShapeTiny) s_cnt[1] = 1u;
+    else if (sh == kShapeCopy) s_cnt[2] = 1u;
+    else if (sh <= kShapeSearch) s_cnt[3] = 1u;
+    else if (f) {
+      const uint32_t i = atomicAdd(&s_cnt[0], 1u);
+      list2[i] = rr;
+      f2[i] = f;
+    }
+    shape[rr] = sh;
+  }
+  __syncthreads();
+  if (tid < 5) words[tid] = tid == 0 ? (uint64_t)nzr : (uint64_t)s_cnt[tid - 1];
 }
 
 // ---------------------------------------------------------------- one wave per row, rows in chunks
@@ -483,43 +565,64 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   ra.kp = kp;
   ra.np = np;
   const FastDiv ndiv = make_fastdiv(np);
-  // rows of A'
-  Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
-  ra.row_start = arows.starts;
-  ra.row_id = arows.ids;
-  ra.nzr_a = arows.count;
-  // compressed B'
-  if (dense) {
-    if (kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "contract: singly-compressed row pointer of more than 2^34 entries");
-    uint32_t* bptr = s.get<uint32_t>(kp + 1);
-    LCO_LAUNCH(ctx, "dense_ptr", dense_ptr_kernel, grid_for(ctx, nb + 1, 256), 256, 0, B->livs, nb, ndiv, kp, bptr);
-    ra.bptr = bptr;
-  } else {
-    Segments brows = segment_livs(ctx, s, B->livs, nb, ndiv);
-    ra.brow_id = brows.ids;
-    ra.brow_start = brows.starts;
-    ra.nzr_b = brows.count;
-  }
-  // product counts per A' entry and their prefix
+  // the tiny and copy row classes pay for their launches only on large products
+  const bool classes = na >= kClassMinEntries;
+  const bool small = dense && na <= kSetupMaxEntries && nb <= kSetupMaxEntries && kp < kSetupMaxRowPtr;
   uint64_t* len = s.get<uint64_t>(na);
   uint64_t* poff = s.get<uint64_t>(na + 1);
   uint32_t* bstart = s.get<uint32_t>(na);
-  if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
-  else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
-  ra.bstart = bstart;
-  ra.elen = len;
-  // row shapes; long rows collected with their product counts
-  // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
-  uint64_t* n2_dev = s.get<uint64_t>(4);
-  uint64_t* flags_dev = n2_dev + 1;
   uint32_t* list2 = s.get<uint32_t>(na);
   uint64_t* f2 = s.get<uint64_t>(na);
-  memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
   uint8_t* shape = s.get<uint8_t>(na);
-  LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, n2_dev, list2, f2,
-             shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
-  const uint64_t* rb1[5] = {arows.count, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
-  const uint64_t* h = readback(ctx, rb1, 5);
+  ra.bstart = bstart;
+  ra.elen = len;
+  const uint64_t* h;
+  if (small) {
+    // rows of A', row pointers of B', entry lengths and row classes in one launch
+    uint32_t* row_start = s.get<uint32_t>(na + 1);
+    uint64_t* row_id = s.get<uint64_t>(na);
+    uint64_t* words = s.get<uint64_t>(5);
+    uint32_t* bptr = s.get<uint32_t>(kp + 1);
+    ra.row_start = row_start;
+    ra.row_id = row_id;
+    ra.nzr_a = words;
+    ra.bptr = bptr;
+    LCO_LAUNCH(ctx, "row_setup_small", row_setup_small_kernel, 1, kSetupThreads, 0, ra, ndiv, classes, row_start,
+               row_id, words, bptr, len, bstart, list2, f2, shape);
+    const uint64_t* rb1[5] = {words, words + 1, words + 2, words + 3, words + 4};
+    h = readback(ctx, rb1, 5);
+  } else {
+    // rows of A'
+    Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
+    ra.row_start = arows.starts;
+    ra.row_id = arows.ids;
+    ra.nzr_a = arows.count;
+    // compressed B'
+    if (dense) {
+      if (kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "contract: singly-compressed row pointer of more than 2^34 entries");
+      uint32_t* bptr = s.get<uint32_t>(kp + 1);
+      LCO_LAUNCH(ctx, "dense_ptr", dense_ptr_kernel, grid_for(ctx, nb + 1, 256), 256, 0, B->livs, nb, ndiv, kp,
+                 bptr);
+      ra.bptr = bptr;
+    } else {
+      Segments brows = segment_livs(ctx, s, B->livs, nb, ndiv);
+      ra.brow_id = brows.ids;
+      ra.brow_start = brows.starts;
+      ra.nzr_b = brows.count;
+    }
+    // product count and B' row start of each A' entry
+    if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+    else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+    // row shapes; long rows collected with their product counts
+    // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
+    uint64_t* n2_dev = s.get<uint64_t>(4);
+    uint64_t* flags_dev = n2_dev + 1;
+    memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
+    LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, classes, n2_dev,
+               list2, f2, shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
+    const uint64_t* rb1[5] = {arows.count, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
+    h = readback(ctx, rb1, 5);
+  }
   const uint64_t nzr = h[0], n2 = h[1];
   const bool tiny = h[2] != 0, copy = h[3] != 0, wave = h[4] != 0;
   const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);  // 64 rows per wave and sweep
@@ -538,7 +641,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   // per-row output counts
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
   uint64_t* coff = s.get<uint64_t>(nzr + 1);
-  memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));
+  if (!wave) memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));  // else the one-wave kernel writes every count
   // rows per chunk: up to 64, but enough chunks for every resident wave (32 per compute unit)
   const uint64_t resident = (uint64_t)ctx->num_cus * 32;
   const int chunk_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>(kChunkRows, nzr / resident));
