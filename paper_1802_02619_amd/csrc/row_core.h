@@ -71,9 +71,6 @@ __device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, doubl
 __device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
   return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
 }
-__device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
-  return (c * 0x9E3779B1u) >> 25;  // 7 bits, for columns below 2^32
-}
 
 // Per-row shape codes of the one-wave kernel.
 constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
@@ -88,72 +85,6 @@ constexpr int kTinyProducts = 16;
 // product without any search.  The shape code is log2 W for those rows.
 __device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
   return f <= (uint64_t)kWave && t <= (uint32_t)kWave;
-}
-
-// One wave per row, rows in their natural (ascending) order.  Each lane ends up
-// with at most one product: its A' entry `ent`, its column and (numeric) value.
-template <bool NUMERIC>
-__device__ __forceinline__ void gather_products(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                                int lane, bool& valid, int& ent, uint64_t& col, double& v) {
-  valid = false;
-  ent = 0;
-  col = kEmpty;
-  v = 0.0;
-  if (sh != kShapeSearch) {
-    // entry-major lanes: no search
-    const int e = lane >> sh, k = lane & ((1 << sh) - 1);
-    if (e < t) {
-      const uint32_t ge = e0 + e;
-      const uint64_t len = ra.poff[ge + 1] - ra.poff[ge];
-      if ((uint64_t)k < len) {
-        const uint64_t j = ra.a_livs[ge - ra.a_base] - ra.kp * row;
-        const uint32_t q = ra.bstart[ge] + (uint32_t)k;
-        valid = true;
-        ent = e;
-        col = ra.b_livs[q] - ra.np * j;
-        if (NUMERIC) v = ra.a_vals[ge - ra.a_base] * ra.b_vals[q];
-      }
-    }
-    return;
-  }
-  // general small row: product p = lane, found by a binary search over the
-  // entries' inclusive product counts
-  uint64_t j = 0;
-  uint32_t len = 0, bs = 0, rel = 0;
-  double av = 0.0;
-  const uint64_t p0 = ra.poff[e0];
-  if (lane < t) {
-    const uint32_t ge = e0 + lane;
-    j = ra.a_livs[ge - ra.a_base] - ra.kp * row;
-    rel = (uint32_t)(ra.poff[ge] - p0);
-    len = (uint32_t)(ra.poff[ge + 1] - ra.poff[ge]);
-    bs = ra.bstart[ge];
-    if (NUMERIC) av = ra.a_vals[ge - ra.a_base];
-  }
-  const uint32_t incl = rel + len;
-  const uint32_t f = (uint32_t)__shfl((int)incl, t - 1, kWave);
-  const uint32_t p = (uint32_t)lane;
-  int lo = 0, hi = t - 1;
-#pragma unroll
-  for (int it = 0; it < 6; ++it) {
-    const int mid = (lo + hi) >> 1;
-    const uint32_t x = (uint32_t)__shfl((int)incl, mid, kWave);
-    if (lo < hi) {
-      if (x > p) hi = mid;
-      else lo = mid + 1;
-    }
-  }
-  const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
-  const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
-  const uint64_t j_e = __shfl(j, lo, kWave);
-  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
-  if (p < f) {
-    const uint32_t q = bs_e + (p - excl_e);
-    valid = true;
-    ent = lo;
-    col = ra.b_livs[q] - ra.np * j_e;
-    if (NUMERIC) v = av_e * ra.b_vals[q];
-  }
 }
 
 // Shared memory of the one-wave-per-row kernels (one row table per wave).
@@ -172,7 +103,8 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
 // The products of one small row from the entry window (lane l holds entry w0 + l:
 // its product count, B' row start, value, and its A' LIV (numeric pass) or
 // j * n' (symbolic pass: the LIV of its B' row's first position)); each lane
-// ends up with at most one product, as in gather_products.
+// ends up with at most one product: its A' entry `ent` within the row, its
+// column and (numeric) value.
 template <bool NUMERIC>
 __device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
                                                 uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row,
@@ -381,36 +313,6 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     o.val = acc;
   }
   return (uint32_t)__popcll(hmask);
-}
-
-template <bool ACC, bool NUMERIC>
-__device__ __forceinline__ uint32_t small_row_compute(const RowArgs& ra, uint32_t e0, int t, uint64_t row,
-                                                      uint8_t sh, bool narrow, int w, int lane, const RowSmem& sm,
-                                                      RowOut& o) {
-  bool valid;
-  int ent;
-  uint64_t col;
-  double v;
-  gather_products<NUMERIC>(ra, e0, t, row, sh, lane, valid, ent, col, v);
-  return row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
-}
-
-// Symbolic (the row's output count into *cnt_slot) or numeric (the sorted row
-// written at out_base) product of one small row.
-template <bool ACC, bool NUMERIC>
-__device__ __forceinline__ void small_row_body(const RowArgs& ra, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                               bool narrow, int w, int lane, const RowSmem& sm,
-                                               uint64_t* cnt_slot, uint64_t out_base, uint64_t* __restrict__ out_livs,
-                                               double* __restrict__ out_vals) {
-  RowOut o;
-  const uint32_t d = small_row_compute<ACC, NUMERIC>(ra, e0, t, row, sh, narrow, w, lane, sm, o);
-  if (!NUMERIC) {
-    if (lane == 0) *cnt_slot = d;
-  } else if (o.own) {
-    const uint64_t p = out_base + o.rank;
-    out_livs[p] = o.col + ra.np * row;
-    out_vals[p] = o.val;
-  }
 }
 
 }  // namespace

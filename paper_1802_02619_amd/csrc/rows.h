@@ -36,7 +36,6 @@ struct RowArgs {
   const uint64_t* elen = nullptr;        // products per A' entry (nnz_a)
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
   const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
-  int64_t a_base = 0;                    // index of A' entry 0 in the entry numbering of poff/bstart
 };
 
 // C' = A' * B' row by row; `dense` selects singly (CSR) or doubly (DCSR)
