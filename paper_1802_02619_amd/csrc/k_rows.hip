@@ -82,6 +82,23 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
   }
 }
 
+// Rows of A' taken densely, every row 0..m'-1 including empty ones (for
+// products where A' has few empty rows): row_start[r] = first entry of row r,
+// row_id[r] = r, *count = m'.  Empty rows hold no products and are skipped.
+__global__ void dense_rows_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv kdiv, uint64_t mp,
+                                  uint32_t* __restrict__ row_start, uint64_t* __restrict__ row_id,
+                                  uint64_t* __restrict__ count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = e == 0 ? 0 : fd_div(kdiv, livs[e - 1]) + 1;
+    const uint64_t hi = e == n ? mp : fd_div(kdiv, livs[e]);
+    for (uint64_t r = lo; r <= hi; ++r) {
+      row_start[r] = (uint32_t)e;
+      if (r < mp) row_id[r] = r;
+    }
+    if (e == n) *count = mp;
+  }
+}
+
 // For each A' entry: the start and length of the B' row its column selects.
 template <bool DENSE>
 __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_t* __restrict__ bstart) {
@@ -551,7 +568,6 @@ Segments segment_livs(lco_ctx ctx, Scratch& s, const uint64_t* livs, int64_t n, 
 
 lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, uint64_t mp, uint64_t kp,
                       uint64_t np, bool dense, bool acc, int out_order, const uint64_t* out_dims) {
-  (void)mp;
   const int64_t na = A->nnz, nb = B->nnz;
   Scratch s(ctx);
   RowArgs ra;
@@ -568,12 +584,15 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   // the tiny and copy row classes pay for their launches only on large products
   const bool classes = na >= kClassMinEntries;
   const bool small = dense && na <= kSetupMaxEntries && nb <= kSetupMaxEntries && kp < kSetupMaxRowPtr;
+  // rows of A' taken densely (all m' of them) when few are empty
+  const bool dense_rows = !small && mp <= 2 * (uint64_t)na && mp < UINT32_MAX;
+  const uint64_t rows_cap = dense_rows ? std::max<uint64_t>(mp, (uint64_t)na) : (uint64_t)na;
   uint64_t* len = s.get<uint64_t>(na);
   uint64_t* poff = s.get<uint64_t>(na + 1);
   uint32_t* bstart = s.get<uint32_t>(na);
-  uint32_t* list2 = s.get<uint32_t>(na);
-  uint64_t* f2 = s.get<uint64_t>(na);
-  uint8_t* shape = s.get<uint8_t>(na);
+  uint32_t* list2 = s.get<uint32_t>(rows_cap);
+  uint64_t* f2 = s.get<uint64_t>(rows_cap);
+  uint8_t* shape = s.get<uint8_t>(rows_cap);
   ra.bstart = bstart;
   ra.elen = len;
   const uint64_t* h;
@@ -592,11 +611,25 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     const uint64_t* rb1[5] = {words, words + 1, words + 2, words + 3, words + 4};
     h = readback(ctx, rb1, 5);
   } else {
-    // rows of A'
-    Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
-    ra.row_start = arows.starts;
-    ra.row_id = arows.ids;
-    ra.nzr_a = arows.count;
+    // rows of A': all m' of them when few are empty (one launch), else the non-empty ones
+    const uint64_t* nzr_word;
+    if (dense_rows) {
+      uint32_t* row_start = s.get<uint32_t>(mp + 1);
+      uint64_t* row_id = s.get<uint64_t>(mp);
+      uint64_t* count = s.get<uint64_t>(1);
+      LCO_LAUNCH(ctx, "dense_rows", dense_rows_kernel, grid_for(ctx, na + 1, 256), 256, 0, A->livs, na, ra.kdiv, mp,
+                 row_start, row_id, count);
+      ra.row_start = row_start;
+      ra.row_id = row_id;
+      ra.nzr_a = count;
+      nzr_word = count;
+    } else {
+      Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
+      ra.row_start = arows.starts;
+      ra.row_id = arows.ids;
+      ra.nzr_a = arows.count;
+      nzr_word = arows.count;
+    }
     // compressed B'
     if (dense) {
       if (kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "contract: singly-compressed row pointer of more than 2^34 entries");
@@ -618,9 +651,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     uint64_t* n2_dev = s.get<uint64_t>(4);
     uint64_t* flags_dev = n2_dev + 1;
     memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
-    LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, na, 256), 256, 0, ra, na, classes, n2_dev,
+    LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, (int64_t)rows_cap, 256), 256, 0, ra,
+               (int64_t)rows_cap, classes, n2_dev,
                list2, f2, shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
-    const uint64_t* rb1[5] = {arows.count, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
+    const uint64_t* rb1[5] = {nzr_word, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
     h = readback(ctx, rb1, 5);
   }
   const uint64_t nzr = h[0], n2 = h[1];
