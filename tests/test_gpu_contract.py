@@ -248,6 +248,26 @@ def test_row_classes_mixed(lco_lib, gpu_ctx, oracle_mod):
         t.destroy()
 
 
+def test_dense_rows_with_empty_rows(lco_lib, gpu_ctx, oracle_mod):
+    """A' with at most twice as many rows as entries takes its row starts over all
+    rows: here every third row is empty and so are the last 100 (and the last row),
+    with more than 16384 entries (not the one-block setup)."""
+    rng = np.random.default_rng(55)
+    m, k, n = 9000, 300, 400
+    rows = [i for i in range(m - 100) if i % 3]
+    ca = np.array([(i, int(c)) for i in rows for c in rng.choice(k, 3, replace=False)], dtype=np.uint64)
+    va = rng.integers(-3, 4, len(ca)).astype(np.float64)
+    va[va == 0] = 1.0
+    cb, vb = L.random_sparse(rng, [k, n], 2400, integer_values=True)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    assert m <= 2 * len(ca) and len(ca) > 16384
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [0, 2], exact=True,
+            algos=("auto", "CSR", "CSRNA", "DCSR"))
+    for t in (ga, gb):
+        t.destroy()
+
+
 @pytest.mark.parametrize("b_len", [1, 2, 4])
 def test_tiny_rows_staged_and_direct(lco_lib, gpu_ctx, oracle_mod, b_len):
     """Rows of at most 4 entries and 16 products only (one lane per row): with
