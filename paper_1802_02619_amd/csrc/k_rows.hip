@@ -10,17 +10,26 @@
 // LIV = col + n'*row.  Each output entry sums its products in ascending order
 // of the contracted index starting from 0.0.
 //
-// Work split: the non-empty rows of A' are binned by their product count f(i).
+// Setup: the rows of A' (row starts and ids), the row pointers of B' (or its
+// non-empty rows when doubly compressed), and for every A' entry its product
+// count and B' row start.  Rows of A' come from one pointer kernel over all m'
+// rows when few are empty, else from head flags, a scan and a compaction; small
+// products do the whole setup in one block.
+//
+// Work split: the rows of A' are binned by their product count f(i).
 //  - at most 4 A' entries and f(i) <= 16: one lane per row (k-way merge of the
-//    entries' B' rows).
-//  - one A' entry and f(i) > 16: a wave copies the scaled B' row.
-//  - f(i) <= 64 and at most 64 A' entries: one wave per row.  CSR/DCSR keep an
-//    LDS hash table (column -> slot) as the sparse accumulator, accumulate in
-//    registers (slot s lives in lane s mod 64) in product order, then sort the
-//    row's distinct columns with a wave bitonic network.  CSRNA sorts the
-//    (column, product index) pairs and sums runs.
+//    entries' B' rows); from 65536 A' entries up.
+//  - one A' entry and f(i) > 16: a wave copies the scaled B' row; idem.
+//  - f(i) <= 64 and at most 64 A' entries: one wave per row, rows in chunks.
+//    CSR/DCSR insert the row's columns into an LDS hash table; each product
+//    records its lane under its column, and the column's first product (its
+//    owner) sums the column's values in lane order, i.e. ascending A' entry;
+//    owners are ranked by column and written in order.  CSRNA sorts the
+//    (column, product index) pairs with a wave bitonic network and sums runs.
 //  - larger rows: products are expanded to global memory keyed by (row rank,
 //    column), sorted with the stable radix engine and summed per run.
+// A symbolic pass counts every row's outputs, a scan places the rows, and the
+// numeric pass writes them.
 #include <algorithm>
 #include <cstring>
 
