@@ -128,21 +128,17 @@ __global__ void bt_classify_kernel(const uint32_t* __restrict__ rs, const uint32
 // window holds entries of one instance only; a row of another instance, or
 // entries outside the window, move it.
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void bt_chunk_kernel(
+__global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
     const BInst* __restrict__ in, const uint32_t* __restrict__ rs, const uint64_t* __restrict__ rid,
     const uint32_t* __restrict__ rinst, const uint8_t* __restrict__ shape, const uint32_t* __restrict__ fallback,
     const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, int chunk_rows,
     uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs,
     double* __restrict__ out_vals) {
-  __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
-  __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
-  __shared__ double s_vals[kRowWaves][kWave + 8];
-  __shared__ uint64_t s_lanes[kRowWaves][2 * kWave];
-  __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
-  const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
+  __shared__ RowLds s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const uint64_t nchunks = ((uint64_t)nrows + chunk_rows - 1) / chunk_rows;
   const RowSpan span = xcd_row_span(nchunks, w);
+  if constexpr (ACC && NUMERIC) tab_clear(s_lds[w], lane);
   for (uint64_t c = span.first; c < span.end; c += span.step) {
     const uint64_t r0 = c * chunk_rows;
     const int rows = (int)((uint64_t)nrows - r0 < (uint64_t)chunk_rows ? (uint64_t)nrows - r0 : (uint64_t)chunk_rows);
@@ -189,14 +185,11 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void bt_chunk_kernel(
           }
         }
       }
-      bool valid;
-      int ent;
-      uint64_t col;
-      double v;
-      window_products<NUMERIC>(x.b_livs, x.b_vals, x.np, x.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av,
-                               valid, ent, col, v);
+      RowProduct<NUMERIC> pr;
+      window_products<NUMERIC>(x.b_livs, x.b_vals, x.np, x.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr);
       RowOut o;
-      const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, x.np < (1ull << 32), w, lane, sm, o);
+      const uint32_t d =
+          row_reduce<ACC, NUMERIC>(pr.valid, pr.ent, pr.col(), pr.val(), t, x.np < (1ull << 32), lane, s_lds[w], o);
       if (!NUMERIC) {
         if (lane == i) my_cnt = d;
       } else if (o.own) {

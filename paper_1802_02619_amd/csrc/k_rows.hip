@@ -258,22 +258,18 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
 constexpr int kChunkRows = kWave;
 
 template <bool ACC, bool NUMERIC>
-__global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
+__global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
                                                                 const uint8_t* __restrict__ shape,
                                                                 uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
                                                                 uint64_t* __restrict__ out_livs,
                                                                 double* __restrict__ out_vals) {
-  __shared__ uint64_t s_hash[kRowWaves][2 * kWave];
-  __shared__ uint32_t s_hash32[kRowWaves][2 * kWave];
-  __shared__ double s_vals[kRowWaves][kWave + 8];
-  __shared__ uint64_t s_lanes[kRowWaves][2 * kWave];
-  __shared__ __align__(16) uint32_t s_own[kRowWaves][kWave];
-  const RowSmem sm{s_hash, s_hash32, s_vals, s_lanes, s_own};
+  __shared__ RowLds s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const bool narrow = ra.np < (1ull << 32);
   const uint64_t nchunks = ((uint64_t)nzr + chunk_rows - 1) / chunk_rows;
   const RowSpan span = xcd_row_span(nchunks, w);
+  if constexpr (ACC && NUMERIC) tab_clear(s_lds[w], lane);
   for (uint64_t c = span.first; c < span.end; c += span.step) {
     const uint64_t r0 = c * chunk_rows;
     const int rows = (int)((uint64_t)nzr - r0 < (uint64_t)chunk_rows ? (uint64_t)nzr - r0 : (uint64_t)chunk_rows);
@@ -295,12 +291,15 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void row_chunk_kernel
     uint32_t x_len = 0, x_bs = 0;
     uint64_t x_jn = 0;
     double x_av = 0.0;
-    for (int i = 0; i < rows; ++i) {
+    // Rows of this kernel (no products, long rows and rows of the lane and copy
+    // kernels are skipped).  The B' loads of the next row are issued before the
+    // current row is reduced, so that their latency overlaps its LDS work.
+    uint64_t todo = __ballot(lane < rows && m_sh <= kShapeSearch);
+    RowProduct<NUMERIC> next;
+    auto stage = [&](int i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
-      if (sh > kShapeSearch) continue;  // no products, a long row, or a row of the lane or copy kernels
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
       const uint64_t row = readlane_u64(m_id, i);
-      const int t = (int)(e1 - e0);
       if ((int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
         w0 = e0;
         const int64_t e = w0 + lane;
@@ -317,19 +316,26 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 1 : 8) void row_chunk_kernel
           if (NUMERIC) x_av = ra.a_vals[e];
         }
       }
-      bool valid;
-      int ent;
-      uint64_t col;
-      double v;
-      window_products<NUMERIC>(ra.b_livs, ra.b_vals, ra.np, ra.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av,
-                               valid, ent, col, v);
+      window_products<NUMERIC>(ra.b_livs, ra.b_vals, ra.np, ra.kp, e0, (int)(e1 - e0), row, sh, lane, w0, x_len,
+                               x_bs, x_jn, x_av, next);
+    };
+    if (todo) stage(__builtin_ctzll(todo));
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const bool valid = next.valid;
+      const int ent = next.ent;
+      const uint64_t col = next.col();
+      const double v = next.val();
+      const int t = (int)(readlane_u32(m_s1, i) - readlane_u32(m_s0, i));
+      if (todo) stage(__builtin_ctzll(todo));
       RowOut o;
-      const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, w, lane, sm, o);
+      const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, lane, s_lds[w], o);
       if (!NUMERIC) {
         if (lane == i) my_cnt = d;
       } else if (o.own) {
         const uint64_t pos = readlane_u64(m_off, i) + o.rank;
-        out_livs[pos] = o.col + ra.np * row;
+        out_livs[pos] = o.col + ra.np * readlane_u64(m_id, i);
         out_vals[pos] = o.val;
       }
     }

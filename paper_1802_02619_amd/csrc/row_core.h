@@ -71,6 +71,9 @@ __device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, doubl
 __device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
   return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
 }
+__device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
+  return (c * 0x9E3779B1u) >> 25;  // 7 bits
+}
 
 // Per-row shape codes of the one-wave kernel.
 constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
@@ -87,34 +90,57 @@ __device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
   return f <= (uint64_t)kWave && t <= (uint32_t)kWave;
 }
 
-// Shared memory of the one-wave-per-row kernels (one row table per wave).
-struct RowSmem {
-  uint64_t (*hash)[2 * kWave];
-  uint32_t (*hash32)[2 * kWave];
-  double (*vals)[kWave + 8];      // each lane's product value, and a zero at index kWave
-  uint64_t (*lanes)[2 * kWave];   // per hash slot: the lanes whose product has that column
-  uint32_t (*own)[kWave];
+// LDS of one wave of the one-wave-per-row kernels.  A numeric row with at most
+// kTabEntries entries and 32-bit columns sums through the table
+// tab[entry][owner lane], which is all +0.0 between rows; other numeric
+// accumulator rows use the lane masks and staged values that share its space
+// and clear them again when done.  The symbolic pass keys 32-bit columns in
+// hash32, in the same space.
+constexpr int kTabEntries = 7;
+struct alignas(16) RowLds {
+  uint64_t hash[2 * kWave];  // hash slots: column (with the owner lane above 32-bit columns in table rows)
+  uint32_t own[kWave];       // owners' columns in lane order (rank by broadcast compares)
+  union {
+    double tab[kTabEntries][kWave + 1];  // per A' entry, per owner number: the product's value (rows padded by one
+                                         // value, so that one owner's cells fall in different banks)
+    struct {
+      uint64_t lanes[2 * kWave];  // per hash slot: the lanes whose product has that column
+      double vals[kWave + 8];     // each lane's product value, and a zero at index kWave
+    } mask;
+    uint32_t hash32[2 * kWave];
+  };
 };
+static_assert(sizeof(RowLds) % 16 == 0 && offsetof(RowLds, own) % 16 == 0, "RowLds alignment");
+
+// Clears a wave's table (once, before its first row).
+__device__ __forceinline__ void tab_clear(RowLds& L, int lane) {
+#pragma unroll
+  for (int e = 0; e < kTabEntries; ++e) {
+    L.tab[e][lane] = 0.0;
+    if (lane == 0) L.tab[e][kWave] = 0.0;
+  }
+}
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
   return ((uint64_t)readlane_u32((uint32_t)(x >> 32), l) << 32) | readlane_u32((uint32_t)x, l);
 }
 
-// The products of one small row from the entry window (lane l holds entry w0 + l:
-// its product count, B' row start, value, and its A' LIV (numeric pass) or
-// j * n' (symbolic pass: the LIV of its B' row's first position)); each lane
-// ends up with at most one product: its A' entry `ent` within the row, its
-// column and (numeric) value.
+// Locates the products of one small row in the entry window (lane l holds
+// entry w0 + l: its product count, B' row start, value, and its A' LIV (numeric
+// pass) or j * n' (symbolic pass: the LIV of its B' row's first position)).
+// Each lane ends up with at most one product: its A' entry `ent` within the
+// row, its B' position `q`, the amount `off` its B' LIV exceeds its column by,
+// and (numeric) the A' value `av` that scales it.  The caller loads B' at q.
 template <bool NUMERIC>
-__device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
-                                                uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row,
-                                                uint8_t sh, int lane, int64_t w0, uint32_t x_len, uint32_t x_bs,
-                                                uint64_t x_jn, double x_av, bool& valid, int& ent, uint64_t& col,
-                                                double& v) {
+__device__ __forceinline__ void window_locate(uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row, uint8_t sh,
+                                              int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_jn,
+                                              double x_av, bool& valid, int& ent, uint32_t& q, uint64_t& off,
+                                              double& av) {
   valid = false;
   ent = 0;
-  col = kEmpty;
-  v = 0.0;
+  q = 0;
+  off = 0;
+  av = 0.0;
   const int first = (int)((int64_t)e0 - w0);  // window lane of the row's first entry
   if (sh != kShapeSearch) {
     // entry-major lanes: lane = entry * W + position
@@ -123,13 +149,12 @@ __device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_l
     const uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
     const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
     const uint64_t jn = __shfl(x_jn, src, kWave);
-    const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+    if (NUMERIC) av = __shfl(x_av, src, kWave);
     if (e < t && (uint32_t)k < len) {
-      const uint32_t q = bs + (uint32_t)k;
       valid = true;
       ent = e;
-      col = b_livs[q] - (NUMERIC ? np * (jn - kp * row) : jn);
-      if (NUMERIC) v = av * b_vals[q];
+      q = bs + (uint32_t)k;
+      off = NUMERIC ? np * (jn - kp * row) : jn;
     }
     return;
   }
@@ -139,7 +164,7 @@ __device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_l
   uint32_t len = (uint32_t)__shfl((int)x_len, src, kWave);
   const uint32_t bs = (uint32_t)__shfl((int)x_bs, src, kWave);
   const uint64_t jn = __shfl(x_jn, src, kWave);
-  const double av = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
+  const double a = NUMERIC ? __shfl(x_av, src, kWave) : 0.0;
   if (lane >= t) len = 0;
   const uint32_t incl = wave_inclusive_scan(len);
   const uint32_t rel = incl - len;
@@ -158,14 +183,47 @@ __device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_l
   const uint32_t excl_e = (uint32_t)__shfl((int)rel, lo, kWave);
   const uint32_t bs_e = (uint32_t)__shfl((int)bs, lo, kWave);
   const uint64_t jn_e = __shfl(jn, lo, kWave);
-  const double av_e = NUMERIC ? __shfl(av, lo, kWave) : 0.0;
+  if (NUMERIC) av = __shfl(a, lo, kWave);
   if (p < f) {
-    const uint32_t q = bs_e + (p - excl_e);
     valid = true;
     ent = lo;
-    col = b_livs[q] - (NUMERIC ? np * (jn_e - kp * row) : jn_e);
-    if (NUMERIC) v = av_e * b_vals[q];
+    q = bs_e + (p - excl_e);
+    off = NUMERIC ? np * (jn_e - kp * row) : jn_e;
   }
+}
+
+// One lane's product of a small row: where it is, and its B' entry once loaded.
+template <bool NUMERIC>
+struct RowProduct {
+  bool valid = false;
+  int ent = 0;
+  uint64_t off = 0;
+  double av = 0.0;
+  uint64_t liv = 0;    // B' LIV (in flight until first use)
+  double bval = 0.0;   // B' value (numeric)
+
+  __device__ __forceinline__ void load(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
+                                       uint32_t q) {
+    if (valid) {
+      liv = b_livs[q];
+      if (NUMERIC) bval = b_vals[q];
+    }
+  }
+  // the product's column (kEmpty when this lane holds none) and value
+  __device__ __forceinline__ uint64_t col() const { return valid ? liv - off : kEmpty; }
+  __device__ __forceinline__ double val() const { return (NUMERIC && valid) ? av * bval : 0.0; }
+};
+
+// Locates a small row's products in the window and issues their B' loads.
+template <bool NUMERIC>
+__device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
+                                                uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row,
+                                                uint8_t sh, int lane, int64_t w0, uint32_t x_len, uint32_t x_bs,
+                                                uint64_t x_jn, double x_av, RowProduct<NUMERIC>& pr) {
+  uint32_t q;
+  window_locate<NUMERIC>(np, kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr.valid, pr.ent, q, pr.off,
+                         pr.av);
+  pr.load(b_livs, b_vals, q);
 }
 
 // One lane's share of a small row's product: at most one output entry.
@@ -182,47 +240,49 @@ struct RowOut {
 // The reduction of one small row's products (one per lane: `valid`, its A'
 // entry `ent` in the row, column `col`, value `v`) into the row's output.
 template <bool ACC, bool NUMERIC>
-__device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col, double v, int t, bool narrow, int w,
-                                               int lane, const RowSmem& sm, RowOut& o) {
+__device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col, double v, int t, bool narrow,
+                                               int lane, RowLds& L, RowOut& o) {
   if (ACC) {
-    // sparse accumulator: an LDS hash table maps a column to a slot (32-bit
-    // keys when the columns allow), and one FP64 accumulator per slot
-    if (narrow) {
-      sm.hash32[w][lane] = 0xFFFFFFFFu;
-      sm.hash32[w][lane + kWave] = 0xFFFFFFFFu;
+    // Sparse accumulator: an LDS hash table maps a column to a slot, and the
+    // lane that inserts a column owns it.  Numeric rows of at most kTabEntries
+    // entries with 32-bit columns ("table rows") store the owner lane beside
+    // the column, so that every product learns its owner.
+    const bool table = NUMERIC && narrow && t <= kTabEntries;
+    const bool key32 = !NUMERIC && narrow;
+    if (key32) {
+      L.hash32[lane] = 0xFFFFFFFFu;
+      L.hash32[lane + kWave] = 0xFFFFFFFFu;
     } else {
-      sm.hash[w][lane] = kEmpty;
-      sm.hash[w][lane + kWave] = kEmpty;
+      L.hash[lane] = kEmpty;
+      L.hash[lane + kWave] = kEmpty;
     }
-    if (NUMERIC) {
-      sm.lanes[w][lane] = 0;
-      sm.lanes[w][lane + kWave] = 0;
-      if (lane == 0) sm.vals[w][kWave] = 0.0;
+    if (NUMERIC && !table) {
+      L.mask.lanes[lane] = 0;
+      L.mask.lanes[lane + kWave] = 0;
+      if (lane == 0) L.mask.vals[kWave] = 0.0;
     }
     wave_lds_sync();
-    uint32_t slot = valid ? hash_slot(col) : 0;
+    uint32_t slot = valid ? (narrow ? hash_slot32((uint32_t)col) : hash_slot(col)) : 0;
+    // probe until the slot is empty (this lane inserts the column) or holds the
+    // column (at most 64 columns in 128 slots: a free slot always exists)
     bool isnew = false;
+    uint64_t prev = kEmpty;
     if (valid) {
-      if (narrow) {
+      if (key32) {
         const uint32_t c32 = (uint32_t)col;
         for (int probe = 0; probe < 2 * kWave; ++probe) {
-          const uint32_t prev = atomicCAS(&sm.hash32[w][slot], 0xFFFFFFFFu, c32);
-          if (prev == 0xFFFFFFFFu) {
-            isnew = true;
-            break;
-          }
-          if (prev == c32) break;
+          const uint32_t p = atomicCAS(&L.hash32[slot], 0xFFFFFFFFu, c32);
+          isnew = p == 0xFFFFFFFFu;
+          if (isnew || p == c32) break;
           slot = (slot + 1) & (2 * kWave - 1);
         }
       } else {
+        const uint64_t key = table ? (((uint64_t)lane << 32) | (uint32_t)col) : col;
+        const uint64_t cmp = table ? 0xFFFFFFFFull : ~0ull;  // the bits that hold the column
         for (int probe = 0; probe < 2 * kWave; ++probe) {
-          const uint64_t prev = atomicCAS((unsigned long long*)&sm.hash[w][slot], (unsigned long long)kEmpty,
-                                          (unsigned long long)col);
-          if (prev == kEmpty) {
-            isnew = true;
-            break;
-          }
-          if (prev == col) break;
+          prev = atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
+          isnew = prev == kEmpty;
+          if (isnew || ((prev ^ col) & cmp) == 0) break;
           slot = (slot + 1) & (2 * kWave - 1);
         }
       }
@@ -230,18 +290,74 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     const uint64_t newmask = __ballot(isnew);
     const uint32_t distinct = (uint32_t)__popcll(newmask);
     if (NUMERIC) {
-      // Every product records its lane in its column's slot and stages its value
-      // by lane.  The owner of a column (the lane that inserted it, i.e. its
-      // first product) then sums the column's products in ascending lane order,
-      // which is ascending A' entry (contracted index) order, starting from 0.0:
-      // the values are read eight at a time (absent ones read the staged zero,
-      // and adding +0.0 to a sum that started at +0.0 changes nothing), so the
-      // reads of a group are independent and overlap.
-      if (valid) atomicOr((unsigned long long*)&sm.lanes[w][slot], 1ull << lane);
-      sm.vals[w][lane] = v;
+      if (table) {
+        // Owners are numbered d = 0, 1, ... in lane order, and output d is
+        // computed by lane d (and, when there are at most 32, also by lane
+        // d + 32, which shares the rank comparisons).  Each product stores its
+        // value at (its entry, its owner's d); owner d stores its column at d.
+        const int owner = !valid ? 0 : isnew ? lane : (int)(prev >> 32);
+        const uint32_t d = (uint32_t)__popcll(newmask & ((1ull << owner) - 1ull));
+        if (valid) L.tab[ent][d] = v;
+        if (isnew) L.own[d] = (uint32_t)col;
+        if (lane >= (int)distinct) L.own[lane] = 0xFFFFFFFFu;  // padding: larger than any column
+        wave_lds_sync();
+        const bool split = distinct <= 32;
+        const int me = split ? (lane & 31) : lane;
+        const uint32_t c32 = L.own[me];
+        // the sum runs over the entries in order, i.e. ascending contracted
+        // index, from 0.0; entries without this column hold +0.0, which cannot
+        // change a sum that started at +0.0
+        double x[kTabEntries];
+#pragma unroll
+        for (int e = 0; e < kTabEntries; ++e) x[e] = L.tab[e][me];
+        double mine = 0.0;
+#pragma unroll
+        for (int e = 0; e < kTabEntries; ++e) mine += x[e];
+        // rank: the number of smaller columns, by broadcast 16-byte LDS reads
+        // of the column list (each half of the wave takes 16 of at most 32)
+        const uint4* ol = reinterpret_cast<const uint4*>(L.own);
+        uint32_t rank = 0;
+        if (split) {
+          const int base = (lane >> 5) * 4;
+          const uint32_t nq = ((distinct < 16 ? distinct : 16) + 3) >> 2;
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) {
+            if (q < nq) {
+              const uint4 y = ol[base + q];
+              rank += (y.x < c32 ? 1u : 0u) + (y.y < c32 ? 1u : 0u) + (y.z < c32 ? 1u : 0u) + (y.w < c32 ? 1u : 0u);
+            }
+          }
+          rank += (uint32_t)__shfl_xor((int)rank, 32, kWave);
+        } else {
+          const uint32_t nq = (distinct + 3) >> 2;
+#pragma unroll
+          for (uint32_t q = 0; q < kWave / 4; ++q) {
+            if (q < nq) {
+              const uint4 y = ol[q];
+              rank += (y.x < c32 ? 1u : 0u) + (y.y < c32 ? 1u : 0u) + (y.z < c32 ? 1u : 0u) + (y.w < c32 ? 1u : 0u);
+            }
+          }
+        }
+        wave_lds_sync();
+        if (valid) L.tab[ent][d] = 0.0;  // every product clears its cell for the next row
+        o.own = lane < (int)distinct;
+        o.rank = rank;
+        o.col = c32;
+        o.val = mine;
+        return distinct;
+      }
+      // Every product records its lane in its column's slot and stages its
+      // value by lane.  The owner (the inserting lane) then sums the column's
+      // products in ascending lane order, which is ascending A' entry
+      // (contracted index) order, starting from 0.0: the values are read eight
+      // at a time (absent ones read the staged zero, and adding +0.0 to a sum
+      // that started at +0.0 changes nothing), so the reads of a group are
+      // independent.
+      if (valid) atomicOr((unsigned long long*)&L.mask.lanes[slot], 1ull << lane);
+      L.mask.vals[lane] = v;
       wave_lds_sync();
       double mine = 0.0;
-      uint64_t m = isnew ? sm.lanes[w][slot] : 0ull;
+      uint64_t m = isnew ? L.mask.lanes[slot] : 0ull;
       const int groups = (t + 7) >> 3;  // a column has at most one product per entry
       for (int g = 0; g < groups; ++g) {
         double x[8];
@@ -249,7 +365,7 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
         for (int k = 0; k < 8; ++k) {
           const int l = m ? __builtin_ctzll(m) : kWave;
           m &= m - 1;
-          x[k] = sm.vals[w][l];
+          x[k] = L.mask.vals[l];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) mine += x[k];
@@ -258,16 +374,19 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
       if (narrow && distinct <= 32) {
         // owners' columns compacted into slots [0, distinct) of a 32-slot list
         // padded with the largest column, then compared by every lane with
-        // broadcast 16-byte LDS reads (no loop, no branches)
-        if (isnew) sm.own[w][__popcll(newmask & lanemask_lt())] = (uint32_t)col;
-        if (lane >= (int)distinct && lane < 32) sm.own[w][lane] = 0xFFFFFFFFu;
+        // broadcast 16-byte LDS reads
+        if (isnew) L.own[__popcll(newmask & lanemask_lt())] = (uint32_t)col;
+        if (lane >= (int)distinct && lane < 32) L.own[lane] = 0xFFFFFFFFu;
         wave_lds_sync();
         const uint32_t c32 = (uint32_t)col;
-        const uint4* ol = reinterpret_cast<const uint4*>(sm.own[w]);
+        const uint4* ol = reinterpret_cast<const uint4*>(L.own);
+        const uint32_t nq = (distinct + 3) >> 2;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint4 x = ol[q];
-          rank += (x.x < c32 ? 1u : 0u) + (x.y < c32 ? 1u : 0u) + (x.z < c32 ? 1u : 0u) + (x.w < c32 ? 1u : 0u);
+        for (uint32_t q = 0; q < 8; ++q) {
+          if (q < nq) {
+            const uint4 y = ol[q];
+            rank += (y.x < c32 ? 1u : 0u) + (y.y < c32 ? 1u : 0u) + (y.z < c32 ? 1u : 0u) + (y.w < c32 ? 1u : 0u);
+          }
         }
       } else {
         for (uint64_t mm = newmask; mm; mm &= mm - 1) {
@@ -281,6 +400,12 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
       o.rank = rank;
       o.col = col;
       o.val = mine;
+      wave_lds_sync();
+      // the table's space is all +0.0 again
+      L.mask.lanes[lane] = 0;
+      L.mask.lanes[lane + kWave] = 0;
+      L.mask.vals[lane] = 0.0;
+      return distinct;
     }
     wave_lds_sync();
     return distinct;
