@@ -174,19 +174,14 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
         if (g < x.eoff + x.nnz_a) {
           x_len = (uint32_t)(poff[g + 1] - poff[g]);
           x_bs = bstart[g];
-          const uint64_t liv = x.a_livs[g - x.eoff];
-          if (NUMERIC) {
-            x_jn = liv;
-            x_av = x.a_vals[g - x.eoff];
-          } else {
-            uint64_t j;
-            fd_divmod(x.kdiv, liv, j);
-            x_jn = j * x.np;
-          }
+          uint64_t j;
+          fd_divmod(x.kdiv, x.a_livs[g - x.eoff], j);
+          x_jn = j * x.np;
+          if (NUMERIC) x_av = x.a_vals[g - x.eoff];
         }
       }
       RowProduct<NUMERIC> pr;
-      window_products<NUMERIC>(x.b_livs, x.b_vals, x.np, x.kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr);
+      window_products<NUMERIC>(x.b_livs, x.b_vals, e0, t, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr);
       RowOut o;
       const uint32_t d =
           row_reduce<ACC, NUMERIC>(pr.valid, pr.ent, pr.col(), pr.val(), t, x.np < (1ull << 32), lane, s_lds[w], o);

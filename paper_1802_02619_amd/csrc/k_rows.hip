@@ -285,9 +285,8 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
     }
     uint32_t my_cnt = 0;
     int64_t w0 = -(int64_t)kWave - 1;  // no window yet
-    // window lane l: entry w0 + l's product count, B' row start, value, and its
-    // LIV (numeric pass) or j * n' (symbolic pass: the LIV of its B' row's first
-    // position, j = its contracted index)
+    // window lane l: entry w0 + l's product count, B' row start, value, and
+    // j * n' (the LIV of its B' row's first position, j = its contracted index)
     uint32_t x_len = 0, x_bs = 0;
     uint64_t x_jn = 0;
     double x_av = 0.0;
@@ -299,25 +298,20 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
     auto stage = [&](int i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
-      const uint64_t row = readlane_u64(m_id, i);
       if ((int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
         w0 = e0;
         const int64_t e = w0 + lane;
         if (e < ra.nnz_a) {
           x_len = (uint32_t)ra.elen[e];
           x_bs = ra.bstart[e];
-          if (NUMERIC) {
-            x_jn = ra.a_livs[e];  // (measured faster to keep the LIV in the numeric pass)
-          } else {
-            uint64_t j;
-            fd_divmod(ra.kdiv, ra.a_livs[e], j);
-            x_jn = j * ra.np;
-          }
+          uint64_t j;
+          fd_divmod(ra.kdiv, ra.a_livs[e], j);
+          x_jn = j * ra.np;
           if (NUMERIC) x_av = ra.a_vals[e];
         }
       }
-      window_products<NUMERIC>(ra.b_livs, ra.b_vals, ra.np, ra.kp, e0, (int)(e1 - e0), row, sh, lane, w0, x_len,
-                               x_bs, x_jn, x_av, next);
+      window_products<NUMERIC>(ra.b_livs, ra.b_vals, e0, (int)(e1 - e0), sh, lane, w0, x_len, x_bs, x_jn, x_av,
+                               next);
     };
     if (todo) stage(__builtin_ctzll(todo));
     while (todo) {

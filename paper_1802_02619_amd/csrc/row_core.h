@@ -68,11 +68,16 @@ __device__ __forceinline__ void wave_bitonic(uint64_t& key, uint32_t& idx, doubl
   }
 }
 
+// Hash slots per wave, two per lane (at most 64 columns per row: at most half
+// full).
+constexpr int kHashBits = 7;
+constexpr int kHashSlots = 1 << kHashBits;
+static_assert(kHashSlots == 2 * kWave, "two hash slots per lane");
 __device__ __forceinline__ uint32_t hash_slot(uint64_t c) {
-  return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits
+  return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> (64 - kHashBits));
 }
 __device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
-  return (c * 0x9E3779B1u) >> 25;  // 7 bits
+  return (c * 0x9E3779B1u) >> (32 - kHashBits);
 }
 
 // Per-row shape codes of the one-wave kernel.
@@ -98,16 +103,16 @@ __device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
 // hash32, in the same space.
 constexpr int kTabEntries = 7;
 struct alignas(16) RowLds {
-  uint64_t hash[2 * kWave];  // hash slots: column (with the owner lane above 32-bit columns in table rows)
+  uint64_t hash[kHashSlots];  // hash slots: column (with the owner lane above 32-bit columns in table rows)
   uint32_t own[kWave];       // owners' columns in lane order (rank by broadcast compares)
   union {
     double tab[kTabEntries][kWave + 1];  // per A' entry, per owner number: the product's value (rows padded by one
                                          // value, so that one owner's cells fall in different banks)
     struct {
-      uint64_t lanes[2 * kWave];  // per hash slot: the lanes whose product has that column
+      uint64_t lanes[kHashSlots];  // per hash slot: the lanes whose product has that column
       double vals[kWave + 8];     // each lane's product value, and a zero at index kWave
     } mask;
-    uint32_t hash32[2 * kWave];
+    uint32_t hash32[kHashSlots];
   };
 };
 static_assert(sizeof(RowLds) % 16 == 0 && offsetof(RowLds, own) % 16 == 0, "RowLds alignment");
@@ -126,16 +131,16 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
 }
 
 // Locates the products of one small row in the entry window (lane l holds
-// entry w0 + l: its product count, B' row start, value, and its A' LIV (numeric
-// pass) or j * n' (symbolic pass: the LIV of its B' row's first position)).
+// entry w0 + l: its product count, B' row start, value, and j * n', the LIV of
+// its B' row's first position, j = its contracted index).
 // Each lane ends up with at most one product: its A' entry `ent` within the
-// row, its B' position `q`, the amount `off` its B' LIV exceeds its column by,
-// and (numeric) the A' value `av` that scales it.  The caller loads B' at q.
+// row, its B' position `q`, the amount `off` (= j * n') its B' LIV exceeds its
+// column by, and (numeric) the A' value `av` that scales it.  The caller loads
+// B' at q.
 template <bool NUMERIC>
-__device__ __forceinline__ void window_locate(uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row, uint8_t sh,
-                                              int lane, int64_t w0, uint32_t x_len, uint32_t x_bs, uint64_t x_jn,
-                                              double x_av, bool& valid, int& ent, uint32_t& q, uint64_t& off,
-                                              double& av) {
+__device__ __forceinline__ void window_locate(uint32_t e0, int t, uint8_t sh, int lane, int64_t w0, uint32_t x_len,
+                                              uint32_t x_bs, uint64_t x_jn, double x_av, bool& valid, int& ent,
+                                              uint32_t& q, uint64_t& off, double& av) {
   valid = false;
   ent = 0;
   q = 0;
@@ -154,7 +159,7 @@ __device__ __forceinline__ void window_locate(uint64_t np, uint64_t kp, uint32_t
       valid = true;
       ent = e;
       q = bs + (uint32_t)k;
-      off = NUMERIC ? np * (jn - kp * row) : jn;
+      off = jn;
     }
     return;
   }
@@ -188,7 +193,7 @@ __device__ __forceinline__ void window_locate(uint64_t np, uint64_t kp, uint32_t
     valid = true;
     ent = lo;
     q = bs_e + (p - excl_e);
-    off = NUMERIC ? np * (jn_e - kp * row) : jn_e;
+    off = jn_e;
   }
 }
 
@@ -217,12 +222,10 @@ struct RowProduct {
 // Locates a small row's products in the window and issues their B' loads.
 template <bool NUMERIC>
 __device__ __forceinline__ void window_products(const uint64_t* __restrict__ b_livs, const double* __restrict__ b_vals,
-                                                uint64_t np, uint64_t kp, uint32_t e0, int t, uint64_t row,
-                                                uint8_t sh, int lane, int64_t w0, uint32_t x_len, uint32_t x_bs,
-                                                uint64_t x_jn, double x_av, RowProduct<NUMERIC>& pr) {
+                                                uint32_t e0, int t, uint8_t sh, int lane, int64_t w0, uint32_t x_len,
+                                                uint32_t x_bs, uint64_t x_jn, double x_av, RowProduct<NUMERIC>& pr) {
   uint32_t q;
-  window_locate<NUMERIC>(np, kp, e0, t, row, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr.valid, pr.ent, q, pr.off,
-                         pr.av);
+  window_locate<NUMERIC>(e0, t, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr.valid, pr.ent, q, pr.off, pr.av);
   pr.load(b_livs, b_vals, q);
 }
 
@@ -270,20 +273,20 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     if (valid) {
       if (key32) {
         const uint32_t c32 = (uint32_t)col;
-        for (int probe = 0; probe < 2 * kWave; ++probe) {
+        for (int probe = 0; probe < kHashSlots; ++probe) {
           const uint32_t p = atomicCAS(&L.hash32[slot], 0xFFFFFFFFu, c32);
           isnew = p == 0xFFFFFFFFu;
           if (isnew || p == c32) break;
-          slot = (slot + 1) & (2 * kWave - 1);
+          slot = (slot + 1) & (kHashSlots - 1);
         }
       } else {
         const uint64_t key = table ? (((uint64_t)lane << 32) | (uint32_t)col) : col;
         const uint64_t cmp = table ? 0xFFFFFFFFull : ~0ull;  // the bits that hold the column
-        for (int probe = 0; probe < 2 * kWave; ++probe) {
+        for (int probe = 0; probe < kHashSlots; ++probe) {
           prev = atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
           isnew = prev == kEmpty;
           if (isnew || ((prev ^ col) & cmp) == 0) break;
-          slot = (slot + 1) & (2 * kWave - 1);
+          slot = (slot + 1) & (kHashSlots - 1);
         }
       }
     }
