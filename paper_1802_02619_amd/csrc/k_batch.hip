@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
     const uint64_t* __restrict__ poff, const uint32_t* __restrict__ bstart, uint32_t nrows, int chunk_rows,
     uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff, uint64_t* __restrict__ out_livs,
     double* __restrict__ out_vals) {
-  __shared__ RowLds s_lds[kRowWaves];
+  __shared__ RowLds<NUMERIC> s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const uint64_t nchunks = ((uint64_t)nrows + chunk_rows - 1) / chunk_rows;
   const RowSpan span = xcd_row_span(nchunks, w);

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
                                                                 const uint64_t* __restrict__ coff,
                                                                 uint64_t* __restrict__ out_livs,
                                                                 double* __restrict__ out_vals) {
-  __shared__ RowLds s_lds[kRowWaves];
+  __shared__ RowLds<NUMERIC> s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const bool narrow = ra.np < (1ull << 32);
   const uint64_t nchunks = ((uint64_t)nzr + chunk_rows - 1) / chunk_rows;

@@ -95,30 +95,44 @@ __device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
   return f <= (uint64_t)kWave && t <= (uint32_t)kWave;
 }
 
-// LDS of one wave of the one-wave-per-row kernels.  A numeric row with at most
-// kTabEntries entries and 32-bit columns sums through the table
-// tab[entry][owner lane], which is all +0.0 between rows; other numeric
-// accumulator rows use the lane masks and staged values that share its space
-// and clear them again when done.  The symbolic pass keys 32-bit columns in
-// hash32, in the same space.
+// LDS of one wave of the one-wave-per-row kernels.  The hash table has
+// kHashSlots slots; in the symbolic pass, one spare slot per lane follows
+// them, which a lane that has finished probing keeps probing while other lanes
+// still search.
+// Numeric: a row with at most kTabEntries entries and 32-bit columns sums
+// through the table tab[entry][owner number], which is all +0.0 between rows;
+// other accumulator rows use the lane masks and staged values that share its
+// space and clear them again when done.
 constexpr int kTabEntries = 7;
-struct alignas(16) RowLds {
-  uint64_t hash[kHashSlots];  // hash slots: column (with the owner lane above 32-bit columns in table rows)
-  uint32_t own[kWave];       // owners' columns in lane order (rank by broadcast compares)
+template <bool NUMERIC>
+struct RowLds;
+template <>
+struct alignas(16) RowLds<false> {
+  union {
+    uint64_t hash[kHashSlots + kWave];    // columns
+    uint32_t hash32[kHashSlots + kWave];  // 32-bit columns
+  };
+};
+template <>
+struct alignas(16) RowLds<true> {
+  union {
+    uint64_t hash[kHashSlots];    // column (with the owner lane above 32-bit columns in table rows)
+    uint32_t hash32[kHashSlots];  // (32-bit keys: the symbolic pass only)
+  };
+  uint32_t own[kWave];  // owners' columns (rank by broadcast compares)
   union {
     double tab[kTabEntries][kWave + 1];  // per A' entry, per owner number: the product's value (rows padded by one
                                          // value, so that one owner's cells fall in different banks)
     struct {
       uint64_t lanes[kHashSlots];  // per hash slot: the lanes whose product has that column
-      double vals[kWave + 8];     // each lane's product value, and a zero at index kWave
+      double vals[kWave + 8];      // each lane's product value, and a zero at index kWave
     } mask;
-    uint32_t hash32[kHashSlots];
   };
 };
-static_assert(sizeof(RowLds) % 16 == 0 && offsetof(RowLds, own) % 16 == 0, "RowLds alignment");
+static_assert(offsetof(RowLds<true>, own) % 16 == 0, "RowLds alignment");
 
 // Clears a wave's table (once, before its first row).
-__device__ __forceinline__ void tab_clear(RowLds& L, int lane) {
+__device__ __forceinline__ void tab_clear(RowLds<true>& L, int lane) {
 #pragma unroll
   for (int e = 0; e < kTabEntries; ++e) {
     L.tab[e][lane] = 0.0;
@@ -244,7 +258,7 @@ struct RowOut {
 // entry `ent` in the row, column `col`, value `v`) into the row's output.
 template <bool ACC, bool NUMERIC>
 __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col, double v, int t, bool narrow,
-                                               int lane, RowLds& L, RowOut& o) {
+                                               int lane, RowLds<NUMERIC>& L, RowOut& o) {
   if (ACC) {
     // Sparse accumulator: an LDS hash table maps a column to a slot, and the
     // lane that inserts a column owns it.  Numeric rows of at most kTabEntries
@@ -252,53 +266,85 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     // the column, so that every product learns its owner.
     const bool table = NUMERIC && narrow && t <= kTabEntries;
     const bool key32 = !NUMERIC && narrow;
-    if (key32) {
-      L.hash32[lane] = 0xFFFFFFFFu;
-      L.hash32[lane + kWave] = 0xFFFFFFFFu;
+    if constexpr (!NUMERIC) {
+      if (key32) {
+        L.hash32[lane] = 0xFFFFFFFFu;
+        L.hash32[lane + kWave] = 0xFFFFFFFFu;
+      } else {
+        L.hash[lane] = kEmpty;
+        L.hash[lane + kWave] = kEmpty;
+      }
     } else {
       L.hash[lane] = kEmpty;
       L.hash[lane + kWave] = kEmpty;
-    }
-    if (NUMERIC && !table) {
-      L.mask.lanes[lane] = 0;
-      L.mask.lanes[lane + kWave] = 0;
-      if (lane == 0) L.mask.vals[kWave] = 0.0;
+      if (!table) {
+        L.mask.lanes[lane] = 0;
+        L.mask.lanes[lane + kWave] = 0;
+        if (lane == 0) L.mask.vals[kWave] = 0.0;
+      }
     }
     wave_lds_sync();
+    // Probe until the slot is empty (this lane inserts the column) or holds the
+    // column; at most 64 columns in 128 slots, so a free slot always exists.
+    // A lane that is done moves to its spare slot, and the wave leaves the
+    // loop together once no lane is still probing.
     uint32_t slot = valid ? (narrow ? hash_slot32((uint32_t)col) : hash_slot(col)) : 0;
-    // probe until the slot is empty (this lane inserts the column) or holds the
-    // column (at most 64 columns in 128 slots: a free slot always exists)
+    uint32_t owner = 0;  // the lane that inserted the column (table rows)
     bool isnew = false;
-    uint64_t prev = kEmpty;
-    if (valid) {
-      if (key32) {
-        const uint32_t c32 = (uint32_t)col;
-        for (int probe = 0; probe < kHashSlots; ++probe) {
-          const uint32_t p = atomicCAS(&L.hash32[slot], 0xFFFFFFFFu, c32);
-          isnew = p == 0xFFFFFFFFu;
-          if (isnew || p == c32) break;
-          slot = (slot + 1) & (kHashSlots - 1);
-        }
-      } else {
+    if constexpr (NUMERIC) {
+      // Probe until the slot is empty (this lane inserts the column) or holds
+      // the column; at most 64 columns in 128 slots, so a free slot always
+      // exists.  Only lanes still probing take part in a probe.
+      if (valid) {
         const uint64_t key = table ? (((uint64_t)lane << 32) | (uint32_t)col) : col;
         const uint64_t cmp = table ? 0xFFFFFFFFull : ~0ull;  // the bits that hold the column
         for (int probe = 0; probe < kHashSlots; ++probe) {
-          prev = atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
-          isnew = prev == kEmpty;
-          if (isnew || ((prev ^ col) & cmp) == 0) break;
+          const uint64_t p =
+              atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
+          isnew = p == kEmpty;
+          owner = isnew ? (uint32_t)lane : (uint32_t)(p >> 32);
+          if (isnew || ((p ^ col) & cmp) == 0) break;
           slot = (slot + 1) & (kHashSlots - 1);
+        }
+      }
+    } else {
+      // The same probing, but a lane that is done moves to its spare slot, and
+      // the wave leaves the loop together once no lane is still probing (fewer
+      // scalar instructions than a divergent loop).
+      const uint32_t spare = kHashSlots + lane;
+      uint32_t at = valid ? slot : spare;
+      if (key32) {
+        const uint32_t c32 = (uint32_t)col;
+        for (int probe = 0; probe <= kHashSlots; ++probe) {
+          const uint32_t p = atomicCAS(&L.hash32[at], 0xFFFFFFFFu, c32);
+          const bool live = at < kHashSlots;
+          const bool fresh = live && p == 0xFFFFFFFFu;
+          const bool hit = fresh || (live && p == c32);
+          isnew = isnew || fresh;
+          at = hit ? spare : live ? ((at + 1) & (kHashSlots - 1)) : at;
+          if (!__any(at < kHashSlots)) break;
+        }
+      } else {
+        for (int probe = 0; probe <= kHashSlots; ++probe) {
+          const uint64_t p =
+              atomicCAS((unsigned long long*)&L.hash[at], (unsigned long long)kEmpty, (unsigned long long)col);
+          const bool live = at < kHashSlots;
+          const bool fresh = live && p == kEmpty;
+          const bool hit = fresh || (live && p == col);
+          isnew = isnew || fresh;
+          at = hit ? spare : live ? ((at + 1) & (kHashSlots - 1)) : at;
+          if (!__any(at < kHashSlots)) break;
         }
       }
     }
     const uint64_t newmask = __ballot(isnew);
     const uint32_t distinct = (uint32_t)__popcll(newmask);
-    if (NUMERIC) {
+    if constexpr (NUMERIC) {
       if (table) {
         // Owners are numbered d = 0, 1, ... in lane order, and output d is
         // computed by lane d (and, when there are at most 32, also by lane
         // d + 32, which shares the rank comparisons).  Each product stores its
         // value at (its entry, its owner's d); owner d stores its column at d.
-        const int owner = !valid ? 0 : isnew ? lane : (int)(prev >> 32);
         const uint32_t d = (uint32_t)__popcll(newmask & ((1ull << owner) - 1ull));
         if (valid) L.tab[ent][d] = v;
         if (isnew) L.own[d] = (uint32_t)col;
