@@ -44,7 +44,11 @@ def algorithmic_bytes(kernel: str, sz: dict):
         "row_small_num": 16 * (na + nb + nc) + 4 * (k + 1) + 24 * rows,
         # symbolic row pass: LIVs of A' and B', row pointers, per-row metadata and counts
         "row_small_sym": 8 * (na + nb) + 4 * (k + 1) + 24 * rows,
+        # per A' entry: read its LIV, write its product count and B' row start (32-bit each),
+        # read the row pointers of B'
         "entry_len": 16 * na + 4 * (k + 1),
+        # the same, plus the row starts (4 B) and ids (8 B) of all m' = rows rows of A'
+        "dense_rows_len": 16 * na + 4 * (k + 1) + 12 * rows,
         "dense_ptr": 8 * nb + 4 * (k + 1),
         "seg_heads": 12 * na,
     }

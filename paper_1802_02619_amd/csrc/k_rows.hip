@@ -91,26 +91,9 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
   }
 }
 
-// Rows of A' taken densely, every row 0..m'-1 including empty ones (for
-// products where A' has few empty rows): row_start[r] = first entry of row r,
-// row_id[r] = r, *count = m'.  Empty rows hold no products and are skipped.
-__global__ void dense_rows_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv kdiv, uint64_t mp,
-                                  uint32_t* __restrict__ row_start, uint64_t* __restrict__ row_id,
-                                  uint64_t* __restrict__ count) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t lo = e == 0 ? 0 : fd_div(kdiv, livs[e - 1]) + 1;
-    const uint64_t hi = e == n ? mp : fd_div(kdiv, livs[e]);
-    for (uint64_t r = lo; r <= hi; ++r) {
-      row_start[r] = (uint32_t)e;
-      if (r < mp) row_id[r] = r;
-    }
-    if (e == n) *count = mp;
-  }
-}
-
 // For each A' entry: the start and length of the B' row its column selects.
 template <bool DENSE>
-__global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_t* __restrict__ bstart) {
+__global__ void entry_len_kernel(RowArgs ra, uint32_t* __restrict__ len, uint32_t* __restrict__ bstart) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ra.nnz_a;
        e += (int64_t)gridDim.x * blockDim.x) {
     uint64_t j;
@@ -119,6 +102,34 @@ __global__ void entry_len_kernel(RowArgs ra, uint64_t* __restrict__ len, uint32_
     b_row<DENSE>(ra, j, s, l);
     len[e] = l;
     bstart[e] = s;
+  }
+}
+
+// The same, together with the rows of A' taken densely, every row 0..m'-1
+// including empty ones (for products where A' has few empty rows):
+// row_start[r] = first entry of row r, row_id[r] = r, *count = m'.  Empty
+// rows hold no products and are skipped.
+template <bool DENSE>
+__global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restrict__ row_start,
+                                      uint64_t* __restrict__ row_id, uint64_t* __restrict__ count,
+                                      uint32_t* __restrict__ len, uint32_t* __restrict__ bstart) {
+  const int64_t n = ra.nnz_a;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t hi = mp;
+    if (e < n) {
+      uint64_t j;
+      hi = fd_divmod(ra.kdiv, ra.a_livs[e], j);
+      uint32_t st, l;
+      b_row<DENSE>(ra, j, st, l);
+      len[e] = l;
+      bstart[e] = st;
+    }
+    const uint64_t lo = e == 0 ? 0 : fd_div(ra.kdiv, ra.a_livs[e - 1]) + 1;
+    for (uint64_t r = lo; r <= hi; ++r) {
+      row_start[r] = (uint32_t)e;
+      if (r < mp) row_id[r] = r;
+    }
+    if (e == n) *count = mp;
   }
 }
 
@@ -185,7 +196,7 @@ constexpr uint64_t kSetupMaxRowPtr = 65536;
 
 __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
     RowArgs ra, FastDiv ndiv, bool classes, uint32_t* __restrict__ row_start, uint64_t* __restrict__ row_id,
-    uint64_t* __restrict__ words, uint32_t* __restrict__ bptr, uint64_t* __restrict__ elen,
+    uint64_t* __restrict__ words, uint32_t* __restrict__ bptr, uint32_t* __restrict__ elen,
     uint32_t* __restrict__ bstart, uint32_t* __restrict__ list2, uint64_t* __restrict__ f2,
     uint8_t* __restrict__ shape) {
   __shared__ uint32_t wsum[kSetupThreads / kWave + 1];
@@ -302,7 +313,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
         w0 = e0;
         const int64_t e = w0 + lane;
         if (e < ra.nnz_a) {
-          x_len = (uint32_t)ra.elen[e];
+          x_len = ra.elen[e];
           x_bs = ra.bstart[e];
           uint64_t j;
           fd_divmod(ra.kdiv, ra.a_livs[e], j);
@@ -368,7 +379,7 @@ __device__ __forceinline__ uint32_t tiny_merge(const RowArgs& ra, uint32_t r, ui
     if (e < t) {
       const uint32_t ge = e0 + e;
       p[e] = ra.bstart[ge];
-      end[e] = p[e] + (uint32_t)ra.elen[ge];
+      end[e] = p[e] + ra.elen[ge];
       jn[e] = (ra.a_livs[ge] - ra.kp * row) * ra.np;
       if (NUMERIC) av[e] = ra.a_vals[ge];
       if (p[e] < end[e]) col[e] = ra.b_livs[p[e]] - jn[e];
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(256) void row_copy_kernel(RowArgs ra, uint32_t nzr,
     if (shape[r] != kShapeCopy) continue;
     const uint32_t e0 = ra.row_start[r];
     const uint64_t row = ra.row_id[r];
-    const uint32_t len = (uint32_t)ra.elen[e0], bs = ra.bstart[e0];
+    const uint32_t len = ra.elen[e0], bs = ra.bstart[e0];
     const uint64_t jn = (ra.a_livs[e0] - ra.kp * row) * ra.np;
     const double a = ra.a_vals[e0];
     const uint64_t base = coff[r];
@@ -596,7 +607,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   // rows of A' taken densely (all m' of them) when few are empty
   const bool dense_rows = !small && mp <= 2 * (uint64_t)na && mp < UINT32_MAX;
   const uint64_t rows_cap = dense_rows ? std::max<uint64_t>(mp, (uint64_t)na) : (uint64_t)na;
-  uint64_t* len = s.get<uint64_t>(na);
+  uint32_t* len = s.get<uint32_t>(na);
   uint64_t* poff = s.get<uint64_t>(na + 1);
   uint32_t* bstart = s.get<uint32_t>(na);
   uint32_t* list2 = s.get<uint32_t>(rows_cap);
@@ -620,25 +631,6 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     const uint64_t* rb1[5] = {words, words + 1, words + 2, words + 3, words + 4};
     h = readback(ctx, rb1, 5);
   } else {
-    // rows of A': all m' of them when few are empty (one launch), else the non-empty ones
-    const uint64_t* nzr_word;
-    if (dense_rows) {
-      uint32_t* row_start = s.get<uint32_t>(mp + 1);
-      uint64_t* row_id = s.get<uint64_t>(mp);
-      uint64_t* count = s.get<uint64_t>(1);
-      LCO_LAUNCH(ctx, "dense_rows", dense_rows_kernel, grid_for(ctx, na + 1, 256), 256, 0, A->livs, na, ra.kdiv, mp,
-                 row_start, row_id, count);
-      ra.row_start = row_start;
-      ra.row_id = row_id;
-      ra.nzr_a = count;
-      nzr_word = count;
-    } else {
-      Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
-      ra.row_start = arows.starts;
-      ra.row_id = arows.ids;
-      ra.nzr_a = arows.count;
-      nzr_word = arows.count;
-    }
     // compressed B'
     if (dense) {
       if (kp >= (uint64_t)1 << 34) fail(LCO_E_OOM, "contract: singly-compressed row pointer of more than 2^34 entries");
@@ -652,9 +644,32 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       ra.brow_start = brows.starts;
       ra.nzr_b = brows.count;
     }
-    // product count and B' row start of each A' entry
-    if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
-    else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+    // rows of A' (all m' of them when few are empty, else the non-empty ones),
+    // and the product count and B' row start of each A' entry
+    const uint64_t* nzr_word;
+    if (dense_rows) {
+      uint32_t* row_start = s.get<uint32_t>(mp + 1);
+      uint64_t* row_id = s.get<uint64_t>(mp);
+      uint64_t* count = s.get<uint64_t>(1);
+      if (dense)
+        LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<true>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
+                   row_start, row_id, count, len, bstart);
+      else
+        LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<false>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
+                   row_start, row_id, count, len, bstart);
+      ra.row_start = row_start;
+      ra.row_id = row_id;
+      ra.nzr_a = count;
+      nzr_word = count;
+    } else {
+      Segments arows = segment_livs(ctx, s, A->livs, na, ra.kdiv);
+      ra.row_start = arows.starts;
+      ra.row_id = arows.ids;
+      ra.nzr_a = arows.count;
+      nzr_word = arows.count;
+      if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+      else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+    }
     // row shapes; long rows collected with their product counts
     // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
     uint64_t* n2_dev = s.get<uint64_t>(4);
@@ -674,7 +689,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint64_t* off2 = nullptr;
   if (n2) {
     // the long-row path locates products through the entries' product offsets
-    scan_u64(ctx, len, poff, na, poff + na);
+    scan_u32_u64(ctx, len, poff, na, poff + na);
     ra.poff = poff;
     off2 = s.get<uint64_t>(n2 + 1);
     scan_u64(ctx, f2, off2, (int64_t)n2, off2 + n2);

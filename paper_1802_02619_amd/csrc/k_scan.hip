@@ -10,8 +10,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __restrict__ in, int64_t n,
+template <class Tin, class T>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const Tin* __restrict__ in, int64_t n,
                                                                    T* __restrict__ partials) {
   __shared__ T wsum[kScanThreads / kWave + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __re
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const int64_t i = base + it * kScanThreads + threadIdx.x;
-    if (i < n) s += in[i];
+    if (i < n) s += (T)in[i];
   }
   T total;
   block_exclusive_scan<T>(s, wsum, total);
@@ -27,8 +27,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* __re
 }
 
 // Scans one tile per block; `offsets` (optional) gives each tile's starting value.
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const T* __restrict__ in, T* __restrict__ out,
+template <class Tin, class T>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const Tin* __restrict__ in, T* __restrict__ out,
                                                                  int64_t n, const T* __restrict__ offsets,
                                                                  T* __restrict__ total_out) {
   __shared__ T tile[kScanTile];
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const T* __rest
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const int64_t i = base + it * kScanThreads + threadIdx.x;
-    tile[it * kScanThreads + threadIdx.x] = i < n ? in[i] : T(0);
+    tile[it * kScanThreads + threadIdx.x] = i < n ? (T)in[i] : T(0);
   }
   __syncthreads();
   T v[kScanItems];
@@ -65,33 +65,37 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const T* __rest
   if (total_out && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total_out = off + total;
 }
 
-template <class T>
-void scan_impl(lco_ctx ctx, const T* in, T* out, int64_t n, T* total, const char* name) {
+template <class Tin, class T>
+void scan_impl(lco_ctx ctx, const Tin* in, T* out, int64_t n, T* total, const char* name) {
   if (n <= 0) {
     if (total) memset_async(ctx, total, 0, sizeof(T));
     return;
   }
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   if (tiles == 1) {
-    LCO_LAUNCH(ctx, name, (scan_tile_kernel<T>), 1, kScanThreads, 0, in, out, n, (const T*)nullptr, total);
+    LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), 1, kScanThreads, 0, in, out, n, (const T*)nullptr, total);
     return;
   }
   Scratch s(ctx);
   T* partials = s.get<T>(tiles);
   T* poff = s.get<T>(tiles);
-  LCO_LAUNCH(ctx, "scan_reduce", (scan_reduce_kernel<T>), tiles, kScanThreads, 0, in, n, partials);
-  scan_impl<T>(ctx, partials, poff, tiles, (T*)nullptr, name);
-  LCO_LAUNCH(ctx, name, (scan_tile_kernel<T>), tiles, kScanThreads, 0, in, out, n, (const T*)poff, total);
+  LCO_LAUNCH(ctx, "scan_reduce", (scan_reduce_kernel<Tin, T>), tiles, kScanThreads, 0, in, n, partials);
+  scan_impl<T, T>(ctx, partials, poff, tiles, (T*)nullptr, name);
+  LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), tiles, kScanThreads, 0, in, out, n, (const T*)poff, total);
 }
 
 }  // namespace
 
 void scan_u32(lco_ctx ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total) {
-  scan_impl<uint32_t>(ctx, in, out, n, total, "scan_u32");
+  scan_impl<uint32_t, uint32_t>(ctx, in, out, n, total, "scan_u32");
 }
 
 void scan_u64(lco_ctx ctx, const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total) {
-  scan_impl<uint64_t>(ctx, in, out, n, total, "scan_u64");
+  scan_impl<uint64_t, uint64_t>(ctx, in, out, n, total, "scan_u64");
+}
+
+void scan_u32_u64(lco_ctx ctx, const uint32_t* in, uint64_t* out, int64_t n, uint64_t* total) {
+  scan_impl<uint32_t, uint64_t>(ctx, in, out, n, total, "scan_u64");
 }
 
 }  // namespace lco

@@ -229,6 +229,8 @@ struct KeyParams {
 // exclusive scans; `total` (device, may be null) receives the sum
 void scan_u32(lco_ctx ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total);
 void scan_u64(lco_ctx ctx, const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total);
+// 64-bit prefix sums of 32-bit values.
+void scan_u32_u64(lco_ctx ctx, const uint32_t* in, uint64_t* out, int64_t n, uint64_t* total);
 
 // Stable LSD radix sort of (livs, vals) pairs by bits [0, bits) of the element key.
 // If `shuffle` is non-null, the input LIVs are first recomputed (pass 1 reads old

@@ -33,7 +33,7 @@ struct RowArgs {
   const uint32_t* row_start = nullptr;   // non-empty rows of A': starts (plus terminal)
   const uint64_t* row_id = nullptr;      //   and ids
   const uint64_t* nzr_a = nullptr;       //   device count
-  const uint64_t* elen = nullptr;        // products per A' entry (nnz_a)
+  const uint32_t* elen = nullptr;        // products per A' entry (nnz_a; a B' row length, below 2^32)
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
   const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
 };
