@@ -2,6 +2,8 @@
 // runtime plumbing (errors, allocator bridge, scratch arena, per-kernel timing).
 #include <cmath>
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -182,19 +184,46 @@ static void check_device_error(lco_ctx ctx, uint32_t word) {
   }
 }
 
+namespace {
+constexpr int kErrWord = 61;   // pinned word receiving the device error word
+constexpr int kFlagWord = 62;  // pinned word receiving the readback sequence number
+
+struct ReadbackArgs {
+  const uint64_t* words[kReadbackWords];
+  int count;
+};
+
+// Gathers the words and the device error word into the pinned buffer, then
+// publishes `seq` in its flag word with a system-scope release, so that the
+// host can wait for the flag rather than for the whole stream.
+__global__ void readback_kernel(ReadbackArgs a, const uint32_t* __restrict__ err, uint64_t* out, uint64_t seq) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < a.count; ++i) out[i] = *a.words[i];
+  out[kErrWord] = *err;
+  __hip_atomic_store(&out[kFlagWord], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+}  // namespace
+
 const uint64_t* readback(lco_ctx ctx, const uint64_t* const* dev_words, int count) {
-  // one copy per run of consecutive device words
-  for (int i = 0; i < count;) {
-    int j = i + 1;
-    while (j < count && dev_words[j] == dev_words[j - 1] + 1) ++j;
-    LCO_HIP(hipMemcpyAsync(ctx->pinned + i, dev_words[i], sizeof(uint64_t) * (j - i), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    i = j;
+  if (count < 0 || count > kReadbackWords) fail(LCO_E_ARG, "readback: too many words");
+  ReadbackArgs a{};
+  for (int i = 0; i < count; ++i) a.words[i] = dev_words[i];
+  a.count = count;
+  const uint64_t seq = ++ctx->readback_seq;
+  LCO_LAUNCH(ctx, "readback", readback_kernel, 1, 64, 0, a, (const uint32_t*)ctx->dev_err, ctx->pinned_dev, seq);
+  // Spin on the flag (it lands a few microseconds after the kernel runs); after
+  // 20 ms, wait for the stream instead, which also reports a failed kernel.
+  volatile uint64_t* flag = ctx->pinned + kFlagWord;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t it = 1; *flag != seq; ++it) {
+    if ((it & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+      LCO_HIP(hipStreamSynchronize(ctx->stream));
+      if (*flag != seq) fail(LCO_E_HIP, "readback: the device did not publish the requested words");
+      break;
+    }
   }
-  LCO_HIP(hipMemcpyAsync((uint32_t*)(ctx->pinned + 63), ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  LCO_HIP(hipStreamSynchronize(ctx->stream));
-  check_device_error(ctx, *(uint32_t*)(ctx->pinned + 63));
+  std::atomic_thread_fence(std::memory_order_acquire);
+  check_device_error(ctx, (uint32_t)ctx->pinned[kErrWord]);
   return ctx->pinned;
 }
 
@@ -333,11 +362,14 @@ lco_status lco_ctx_create(int device, void* hip_stream, lco_alloc_fn alloc, lco_
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
-  hipError_t e = hipHostMalloc((void**)&c->pinned, 64 * sizeof(uint64_t), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&c->pinned, 64 * sizeof(uint64_t), hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0);
   if (e != hipSuccess) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     hip_check(e, "hipHostMalloc");
   }
+  std::memset(c->pinned, 0, 64 * sizeof(uint64_t));
   try {
     c->dev_err = (uint32_t*)dev_alloc(c, 256);
     LCO_HIP(hipMemsetAsync(c->dev_err, 0, 256, c->stream));

@@ -62,7 +62,9 @@ struct lco_ctx_s {
   size_t max_lds = 65536;
   lco::Arena arena;
   int scratch_depth = 0;
-  uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words)
+  uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words, device-coherent)
+  uint64_t* pinned_dev = nullptr;  // the same buffer as the device addresses it
+  uint64_t readback_seq = 0;       // last sequence number published in the buffer's flag word
   lco::Timer timer;
   uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
   int64_t batch_stats[2] = {0, 0};  // last batch on this context: instances batched, run per call
@@ -125,7 +127,9 @@ class Scratch {
 // small host<->device helpers on the context stream
 void memset_async(lco_ctx ctx, void* p, int v, size_t bytes);
 void copy_d2d(lco_ctx ctx, void* dst, const void* src, size_t bytes);
-// copies `count` 64-bit words from device to the pinned buffer and synchronises
+// Copies `count` (at most kReadbackWords) 64-bit device words to the pinned
+// buffer once every operation queued before has finished; returns the buffer.
+constexpr int kReadbackWords = 8;
 const uint64_t* readback(lco_ctx ctx, const uint64_t* const* dev_words, int count);
 void sync(lco_ctx ctx);
 
