@@ -108,12 +108,15 @@ __global__ void entry_len_kernel(RowArgs ra, uint32_t* __restrict__ len, uint32_
 // The same, together with the rows of A' taken densely, every row 0..m'-1
 // including empty ones (for products where A' has few empty rows):
 // row_start[r] = first entry of row r, row_id[r] = r, *count = m'.  Empty
-// rows hold no products and are skipped.
+// rows hold no products and are skipped.  Also clears the four counter words
+// `zero4` of the classification that follows.
 template <bool DENSE>
 __global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restrict__ row_start,
                                       uint64_t* __restrict__ row_id, uint64_t* __restrict__ count,
-                                      uint32_t* __restrict__ len, uint32_t* __restrict__ bstart) {
+                                      uint32_t* __restrict__ len, uint32_t* __restrict__ bstart,
+                                      uint64_t* __restrict__ zero4) {
   const int64_t n = ra.nnz_a;
+  if (blockIdx.x == 0 && threadIdx.x < 4) zero4[threadIdx.x] = 0;  // the classification's counters
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
     uint64_t hi = mp;
     if (e < n) {
@@ -644,6 +647,9 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       ra.brow_start = brows.starts;
       ra.nzr_b = brows.count;
     }
+    // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
+    uint64_t* n2_dev = s.get<uint64_t>(4);
+    uint64_t* flags_dev = n2_dev + 1;
     // rows of A' (all m' of them when few are empty, else the non-empty ones),
     // and the product count and B' row start of each A' entry
     const uint64_t* nzr_word;
@@ -653,10 +659,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       uint64_t* count = s.get<uint64_t>(1);
       if (dense)
         LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<true>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
-                   row_start, row_id, count, len, bstart);
+                   row_start, row_id, count, len, bstart, n2_dev);
       else
         LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<false>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
-                   row_start, row_id, count, len, bstart);
+                   row_start, row_id, count, len, bstart, n2_dev);
       ra.row_start = row_start;
       ra.row_id = row_id;
       ra.nzr_a = count;
@@ -669,12 +675,9 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       nzr_word = arows.count;
       if (dense) LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<true>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
       else LCO_LAUNCH(ctx, "entry_len", entry_len_kernel<false>, grid_for(ctx, na, 256), 256, 0, ra, len, bstart);
+      memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
     }
     // row shapes; long rows collected with their product counts
-    // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
-    uint64_t* n2_dev = s.get<uint64_t>(4);
-    uint64_t* flags_dev = n2_dev + 1;
-    memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
     LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, (int64_t)rows_cap, 256), 256, 0, ra,
                (int64_t)rows_cap, classes, n2_dev,
                list2, f2, shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));

@@ -367,15 +367,15 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
         const uint4* ol = reinterpret_cast<const uint4*>(L.own);
         uint32_t rank = 0;
         if (split) {
-          const int base = (lane >> 5) * 4;
-          const uint32_t nq = ((distinct < 16 ? distinct : 16) + 3) >> 2;
+          // all four reads at once; columns past the distinct ones are padding,
+          // which is never smaller
+          uint4 y[4];
 #pragma unroll
-          for (uint32_t q = 0; q < 4; ++q) {
-            if (q < nq) {
-              const uint4 y = ol[base + q];
-              rank += (y.x < c32 ? 1u : 0u) + (y.y < c32 ? 1u : 0u) + (y.z < c32 ? 1u : 0u) + (y.w < c32 ? 1u : 0u);
-            }
-          }
+          for (int q = 0; q < 4; ++q) y[q] = ol[(lane >> 5) * 4 + q];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            rank += (y[q].x < c32 ? 1u : 0u) + (y[q].y < c32 ? 1u : 0u) + (y[q].z < c32 ? 1u : 0u) +
+                    (y[q].w < c32 ? 1u : 0u);
           rank += (uint32_t)__shfl_xor((int)rank, 32, kWave);
         } else {
           const uint32_t nq = (distinct + 3) >> 2;
