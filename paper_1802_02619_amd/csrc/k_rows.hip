@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
 // memory more than it computes, so it is held to 8 waves per SIMD (64 VGPRs).
 constexpr int kChunkRows = kWave;
 
-template <bool ACC, bool NUMERIC>
+template <bool ACC, bool NUMERIC, bool NARROW>
 __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel(RowArgs ra, uint32_t nzr, int chunk_rows,
                                                                 const uint8_t* __restrict__ shape,
                                                                 uint64_t* __restrict__ cnt,
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
                                                                 double* __restrict__ out_vals) {
   __shared__ RowLds<NUMERIC> s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const bool narrow = ra.np < (1ull << 32);
+  constexpr bool narrow = NARROW;  // columns below 2^32 (n' < 2^32)
   const uint64_t nchunks = ((uint64_t)nzr + chunk_rows - 1) / chunk_rows;
   const RowSpan span = xcd_row_span(nchunks, w);
   if constexpr (ACC && NUMERIC) tab_clear(s_lds[w], lane);
@@ -709,12 +709,20 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   const uint64_t nchunks = (nzr + chunk_rows - 1) / chunk_rows;
   const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nchunks + kRowWaves - 1) / kRowWaves,
                                                                        (uint64_t)ctx->num_cus * 16));
-#define LCO_ROW_SMALL(NUM, ...)                                                                                  \
+  const bool narrow = np < (1ull << 32);
+#define LCO_ROW_SMALL_N(NUM, NARROW, ...)                                                                        \
   do {                                                                                                           \
-    if (acc) LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<true, NUM>), small_grid,  \
-                        kRowThreads, 0, __VA_ARGS__);                                                            \
-    else LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM>), small_grid,     \
-                    kRowThreads, 0, __VA_ARGS__);                                                                \
+    if (acc)                                                                                                     \
+      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<true, NUM, NARROW>), small_grid, \
+                 kRowThreads, 0, __VA_ARGS__);                                                                   \
+    else                                                                                                         \
+      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM, NARROW>),           \
+                 small_grid, kRowThreads, 0, __VA_ARGS__);                                                       \
+  } while (0)
+#define LCO_ROW_SMALL(NUM, ...)                      \
+  do {                                               \
+    if (narrow) LCO_ROW_SMALL_N(NUM, true, __VA_ARGS__); \
+    else LCO_ROW_SMALL_N(NUM, false, __VA_ARGS__);   \
   } while (0)
   if (wave)
     LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr,
@@ -775,6 +783,7 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     throw;
   }
 #undef LCO_ROW_SMALL
+#undef LCO_ROW_SMALL_N
   return C;
 }
 

@@ -268,6 +268,29 @@ def test_dense_rows_with_empty_rows(lco_lib, gpu_ctx, oracle_mod):
         t.destroy()
 
 
+@pytest.mark.parametrize("lc", [[0, 1, 3, 4], [3, 4, 0, 1]])
+def test_wide_columns_every_algorithm(lco_lib, gpu_ctx, oracle_mod, lc):
+    """Columns of the product beyond 2^32 (m' = 2^28 rows, n' = 2^34 columns):
+    row-by-row passes key their hash with 64-bit columns and rank outputs by
+    readlane, so no row uses the 32-bit table (column-by-column algorithms see
+    the transposed shape).  Rows of A hold up to about 10 entries, so the
+    lane-mask sums are covered too."""
+    rng = np.random.default_rng(11)
+    da, db = [1 << 14, 1 << 14, 64], [64, 1 << 17, 1 << 17]
+    heads = np.column_stack([rng.integers(0, da[0], 60), rng.integers(0, da[1], 60)]).astype(np.uint64)
+    ca = np.column_stack([heads[rng.integers(0, 60, 500)], rng.integers(0, 64, 500).astype(np.uint64)])
+    ca = np.unique(ca, axis=0)
+    cb = np.column_stack([rng.integers(0, 64, 300), rng.integers(0, db[1], 300), rng.integers(0, db[2], 300)])
+    cb = np.unique(cb.astype(np.uint64), axis=0)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, da, ca, rng.uniform(-1, 1, len(ca)))
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, db, cb, rng.uniform(-1, 1, len(cb)))
+    plan = lco_lib.lco_plan_info(gpu_ctx, ga, [0, 1, 2], gb, [2, 3, 4], lc)
+    assert plan.num_contracted == 1
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1, 2], gb, ob, [2, 3, 4], lc, exact=True)
+    ga.destroy()
+    gb.destroy()
+
+
 @pytest.mark.parametrize("b_len", [1, 2, 4])
 def test_tiny_rows_staged_and_direct(lco_lib, gpu_ctx, oracle_mod, b_len):
     """Rows of at most 4 entries and 16 products only (one lane per row): with
