@@ -9,6 +9,9 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+// Up to this many tiles, each tile sums the partials before it itself (at most
+// 16 loads per thread) instead of a separate scan of the partials.
+constexpr int64_t kSumPartialsMax = 4096;
 
 template <class Tin, class T>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const Tin* __restrict__ in, int64_t n,
@@ -26,14 +29,25 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const Tin* __
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// Scans one tile per block; `offsets` (optional) gives each tile's starting value.
+// Scans one tile per block.  A tile's starting value is offsets[tile] when
+// `offsets` is given, else the sum of partials[0, tile) when `partials` is
+// given (each block adds up the tile sums before it), else 0.
 template <class Tin, class T>
 __global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const Tin* __restrict__ in, T* __restrict__ out,
                                                                  int64_t n, const T* __restrict__ offsets,
+                                                                 const T* __restrict__ partials,
                                                                  T* __restrict__ total_out) {
   __shared__ T tile[kScanTile];
   __shared__ T wsum[kScanThreads / kWave + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T off = 0;
+  if (offsets) {
+    off = offsets[blockIdx.x];
+  } else if (partials) {
+    T p = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) p += partials[b];
+    block_exclusive_scan<T>(p, wsum, off);
+  }
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const int64_t i = base + it * kScanThreads + threadIdx.x;
@@ -49,7 +63,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const Tin* __re
   }
   T total;
   T run = block_exclusive_scan<T>(s, wsum, total);
-  const T off = offsets ? offsets[blockIdx.x] : T(0);
   run += off;
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
@@ -73,15 +86,23 @@ void scan_impl(lco_ctx ctx, const Tin* in, T* out, int64_t n, T* total, const ch
   }
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   if (tiles == 1) {
-    LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), 1, kScanThreads, 0, in, out, n, (const T*)nullptr, total);
+    LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), 1, kScanThreads, 0, in, out, n, (const T*)nullptr,
+               (const T*)nullptr, total);
     return;
   }
   Scratch s(ctx);
   T* partials = s.get<T>(tiles);
-  T* poff = s.get<T>(tiles);
   LCO_LAUNCH(ctx, "scan_reduce", (scan_reduce_kernel<Tin, T>), tiles, kScanThreads, 0, in, n, partials);
+  if (tiles <= kSumPartialsMax) {
+    // each tile adds up the partial sums before it (two launches instead of three)
+    LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), tiles, kScanThreads, 0, in, out, n, (const T*)nullptr,
+               (const T*)partials, total);
+    return;
+  }
+  T* poff = s.get<T>(tiles);
   scan_impl<T, T>(ctx, partials, poff, tiles, (T*)nullptr, name);
-  LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), tiles, kScanThreads, 0, in, out, n, (const T*)poff, total);
+  LCO_LAUNCH(ctx, name, (scan_tile_kernel<Tin, T>), tiles, kScanThreads, 0, in, out, n, (const T*)poff,
+             (const T*)nullptr, total);
 }
 
 }  // namespace
