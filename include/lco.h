@@ -120,6 +120,12 @@ lco_status lco_ctx_get_crossovers(lco_ctx ctx, double* doubly_compressed, double
  * equals `kernel` since the last reset: *launches, *total_ms.  Timing of a
  * launch is collected lazily at query time. */
 lco_status lco_timing_enable(lco_ctx ctx, int on);
+/* Restricts timing to launches of the kernel named `kernel` (copied; NULL or
+ * "" times every kernel again).  Each timed launch adds two event records to
+ * the stream, which costs a few microseconds of device time per launch, so a
+ * caller that needs one kernel's duration times only that one.  Errors:
+ * LCO_E_ARG when ctx is NULL. */
+lco_status lco_timing_only(lco_ctx ctx, const char* kernel);
 lco_status lco_timing_reset(lco_ctx ctx);
 lco_status lco_timing_query(lco_ctx ctx, const char* kernel, int64_t* launches, double* total_ms);
 /* Name of the i-th distinct kernel seen by the timer (NULL past the end). */

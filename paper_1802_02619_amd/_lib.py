@@ -18,7 +18,7 @@ __all__ = [
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
     "lco_contract", "lco_add", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read",
     "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
-    "lco_fastdiv_host", "lco_timing_enable", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
+    "lco_fastdiv_host", "lco_timing_enable", "lco_timing_only", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_ctx_set_crossovers", "lco_ctx_get_crossovers", "MI355X_CROSSOVERS", "PAPER_CROSSOVERS",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
@@ -123,6 +123,7 @@ def load_library():
             "lco_ctx_set_stream": (i32, [vp, vp]),
             "lco_ctx_synchronize": (i32, [vp]),
             "lco_timing_enable": (i32, [vp, i32]),
+            "lco_timing_only": (i32, [vp, ctypes.c_char_p]),
             "lco_timing_reset": (i32, [vp]),
             "lco_timing_query": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
             "lco_timing_kernel_name": (ctypes.c_char_p, [vp, i32]),
@@ -575,6 +576,11 @@ def lco_fastdiv_host(d: int, nums):
 # ------------------------------------------------------------------ timing
 def lco_timing_enable(ctx: Context, on: bool = True):
     _check(load_library().lco_timing_enable(ctx.handle, int(on)))
+
+
+def lco_timing_only(ctx: Context, kernel=None):
+    """Time only launches of `kernel` (None: every kernel)."""
+    _check(load_library().lco_timing_only(ctx.handle, kernel.encode() if kernel else None))
 
 
 def lco_timing_reset(ctx: Context):

@@ -86,6 +86,7 @@ Timer::~Timer() {
 
 LaunchScope::LaunchScope(lco_ctx c, const char* n) : ctx(c), name(-1) {
   if (!ctx->timer.on) return;
+  if (!ctx->timer.only.empty() && ctx->timer.only != n) return;
   name = ctx->timer.idx(n);
   hipEvent_t a = ctx->timer.get_event();
   LCO_HIP(hipEventRecord(a, ctx->stream));
@@ -417,6 +418,14 @@ lco_status lco_timing_enable(lco_ctx ctx, int on) {
   if (!ctx) return set_error_msg(LCO_E_ARG, "lco_timing_enable: ctx is NULL");
   ctx->timer.on = on != 0;
   return LCO_OK;
+}
+
+lco_status lco_timing_only(lco_ctx ctx, const char* kernel) {
+  if (!ctx) return set_error_msg(LCO_E_ARG, "lco_timing_only: ctx is NULL");
+  LCO_TRY
+  ctx->timer.only = kernel ? kernel : "";
+  return LCO_OK;
+  LCO_CATCH
 }
 
 lco_status lco_timing_reset(lco_ctx ctx) {

@@ -27,6 +27,7 @@ void hip_check(hipError_t e, const char* what);
 // ------------------------------------------------------------------ timing
 struct Timer {
   bool on = false;
+  std::string only;  // when not empty: time launches of this kernel only
   struct Rec { int name; hipEvent_t a, b; };
   std::vector<std::string> names;
   std::map<std::string, int> name_idx;

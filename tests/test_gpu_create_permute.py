@@ -190,6 +190,41 @@ def test_permute_hypersparse_64bit(lco_lib, gpu_ctx, oracle_mod):
     same(gp, oracle_mod.permute(o, [2, 3, 0, 1]))
 
 
+def test_timing_filter(lco_lib, gpu_ctx, oracle_mod):
+    """lco_timing_only: with a kernel name, only that kernel's launches are
+    bracketed by events; with None, every kernel is again."""
+    rng = np.random.default_rng(12)
+    dims = [1 << 16] * 4
+    coords, _ = L.random_sparse(rng, dims, 40000)
+    vals = rng.uniform(-1, 1, len(coords))
+    t = gpu_create(lco_lib, gpu_ctx, dims, coords, vals)
+
+    def launched():
+        return {k for k in lco_lib.lco_timing_kernels(gpu_ctx) if lco_lib.lco_timing_query(gpu_ctx, k)[0]}
+
+    lco_lib.lco_timing_reset(gpu_ctx)
+    lco_lib.lco_timing_only(gpu_ctx, "rx_scatter")
+    lco_lib.lco_timing_enable(gpu_ctx, True)
+    p = lco_lib.lco_permute(gpu_ctx, t, [3, 2, 1, 0])
+    lco_lib.lco_timing_enable(gpu_ctx, False)
+    assert launched() == {"rx_scatter"}
+    n1, ms1 = lco_lib.lco_timing_query(gpu_ctx, "rx_scatter")
+    assert n1 >= 2 and ms1 > 0
+    p.destroy()
+    lco_lib.lco_timing_reset(gpu_ctx)
+    lco_lib.lco_timing_only(gpu_ctx, None)
+    lco_lib.lco_timing_enable(gpu_ctx, True)
+    p = lco_lib.lco_permute(gpu_ctx, t, [3, 2, 1, 0])
+    lco_lib.lco_timing_enable(gpu_ctx, False)
+    assert {"rx_scatter", "rx_count"} <= launched()
+    lco_lib.lco_timing_reset(gpu_ctx)
+    same = oracle_mod.permute(oracle_mod.create(dims, coords, vals), [3, 2, 1, 0])
+    _, livs, v = p.to_numpy()
+    assert np.array_equal(livs, same.livs) and np.array_equal(v.view(np.uint64), same.vals.view(np.uint64))
+    p.destroy()
+    t.destroy()
+
+
 def test_permute_3d_fd_operator_order6(lco_lib, gpu_ctx, oracle_mod):
     c, v = L.fd_laplacian(24, 3)
     _perm_case(lco_lib, gpu_ctx, oracle_mod, [24] * 6, c, v, [(3, 4, 5, 0, 1, 2), (1, 0, 2, 3, 4, 5),
