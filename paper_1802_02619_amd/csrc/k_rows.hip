@@ -107,12 +107,13 @@ __global__ void entry_len_kernel(RowArgs ra, uint32_t* __restrict__ len, uint32_
 
 // The same, together with the rows of A' taken densely, every row 0..m'-1
 // including empty ones (for products where A' has few empty rows):
-// row_start[r] = first entry of row r, row_id[r] = r, *count = m'.  Empty
-// rows hold no products and are skipped.  Also clears the four counter words
-// `zero4` of the classification that follows.
+// row_start[r] = first entry of row r, *count = m' (row r of the list is row r
+// of A', so no ids are stored).  Empty rows hold no products and are skipped.
+// Also clears the four counter words `zero4` of the classification that
+// follows.
 template <bool DENSE>
 __global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restrict__ row_start,
-                                      uint64_t* __restrict__ row_id, uint64_t* __restrict__ count,
+                                      uint64_t* __restrict__ count,
                                       uint32_t* __restrict__ len, uint32_t* __restrict__ bstart,
                                       uint64_t* __restrict__ zero4) {
   const int64_t n = ra.nnz_a;
@@ -128,10 +129,7 @@ __global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restr
       bstart[e] = st;
     }
     const uint64_t lo = e == 0 ? 0 : fd_div(ra.kdiv, ra.a_livs[e - 1]) + 1;
-    for (uint64_t r = lo; r <= hi; ++r) {
-      row_start[r] = (uint32_t)e;
-      if (r < mp) row_id[r] = r;
-    }
+    for (uint64_t r = lo; r <= hi; ++r) row_start[r] = (uint32_t)e;
     if (e == n) *count = mp;
   }
 }
@@ -293,7 +291,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
       const uint64_t r = r0 + lane;
       m_s0 = ra.row_start[r];
       m_s1 = ra.row_start[r + 1];
-      m_id = ra.row_id[r];
+      m_id = row_of(ra, r);
       m_sh = shape[r];
       if (NUMERIC) m_off = coff[r];
     }
@@ -368,7 +366,7 @@ __device__ __forceinline__ uint32_t tiny_merge(const RowArgs& ra, uint32_t r, ui
                                                double* __restrict__ out_vals) {
   const uint32_t e0 = ra.row_start[r];
   const int t = (int)(ra.row_start[r + 1] - e0);
-  const uint64_t row = ra.row_id[r];
+  const uint64_t row = row_of(ra, r);
   uint32_t p[kTinyEntries], end[kTinyEntries];
   uint64_t jn[kTinyEntries], col[kTinyEntries];
   double av[kTinyEntries];
@@ -480,7 +478,7 @@ __global__ __launch_bounds__(256) void row_copy_kernel(RowArgs ra, uint32_t nzr,
   for (uint32_t r = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; r < nzr; r += waves) {
     if (shape[r] != kShapeCopy) continue;
     const uint32_t e0 = ra.row_start[r];
-    const uint64_t row = ra.row_id[r];
+    const uint64_t row = row_of(ra, r);
     const uint32_t len = ra.elen[e0], bs = ra.bstart[e0];
     const uint64_t jn = (ra.a_livs[e0] - ra.kp * row) * ra.np;
     const double a = ra.a_vals[e0];
@@ -508,7 +506,7 @@ __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, con
     const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
     const uint64_t p0 = ra.poff[e0];
     const uint64_t f = ra.poff[e1] - p0;
-    const uint64_t row = ra.row_id[r];
+    const uint64_t row = row_of(ra, r);
     const uint64_t qk = (uint64_t)li << colbits;
     const uint64_t base = off2[li];
     for (uint64_t p = threadIdx.x; p < f; p += kBigThreads) {
@@ -545,7 +543,7 @@ __global__ __launch_bounds__(kBigThreads) void big_reduce_kernel(RowArgs ra, con
     const uint32_t r = list[li];
     const uint64_t f = off2[li + 1] - off2[li];
     const uint64_t base = off2[li];
-    const uint64_t row = ra.row_id[r];
+    const uint64_t row = row_of(ra, r);
     uint64_t run = 0;  // heads seen before this chunk
     for (uint64_t c0 = 0; c0 < f; c0 += kBigThreads) {
       const uint64_t p = c0 + threadIdx.x;
@@ -655,16 +653,15 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     const uint64_t* nzr_word;
     if (dense_rows) {
       uint32_t* row_start = s.get<uint32_t>(mp + 1);
-      uint64_t* row_id = s.get<uint64_t>(mp);
       uint64_t* count = s.get<uint64_t>(1);
       if (dense)
         LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<true>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
-                   row_start, row_id, count, len, bstart, n2_dev);
+                   row_start, count, len, bstart, n2_dev);
       else
         LCO_LAUNCH(ctx, "dense_rows_len", dense_rows_len_kernel<false>, grid_for(ctx, na + 1, 256), 256, 0, ra, mp,
-                   row_start, row_id, count, len, bstart, n2_dev);
+                   row_start, count, len, bstart, n2_dev);
       ra.row_start = row_start;
-      ra.row_id = row_id;
+      ra.row_id = nullptr;
       ra.nzr_a = count;
       nzr_word = count;
     } else {

@@ -251,11 +251,10 @@ struct RowOut {
   double val = 0.0;   // its summed value (numeric only)
 };
 
-// The product of one small row of A' by one wave.  Returns the number of
-// distinct columns (the row's output count); when NUMERIC, `o` receives this
-// lane's output entry.
-// The reduction of one small row's products (one per lane: `valid`, its A'
-// entry `ent` in the row, column `col`, value `v`) into the row's output.
+// The reduction of one small row's products by one wave (one product per
+// lane: `valid`, its A' entry `ent` in the row, column `col`, value `v`; the
+// row has t entries).  Returns the number of distinct columns (the row's output
+// count); when NUMERIC, `o` receives this lane's output entry.
 template <bool ACC, bool NUMERIC>
 __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col, double v, int t, bool narrow,
                                                int lane, RowLds<NUMERIC>& L, RowOut& o) {
@@ -284,10 +283,6 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
       }
     }
     wave_lds_sync();
-    // Probe until the slot is empty (this lane inserts the column) or holds the
-    // column; at most 64 columns in 128 slots, so a free slot always exists.
-    // A lane that is done moves to its spare slot, and the wave leaves the
-    // loop together once no lane is still probing.
     uint32_t slot = valid ? (narrow ? hash_slot32((uint32_t)col) : hash_slot(col)) : 0;
     uint32_t owner = 0;  // the lane that inserted the column (table rows)
     bool isnew = false;
@@ -308,9 +303,9 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
         }
       }
     } else {
-      // The same probing, but a lane that is done moves to its spare slot, and
-      // the wave leaves the loop together once no lane is still probing (fewer
-      // scalar instructions than a divergent loop).
+      // The same probing, but a lane that is done moves to its spare slot (past
+      // the table), and the wave leaves the loop together once no lane is still
+      // probing: fewer scalar instructions than a divergent loop.
       const uint32_t spare = kHashSlots + lane;
       uint32_t at = valid ? slot : spare;
       if (key32) {

@@ -31,12 +31,15 @@ struct RowArgs {
   const uint32_t* brow_start = nullptr;  //   and their starts (plus terminal)
   const uint64_t* nzr_b = nullptr;       //   device count of non-empty rows
   const uint32_t* row_start = nullptr;   // non-empty rows of A': starts (plus terminal)
-  const uint64_t* row_id = nullptr;      //   and ids
+  const uint64_t* row_id = nullptr;      //   and ids (nullptr: row r of the list is row r of A')
   const uint64_t* nzr_a = nullptr;       //   device count
   const uint32_t* elen = nullptr;        // products per A' entry (nnz_a; a B' row length, below 2^32)
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
   const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
 };
+
+// Row of A' at position r of the row list.
+__device__ __forceinline__ uint64_t row_of(const RowArgs& ra, uint64_t r) { return ra.row_id ? ra.row_id[r] : r; }
 
 // C' = A' * B' row by row; `dense` selects singly (CSR) or doubly (DCSR)
 // compressed B', `acc` the sparse accumulator (CSR, DCSR) or none (CSRNA).
