@@ -126,8 +126,10 @@ __global__ void bt_classify_kernel(const uint32_t* __restrict__ rs, const uint32
 // metadata and a window of 64 consecutive entries loaded coalesced (the rows'
 // products are then gathered by lane shuffles, as in the per-call engine).  A
 // window holds entries of one instance only; a row of another instance, or
-// entries outside the window, move it.
-template <bool ACC, bool NUMERIC>
+// entries outside the window, move it.  As in the per-call engine, the B'
+// loads of the next row are issued before the current row is reduced.
+// NARROW: every instance has columns below 2^32 (else each row checks).
+template <bool ACC, bool NUMERIC, bool NARROW>
 __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
     const BInst* __restrict__ in, const uint32_t* __restrict__ rs, const uint64_t* __restrict__ rid,
     const uint32_t* __restrict__ rinst, const uint8_t* __restrict__ shape, const uint32_t* __restrict__ fallback,
@@ -159,14 +161,13 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
     uint32_t x_len = 0, x_bs = 0;
     uint64_t x_jn = 0;
     double x_av = 0.0;
-    for (int i = 0; i < rows; ++i) {
+    uint64_t todo = __ballot(lane < rows && m_sh != kShapeSkip);
+    RowProduct<NUMERIC> next;
+    auto stage = [&](int i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
-      if (sh == kShapeSkip) continue;
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
       const uint32_t xi = readlane_u32(m_in, i);
-      const uint64_t row = readlane_u64(m_id, i);
       const BInst& x = in[xi];
-      const int t = (int)(e1 - e0);
       if (xi != w_inst || (int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
         w0 = e0;
         w_inst = xi;
@@ -180,16 +181,28 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
           if (NUMERIC) x_av = x.a_vals[g - x.eoff];
         }
       }
-      RowProduct<NUMERIC> pr;
-      window_products<NUMERIC>(x.b_livs, x.b_vals, e0, t, sh, lane, w0, x_len, x_bs, x_jn, x_av, pr);
+      window_products<NUMERIC>(x.b_livs, x.b_vals, e0, (int)(e1 - e0), sh, lane, w0, x_len, x_bs, x_jn, x_av,
+                               next);
+    };
+    if (todo) stage(__builtin_ctzll(todo));
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const bool valid = next.valid;
+      const int ent = next.ent;
+      const uint64_t col = next.col();
+      const double v = next.val();
+      const int t = (int)(readlane_u32(m_s1, i) - readlane_u32(m_s0, i));
+      const uint64_t np = in[readlane_u32(m_in, i)].np;
+      if (todo) stage(__builtin_ctzll(todo));
       RowOut o;
       const uint32_t d =
-          row_reduce<ACC, NUMERIC>(pr.valid, pr.ent, pr.col(), pr.val(), t, x.np < (1ull << 32), lane, s_lds[w], o);
+          row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, NARROW || np < (1ull << 32), lane, s_lds[w], o);
       if (!NUMERIC) {
         if (lane == i) my_cnt = d;
       } else if (o.own) {
         const uint64_t pos = readlane_u64(m_off, i) + o.rank;
-        out_livs[pos] = o.col + x.np * row;
+        out_livs[pos] = o.col + np * readlane_u64(m_id, i);
         out_vals[pos] = o.val;
       }
     }
@@ -258,16 +271,21 @@ int batch_grid(lco_ctx ctx, uint64_t rows, int chunk_rows, int blocks_per_cu) {
                                                        (uint64_t)ctx->num_cus * blocks_per_cu));
 }
 
+#define LCO_BT_LAUNCH(NAME, ACC, NUM, ...)                                                               \
+  do {                                                                                                     \
+    if (narrow) LCO_LAUNCH(ctx, NAME, (bt_chunk_kernel<ACC, NUM, true>), __VA_ARGS__);                   \
+    else LCO_LAUNCH(ctx, NAME, (bt_chunk_kernel<ACC, NUM, false>), __VA_ARGS__);                         \
+  } while (0)
+
 void batch_numeric(lco_ctx ctx, const BatchLaunch& L) {
   const BInst* in = static_cast<const BInst*>(L.inst);
+  const bool narrow = L.narrow;
   if (L.acc)
-    LCO_LAUNCH(ctx, "bt_small_num", (bt_chunk_kernel<true, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
-               L.shape, L.fallback, L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs,
-               L.out_vals);
+    LCO_BT_LAUNCH("bt_small_num", true, true, L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst, L.shape, L.fallback,
+                  L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
   else
-    LCO_LAUNCH(ctx, "bt_small_num", (bt_chunk_kernel<false, true>), L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst,
-               L.shape, L.fallback, L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs,
-               L.out_vals);
+    LCO_BT_LAUNCH("bt_small_num", false, true, L.grid, kRowThreads, 0, in, L.rs, L.rid, L.rinst, L.shape, L.fallback,
+                  L.poff, L.bstart, L.rows, L.chunk_rows, (uint64_t*)nullptr, L.coff, L.out_livs, L.out_vals);
 }
 
 std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs,
@@ -276,6 +294,7 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   std::vector<BInst> host(count);
   std::vector<int64_t> eoff(count + 1), boff(count + 1);
   int64_t E = 0, BS = 0, K = 0;
+  bool narrow = true;  // every instance has columns below 2^32
   for (int i = 0; i < count; ++i) {
     const BatchJob& j = jobs[i];
     BInst& x = host[i];
@@ -290,6 +309,7 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
     x.koff = K;
     x.kp = j.kp;
     x.np = j.np;
+    narrow = narrow && j.np < ((uint64_t)1 << 32);
     x.kdiv = make_fastdiv(j.kp);
     x.ndiv = make_fastdiv(j.np);
     E += x.nnz_a;
@@ -341,13 +361,13 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   const int chunk_rows = batch_chunk_rows(ctx, R);
   const int grid = batch_grid(ctx, R, chunk_rows, 16);
   if (acc)
-    LCO_LAUNCH(ctx, "bt_small_sym", (bt_chunk_kernel<true, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst, shape,
-               fallback, poff, bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-               (double*)nullptr);
+    LCO_BT_LAUNCH("bt_small_sym", true, false, grid, kRowThreads, 0, d_in, rs, rid, rinst, shape, fallback, poff,
+                  bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                  (double*)nullptr);
   else
-    LCO_LAUNCH(ctx, "bt_small_sym", (bt_chunk_kernel<false, false>), grid, kRowThreads, 0, d_in, rs, rid, rinst,
-               shape, fallback, poff, bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr,
-               (uint64_t*)nullptr, (double*)nullptr);
+    LCO_BT_LAUNCH("bt_small_sym", false, false, grid, kRowThreads, 0, d_in, rs, rid, rinst, shape, fallback, poff,
+                  bstart, (uint32_t)R, chunk_rows, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                  (double*)nullptr);
   scan_u64(ctx, cnt, coff, R, coff + R);
   uint64_t* ranges = s.get<uint64_t>(2 * count);
   LCO_LAUNCH(ctx, "bt_ranges", bt_ranges_kernel, grid_for(ctx, count, 256), 256, 0, d_in, count, rpos, coff, fallback,
@@ -367,6 +387,7 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   try {
     BatchLaunch L;
     L.acc = acc;
+    L.narrow = narrow;
     L.grid = grid;
     L.chunk_rows = chunk_rows;
     L.rows = (uint32_t)R;
@@ -399,5 +420,7 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
   release_pool(pool);  // the tensors hold the remaining references
   return redo;
 }
+
+#undef LCO_BT_LAUNCH
 
 }  // namespace lco

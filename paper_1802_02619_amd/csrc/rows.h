@@ -73,6 +73,7 @@ struct KeptBuffers {
 // Everything the numeric pass of one batch group reads and writes.
 struct BatchLaunch {
   bool acc = true;
+  bool narrow = false;  // every instance has columns below 2^32
   int grid = 1;
   int chunk_rows = 1;  // consecutive rows per wave visit
   uint32_t rows = 0;
