@@ -10,21 +10,21 @@
 // LIV = col + n'*row.  Each output entry sums its products in ascending order
 // of the contracted index starting from 0.0.
 //
-// Setup: the rows of A' (row starts and ids), the row pointers of B' (or its
-// non-empty rows when doubly compressed), and for every A' entry its product
-// count and B' row start.  Rows of A' come from one pointer kernel over all m'
-// rows when few are empty, else from head flags, a scan and a compaction; small
-// products do the whole setup in one block.
+// Setup: the row pointers of B' (or its non-empty rows when doubly
+// compressed), the rows of A' (row starts, and ids unless every row is
+// listed), and for every A' entry its product count and B' row start.  When
+// few rows of A' are empty, one pass over A' lists all m' rows and writes the
+// per-entry data; otherwise head flags, a scan and a compaction list the
+// non-empty rows.  Small products do the whole setup in one block.
 //
 // Work split: the rows of A' are binned by their product count f(i).
 //  - at most 4 A' entries and f(i) <= 16: one lane per row (k-way merge of the
 //    entries' B' rows); from 65536 A' entries up.
 //  - one A' entry and f(i) > 16: a wave copies the scaled B' row; idem.
-//  - f(i) <= 64 and at most 64 A' entries: one wave per row, rows in chunks.
-//    CSR/DCSR insert the row's columns into an LDS hash table; each product
-//    records its lane under its column, and the column's first product (its
-//    owner) sums the column's values in lane order, i.e. ascending A' entry;
-//    owners are ranked by column and written in order.  CSRNA sorts the
+//  - f(i) <= 64 and at most 64 A' entries: one wave per row, rows in chunks
+//    (see row_core.h).  CSR/DCSR insert the row's columns into an LDS hash
+//    table and sum each column's products in ascending A' entry order; the
+//    outputs are ranked by column and written in order.  CSRNA sorts the
 //    (column, product index) pairs with a wave bitonic network and sums runs.
 //  - larger rows: products are expanded to global memory keyed by (row rank,
 //    column), sorted with the stable radix engine and summed per run.
@@ -265,8 +265,10 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
 // coalesced load per array; a row then takes its entries' data from the window
 // by lane shuffles, so the only global loads that depend on the row are those
 // of its rows of B'.  The window moves forward when a row's entries leave it
-// (rows are consecutive, so their entries are too).  The symbolic pass waits on
-// memory more than it computes, so it is held to 8 waves per SIMD (64 VGPRs).
+// (rows are consecutive, so their entries are too).  The symbolic pass is held
+// to 8 waves per SIMD (64 VGPRs) and the numeric pass to 6 (80 VGPRs), the
+// fastest bounds measured.  NARROW: columns below 2^32 (n' < 2^32), fixed at
+// compile time so that the width is no per-row branch.
 constexpr int kChunkRows = kWave;
 
 template <bool ACC, bool NUMERIC, bool NARROW>
