@@ -28,8 +28,11 @@
  *   - "device" pointers address HIP device memory of the context's device;
  *     "host" pointers address ordinary host memory.
  *   - All device work is enqueued on the context's stream.  Entry points that
- *     must learn a data-dependent size (lco_create, lco_contract, lco_add)
- *     synchronise that stream before returning; lco_permute does not.
+ *     must learn a data-dependent size (lco_create, lco_contract, lco_add) wait
+ *     on the host for the stream's work up to that point (a device-written
+ *     flag in pinned memory) before they allocate their output; the kernels
+ *     that fill it may still be running when they return.  lco_permute does
+ *     not wait.
  *   - Tensors are owned by the caller and released with lco_destroy, which must
  *     happen before the context that made them is destroyed.  Inputs are never
  *     modified.  An input may come from any context on the same device; work
