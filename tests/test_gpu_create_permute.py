@@ -232,6 +232,38 @@ def test_permute_3d_fd_operator_order6(lco_lib, gpu_ctx, oracle_mod):
 
 
 @pytest.mark.slow
+def test_permute_large_recursive_scans(lco_lib, gpu_ctx):
+    """140 M random entries of a 2^16-per-mode order-4 tensor: the radix passes
+    (64-bit keys, 8 passes) scan digit-count arrays of 8.75 M entries, more
+    than the two-launch scan takes, so the recursive scan runs.  All on the
+    device: a permutation is strictly increasing, and permuting back restores
+    the tensor bit for bit."""
+    import torch
+    n = 140_000_000
+    dims = [1 << 16] * 4
+    print(f"large permute n={n}", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    coords = torch.randint(0, 1 << 16, (n, 4), device="cuda", generator=g, dtype=torch.int64)
+    vals = torch.rand(n, device="cuda", generator=g, dtype=torch.float64)
+    t = lco_lib.lco_create(gpu_ctx, dims, coords.reshape(-1), vals, lco_lib.LCO_COORDS | lco_lib.LCO_SUM_DUPLICATES)
+    del coords, vals
+    lco_lib.lco_timing_reset(gpu_ctx)
+    lco_lib.lco_timing_enable(gpu_ctx, True)
+    p = lco_lib.lco_permute(gpu_ctx, t, [1, 0, 3, 2])
+    lco_lib.lco_timing_enable(gpu_ctx, False)
+    passes = lco_lib.lco_timing_query(gpu_ctx, "rx_scatter")[0]
+    reduces = lco_lib.lco_timing_query(gpu_ctx, "scan_reduce")[0]
+    lco_lib.lco_timing_reset(gpu_ctx)
+    assert passes >= 2 and reduces == 2 * passes  # each pass's scan also reduces its tile sums
+    back = lco_lib.lco_permute(gpu_ctx, p, [1, 0, 3, 2])
+    pl = p.livs() ^ torch.iinfo(torch.int64).min  # order-preserving map of the unsigned LIVs to int64
+    assert p.nnz == t.nnz and bool((pl[1:] > pl[:-1]).all())
+    assert torch.equal(back.livs(), t.livs()) and torch.equal(back.vals().view(torch.int64), t.vals().view(torch.int64))
+    for x in (back, p, t):
+        x.destroy()
+
+
+@pytest.mark.slow
 def test_permute_3d_fd_full_size(lco_lib, gpu_ctx, oracle_mod):
     """128^3 grid operator (14,581,760 entries), modes (1..6) -> (4,5,6,1,2,3): bit-exact vs the oracle;
     the operator is symmetric, so the result also equals the input."""
