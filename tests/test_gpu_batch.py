@@ -81,6 +81,52 @@ def test_batch_mixed_instances_equal_per_call(lco_lib, gpu_ctx, oracle_mod):
         out.destroy()
 
 
+def test_batch_mixed_column_widths(lco_lib, gpu_ctx, oracle_mod):
+    """A batch in which one instance has 2^34 columns and the others fewer than
+    2^32: the batched row kernels then check the width per row (64-bit hash keys
+    for that instance, 32-bit table rows for the others).  Equal to per-call
+    products and to the oracle bit for bit."""
+    rng = np.random.default_rng(34)
+    items, refs, keep = [], [], []
+    for side, dim in ((9, 2), (12, 3)):
+        c, v = L.fd_laplacian(side, dim)
+        g = gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v)
+        keep.append(g)
+        la, lb = list(range(2 * dim)), list(range(dim, 3 * dim))
+        lc = list(range(dim)) + list(range(2 * dim, 3 * dim))
+        items.append((g, la, g, lb, lc))
+        o = oracle_mod.create([side] * (2 * dim), c, v)
+        refs.append(oracle_mod.contract(o, la, o, lb, lc))
+    da, db = [1 << 14, 1 << 14, 64], [64, 1 << 17, 1 << 17]
+    heads = np.column_stack([rng.integers(0, da[0], 80), rng.integers(0, da[1], 80)]).astype(np.uint64)
+    ca = np.unique(np.column_stack([heads[rng.integers(0, 80, 240)], rng.integers(0, 64, 240).astype(np.uint64)]),
+                   axis=0)
+    cb = np.column_stack([rng.integers(0, 64, 150), rng.integers(0, db[1], 150), rng.integers(0, db[2], 150)])
+    cb = np.unique(cb.astype(np.uint64), axis=0)
+    va, vb = rng.uniform(-1, 1, len(ca)), rng.uniform(-1, 1, len(cb))
+    ga, gb = gpu_create(lco_lib, gpu_ctx, da, ca, va), gpu_create(lco_lib, gpu_ctx, db, cb, vb)
+    keep += [ga, gb]
+    # row by row (forced CSR), so that the wide side is the column side
+    items.append((ga, [0, 1, 2], gb, [2, 3, 4], [0, 1, 3, 4], lco_lib.ALGO_IDS["CSR"]))
+    refs.append(oracle_mod.contract(oracle_mod.create(da, ca, va), [0, 1, 2], oracle_mod.create(db, cb, vb),
+                                    [2, 3, 4], [0, 1, 3, 4]))
+    outs = lco_lib.lco_contract_batch(gpu_ctx, items)
+    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call}", flush=True)
+    assert batched == 3 and per_call == 0
+    for it, out, ref in zip(items, outs, refs):
+        single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
+        got, alone = np_of(out), np_of(single)
+        assert got[0] == alone[0]
+        assert np.array_equal(got[1], alone[1]) and np.array_equal(got[2], alone[2])
+        assert np.array_equal(got[1], ref.livs) and np.array_equal(got[2], ref.vals.view(np.uint64))
+        single.destroy()
+    for out in outs:
+        out.destroy()
+    for t in keep:
+        t.destroy()
+
+
 def test_batch_many_small_fd(lco_lib, gpu_ctx, oracle_mod):
     """200 uneven 2-D / 3-D FD compositions (sides 4..24) in one batch: every result equals its
     closed-form size and the per-call result."""
