@@ -766,6 +766,7 @@ def main():
                     help="run only the 1 GiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--app-only", action="store_true", help="run only the combinatorial Laplacian leg")
     ap.add_argument("--rp-only", action="store_true", help="run only the permutation-table leg")
+    ap.add_argument("--hyper-only", action="store_true", help="run only the hyper-sparse (SOP) leg")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the selector calibration sweeps (R-TENSORs, Sections 5.2.3-5.2.5)")
     ap.add_argument("--calibrate-reps", type=int, default=3)
@@ -796,6 +797,9 @@ def main():
         return
     if args.rp_only:
         print(json.dumps({"rp_table": rp_leg(lco, ctx, torch, np, L, args.rp_n, max(1, args.rp_reps))}), flush=True)
+        return
+    if args.hyper_only:
+        print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps))}), flush=True)
         return
     coords, vals = L.fd_laplacian(SIDE, 3)
     idx_d = torch.from_numpy(coords.view(np.int64).reshape(-1).copy()).to("cuda:0")
