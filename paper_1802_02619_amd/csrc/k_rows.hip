@@ -167,19 +167,32 @@ __global__ void row_classify_kernel(RowArgs ra, int64_t upper, bool classes, uin
                                     uint8_t* __restrict__ shape, uint32_t* __restrict__ tiny,
                                     uint32_t* __restrict__ copy, uint32_t* __restrict__ wave) {
   const uint64_t nzr = *ra.nzr_a;
+  const int lane = lane_id();
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
     if ((uint64_t)r >= nzr) break;
     uint64_t f;
     const uint8_t sh = classify_row(ra, ra.row_start[r], ra.row_start[r + 1], classes, &f);
-    if (sh == kShapeTiny) *tiny = 1u;
-    else if (sh == kShapeCopy) *copy = 1u;
-    else if (sh <= kShapeSearch) *wave = 1u;
-    else if (f) {
-      const uint64_t i = atomicAdd((unsigned long long*)n2, 1ull);
-      list2[i] = (uint32_t)r;
-      f2[i] = f;
-    }
     shape[r] = sh;
+    // one flag store and one list reservation per wave rather than per row
+    const bool is_long = sh == kShapeSkip && f != 0;
+    const uint64_t tm = __ballot(sh == kShapeTiny), cm = __ballot(sh == kShapeCopy);
+    const uint64_t wm = __ballot(sh <= kShapeSearch), lm = __ballot(is_long);
+    const int first = __builtin_ctzll(__ballot(1));
+    uint64_t base = 0;
+    if (lane == first) {
+      if (tm) *tiny = 1u;
+      if (cm) *copy = 1u;
+      if (wm) *wave = 1u;
+      if (lm) base = atomicAdd((unsigned long long*)n2, (unsigned long long)__popcll(lm));
+    }
+    if (lm) {
+      base = __shfl(base, first, kWave);
+      if (is_long) {
+        const uint64_t i = base + (uint64_t)__popcll(lm & lanemask_lt());
+        list2[i] = (uint32_t)r;
+        f2[i] = f;
+      }
+    }
   }
 }
 
