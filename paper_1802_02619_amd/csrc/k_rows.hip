@@ -44,14 +44,17 @@ __device__ __forceinline__ void b_row(const RowArgs& ra, uint64_t j, uint32_t& s
     start = ra.bptr[j];
     len = ra.bptr[j + 1] - start;
   } else {
-    const uint64_t n = *ra.nzr_b;
-    uint64_t lo = 0, hi = n;
+    // the rows whose ids share j's bucket, then a search among them
+    const uint64_t b = j >> ra.bshift;
+    uint32_t lo = ra.bkt[b];
+    const uint32_t end = ra.bkt[b + 1];
+    uint32_t hi = end;
     while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
+      const uint32_t mid = (lo + hi) >> 1;
       if (ra.brow_id[mid] < j) lo = mid + 1;
       else hi = mid;
     }
-    if (lo < n && ra.brow_id[lo] == j) {
+    if (lo < end && ra.brow_id[lo] == j) {
       start = ra.brow_start[lo];
       len = ra.brow_start[lo + 1] - start;
     } else {
@@ -88,6 +91,21 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
     const uint64_t lo = e == 0 ? 0 : fd_div(ndiv, livs[e - 1]) + 1;
     const uint64_t hi = e == n ? kp : fd_div(ndiv, livs[e]);
     for (uint64_t r = lo; r <= hi; ++r) bptr[r] = (uint32_t)e;
+  }
+}
+
+// Bucket index of the non-empty row ids of a doubly compressed B' (ids[0..*count),
+// ascending, below k'): bkt[b] = first i with ids[i] >> shift >= b, for b in
+// [0, nb] where nb = ((k' - 1) >> shift) + 1, so bkt[nb] = *count.  `cap`
+// bounds *count.
+__global__ void bucket_ptr_kernel(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ count, int64_t cap,
+                                  int shift, uint64_t nb, uint32_t* __restrict__ bkt) {
+  const int64_t n = (int64_t)*count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n && i <= cap;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = i == 0 ? 0 : (ids[i - 1] >> shift) + 1;
+    const uint64_t hi = i == n ? nb : ids[i] >> shift;
+    for (uint64_t b = lo; b <= hi; ++b) bkt[b] = (uint32_t)i;
   }
 }
 
@@ -134,11 +152,6 @@ __global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restr
   }
 }
 
-// Writes the shape code of every row and collects the long rows (more than 64
-// products or entries, except single-entry rows) in `list2` with their product
-// counts `f2` (list order is arbitrary; each long row's result depends only on
-// its own products).  `*tiny` / `*copy` / `*wave` are set when some row is of
-// that class (`wave`: a row of the one-wave kernel).
 // The class of row r (entries [e0, e1)); `classes` enables the tiny and copy
 // classes.  A long row reports its product count through *f_long (else 0).
 __device__ __forceinline__ uint8_t classify_row(const RowArgs& ra, uint32_t e0, uint32_t e1, bool classes,
@@ -159,40 +172,97 @@ __device__ __forceinline__ uint8_t classify_row(const RowArgs& ra, uint32_t e0, 
     return ((uint64_t)(e1 - e0) << lw) <= (uint64_t)kWave ? (uint8_t)lw : kShapeSearch;
   }
   *f_long = f;
-  return kShapeSkip;
+  return kShapeLong;
 }
 
-__global__ void row_classify_kernel(RowArgs ra, int64_t upper, bool classes, uint64_t* __restrict__ n2,
-                                    uint32_t* __restrict__ list2, uint64_t* __restrict__ f2,
-                                    uint8_t* __restrict__ shape, uint32_t* __restrict__ tiny,
-                                    uint32_t* __restrict__ copy, uint32_t* __restrict__ wave) {
-  const uint64_t nzr = *ra.nzr_a;
-  const int lane = lane_id();
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < upper; r += (int64_t)gridDim.x * blockDim.x) {
-    if ((uint64_t)r >= nzr) break;
-    uint64_t f;
-    const uint8_t sh = classify_row(ra, ra.row_start[r], ra.row_start[r + 1], classes, &f);
-    shape[r] = sh;
-    // one flag store and one list reservation per wave rather than per row
-    const bool is_long = sh == kShapeSkip && f != 0;
-    const uint64_t tm = __ballot(sh == kShapeTiny), cm = __ballot(sh == kShapeCopy);
-    const uint64_t wm = __ballot(sh <= kShapeSearch), lm = __ballot(is_long);
-    const int first = __builtin_ctzll(__ballot(1));
-    uint64_t base = 0;
-    if (lane == first) {
-      if (tm) *tiny = 1u;
-      if (cm) *copy = 1u;
-      if (wm) *wave = 1u;
-      if (lm) base = atomicAdd((unsigned long long*)n2, (unsigned long long)__popcll(lm));
-    }
-    if (lm) {
-      base = __shfl(base, first, kWave);
-      if (is_long) {
-        const uint64_t i = base + (uint64_t)__popcll(lm & lanemask_lt());
-        list2[i] = (uint32_t)r;
-        f2[i] = f;
+constexpr int kClassifyThreads = 256;
+
+// Writes the shape code of every row and collects the long rows (more than 64
+// products or entries, except single-entry rows) in `list2` with their product
+// counts `f2`; `*n2` (zero on entry) ends as their number.  List order is
+// arbitrary: each long row's result depends only on its own products.
+// `*tiny` / `*copy` / `*wave` are set when some row is of that class (`wave`: a
+// row of the one-wave kernel).  `fl` (one word per row) holds the product count
+// of each long row between the two passes below.
+// The first pass classifies the rows and counts the long ones per wave; one
+// atomic per block then reserves the block's part of the list, and the second
+// pass writes it.  (A reservation per wave and row chunk serialised hundreds of
+// thousands of atomics on the one counter word when most chunks hold a long row.)
+__global__ __launch_bounds__(kClassifyThreads) void row_classify_kernel(
+    RowArgs ra, int64_t upper, bool classes, uint64_t* __restrict__ n2, uint32_t* __restrict__ list2,
+    uint64_t* __restrict__ f2, uint64_t* __restrict__ fl, uint8_t* __restrict__ shape, uint32_t* __restrict__ tiny,
+    uint32_t* __restrict__ copy, uint32_t* __restrict__ wave) {
+  constexpr int kWaves = kClassifyThreads / kWave;
+  __shared__ uint64_t s_off[kWaves + 1];
+  const int64_t nzr = (int64_t)*ra.nzr_a;
+  const int64_t end = nzr < upper ? nzr : upper;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int64_t first = (int64_t)blockIdx.x * kClassifyThreads + threadIdx.x - lane;
+  const int64_t stride = (int64_t)gridDim.x * kClassifyThreads;
+  uint64_t nlong = 0, any = 0;  // long rows of this wave; classes seen (bit 0 tiny, 1 copy, 2 one-wave)
+  // whole waves step together (every lane takes part in the shuffles below)
+  for (int64_t r0 = first; r0 < end; r0 += stride) {
+    const int64_t r = r0 + lane;
+    const bool valid = r < end;
+    const uint32_t e0 = valid ? ra.row_start[r] : 0u, e1 = valid ? ra.row_start[r + 1] : 0u;
+    // a row of more than 64 entries is long (or has no products): only its
+    // product count is needed, summed by the whole wave with coalesced loads
+    const bool many = e1 - e0 > (uint32_t)kWave;
+    uint64_t f = 0;
+    uint8_t sh = kShapeSkip;
+    if (valid && !many) sh = classify_row(ra, e0, e1, classes, &f);
+    for (uint64_t m = __ballot(many); m; m &= m - 1) {
+      const int src = __builtin_ctzll(m);
+      const uint32_t b0 = __shfl(e0, src, kWave), b1 = __shfl(e1, src, kWave);
+      uint64_t acc = 0;
+      uint64_t e = (uint64_t)b0 + lane;
+      for (; e + 3 * kWave < b1; e += 4 * kWave)
+        acc += (uint64_t)ra.elen[e] + ra.elen[e + kWave] + ra.elen[e + 2 * kWave] + ra.elen[e + 3 * kWave];
+      for (; e < b1; e += kWave) acc += ra.elen[e];
+      acc = wave_reduce_sum(acc);
+      if (lane == src) {
+        f = acc;
+        sh = acc ? kShapeLong : kShapeSkip;
       }
     }
+    if (valid) {
+      shape[r] = sh;
+      if (sh == kShapeLong) fl[r] = f;
+    }
+    nlong += (uint64_t)__popcll(__ballot(valid && sh == kShapeLong));
+    any |= (__ballot(valid && sh == kShapeTiny) ? 1u : 0u) | (__ballot(valid && sh == kShapeCopy) ? 2u : 0u) |
+           (__ballot(valid && sh <= kShapeSearch) ? 4u : 0u);
+  }
+  if (lane == 0) {
+    if (any & 1u) *tiny = 1u;
+    if (any & 2u) *copy = 1u;
+    if (any & 4u) *wave = 1u;
+    s_off[w] = nlong;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      const uint64_t c = s_off[i];
+      s_off[i] = tot;
+      tot += c;
+    }
+    s_off[kWaves] = tot ? atomicAdd((unsigned long long*)n2, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  if (nlong == 0) return;
+  // second pass over the same rows: each lane re-reads the codes it wrote
+  uint64_t base = s_off[kWaves] + s_off[w];
+  for (int64_t r0 = first; r0 < end; r0 += stride) {
+    const int64_t r = r0 + lane;
+    const bool is_long = r < end && shape[r] == kShapeLong;
+    const uint64_t lm = __ballot(is_long);
+    if (is_long) {
+      const uint64_t i = base + (uint64_t)__popcll(lm & lanemask_lt());
+      list2[i] = (uint32_t)r;
+      f2[i] = fl[r];
+    }
+    base += (uint64_t)__popcll(lm);
   }
 }
 
@@ -258,7 +328,7 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
     if (sh == kShapeTiny) s_cnt[1] = 1u;
     else if (sh == kShapeCopy) s_cnt[2] = 1u;
     else if (sh <= kShapeSearch) s_cnt[3] = 1u;
-    else if (f) {
+    else if (sh == kShapeLong) {
       const uint32_t i = atomicAdd(&s_cnt[0], 1u);
       list2[i] = rr;
       f2[i] = f;
@@ -511,7 +581,6 @@ constexpr int kBigThreads = 256;
 
 // Long row number li (list[li]) expands its products at off2[li], keyed by
 // (li, column); the key's list position keeps every row's products together.
-template <bool DENSE>
 __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, const uint32_t* __restrict__ list,
                                                                  uint32_t count, const uint64_t* __restrict__ off2,
                                                                  int colbits, uint64_t* __restrict__ keys,
@@ -533,9 +602,7 @@ __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, con
         else hi = mid - 1;
       }
       const uint64_t j = ra.a_livs[lo] - ra.kp * row;
-      uint32_t bs, len;
-      b_row<DENSE>(ra, j, bs, len);
-      const uint32_t q = bs + (uint32_t)(p0 + p - ra.poff[lo]);
+      const uint32_t q = ra.bstart[lo] + (uint32_t)(p0 + p - ra.poff[lo]);
       const uint64_t col = ra.b_livs[q] - ra.np * j;
       keys[base + p] = qk | col;
       vals[base + p] = ra.a_vals[lo] * ra.b_vals[q];
@@ -659,6 +726,16 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       ra.brow_id = brows.ids;
       ra.brow_start = brows.starts;
       ra.nzr_b = brows.count;
+      // buckets of 2^shift row ids, at most nnz_B of them
+      const uint64_t kmax = kp ? kp - 1 : 0;
+      int shift = 0;
+      while (shift < 63 && (kmax >> shift) + 1 > (uint64_t)std::max<int64_t>(nb, 1)) ++shift;
+      const uint64_t nbk = (kmax >> shift) + 1;
+      uint32_t* bkt = s.get<uint32_t>(nbk + 1);
+      LCO_LAUNCH(ctx, "bucket_ptr", bucket_ptr_kernel, grid_for(ctx, nb + 1, 256), 256, 0, brows.ids, brows.count,
+                 nb, shift, nbk, bkt);
+      ra.bkt = bkt;
+      ra.bshift = shift;
     }
     // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
     uint64_t* n2_dev = s.get<uint64_t>(4);
@@ -690,9 +767,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       memset_async(ctx, n2_dev, 0, 4 * sizeof(uint64_t));
     }
     // row shapes; long rows collected with their product counts
-    LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, (int64_t)rows_cap, 256), 256, 0, ra,
-               (int64_t)rows_cap, classes, n2_dev,
-               list2, f2, shape, (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
+    uint64_t* fl = s.get<uint64_t>(rows_cap);
+    LCO_LAUNCH(ctx, "row_classify", row_classify_kernel, grid_for(ctx, (int64_t)rows_cap, kClassifyThreads),
+               kClassifyThreads, 0, ra, (int64_t)rows_cap, classes, n2_dev, list2, f2, fl, shape,
+               (uint32_t*)flags_dev, (uint32_t*)(flags_dev + 1), (uint32_t*)(flags_dev + 2));
     const uint64_t* rb1[5] = {nzr_word, n2_dev, flags_dev, flags_dev + 1, flags_dev + 2};
     h = readback(ctx, rb1, 5);
   }
@@ -759,12 +837,8 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     double* ev = s.get<double>(f2_total);
     keys = s.get<uint64_t>(f2_total);
     pvals = s.get<double>(f2_total);
-    if (dense)
-      LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2, off2,
-                 colbits, ek, ev);
-    else
-      LCO_LAUNCH(ctx, "big_expand", big_expand_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
-                 off2, colbits, ek, ev);
+    LCO_LAUNCH(ctx, "big_expand", big_expand_kernel, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2, off2, colbits,
+               ek, ev);
     KeyParams kparams;
     radix_sort_pairs(ctx, ek, ev, keys, pvals, (int64_t)f2_total, nullptr, kparams, colbits + qbits, 0);
     LCO_LAUNCH(ctx, "big_reduce_sym", big_reduce_kernel<false>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,

@@ -84,7 +84,8 @@ __device__ __forceinline__ uint32_t hash_slot32(uint32_t c) {
 constexpr uint8_t kShapeSearch = 7;    // at most 64 products, located by search
 constexpr uint8_t kShapeTiny = 8;      // at most kTinyEntries entries and kTinyProducts products: one lane per row
 constexpr uint8_t kShapeCopy = 9;      // one entry (more than kTinyProducts products): the row is a scaled B' row
-constexpr uint8_t kShapeSkip = 0xFF;   // no products, or a long row
+constexpr uint8_t kShapeLong = 0xFE;   // more than 64 products or entries (not one entry): the long-row path
+constexpr uint8_t kShapeSkip = 0xFF;   // no products
 constexpr int kTinyEntries = 4;
 constexpr int kTinyProducts = 16;
 // Rows with at most 64 products and 64 entries run one wave per row.  When the

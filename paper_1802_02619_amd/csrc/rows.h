@@ -30,6 +30,8 @@ struct RowArgs {
   const uint64_t* brow_id = nullptr;     // doubly compressed B': non-empty row ids
   const uint32_t* brow_start = nullptr;  //   and their starts (plus terminal)
   const uint64_t* nzr_b = nullptr;       //   device count of non-empty rows
+  const uint32_t* bkt = nullptr;         //   first of those rows in each bucket of 2^bshift ids (plus terminal)
+  int bshift = 0;
   const uint32_t* row_start = nullptr;   // non-empty rows of A': starts (plus terminal)
   const uint64_t* row_id = nullptr;      //   and ids (nullptr: row r of the list is row r of A')
   const uint64_t* nzr_a = nullptr;       //   device count

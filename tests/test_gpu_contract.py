@@ -268,6 +268,44 @@ def test_dense_rows_with_empty_rows(lco_lib, gpu_ctx, oracle_mod):
         t.destroy()
 
 
+@pytest.mark.parametrize("lc", [[0, 2], [2, 0]])
+def test_many_entry_rows_and_row_buckets(lco_lib, gpu_ctx, oracle_mod, lc):
+    """Rows of more than 64 entries (up to 700; their product counts are summed
+    by a whole wave), some of which select only empty rows of the other operand
+    and so have no products, in 300 rows (a ragged last wave).  The contracted
+    index has 2^20 values and few non-empty rows, so a doubly compressed operand
+    is located through buckets of row ids: clustered rows, rows at both ends of
+    the range, and absent rows looked up inside occupied buckets.  B has a
+    column of 150 entries, a many-entry row of the column-wise orientation."""
+    rng = np.random.default_rng(77)
+    m, k, n = 300, 1 << 20, 500
+    brows = np.unique(np.concatenate([np.arange(200), [k - 1, k - 2, k - 5000], rng.integers(0, k, 300)]))
+    bset = set(int(j) for j in brows)
+    cb = {(int(j), int(c)) for j in brows for c in rng.choice(n, 1 + int(j) % 3, replace=False)}
+    cb |= {(int(j), 7) for j in brows[:150]}
+    cb = np.array(sorted(cb), dtype=np.uint64)
+    vb = rng.integers(-4, 5, len(cb)).astype(np.float64)
+    vb[vb == 0] = 0.25
+    absent = [j for j in range(200, 2048)] + [k - 3, k - 4, k - 4999] + [int(j) for j in rng.integers(0, k, 3000)]
+    absent = np.array(sorted(set(absent) - bset), dtype=np.uint64)
+    a_rows = []
+    for i in range(m):
+        t = [1, 3, 64, 65, 100, 257, 700][i % 7]
+        if i % 13 == 5:  # every column selects an empty row of B
+            cols = rng.choice(absent, t, replace=False)
+        else:
+            h = t // 2
+            cols = np.concatenate([rng.choice(brows, t - h, replace=False), rng.choice(absent, h, replace=False)])
+        a_rows += [(i, int(c)) for c in cols]
+    ca = np.array(a_rows, dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], lc, exact=True)
+    for t in (ga, gb):
+        t.destroy()
+
+
 @pytest.mark.parametrize("lc", [[0, 1, 3, 4], [3, 4, 0, 1]])
 def test_wide_columns_every_algorithm(lco_lib, gpu_ctx, oracle_mod, lc):
     """Columns of the product beyond 2^32 (m' = 2^28 rows, n' = 2^34 columns):
