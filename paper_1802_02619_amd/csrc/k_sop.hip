@@ -76,11 +76,34 @@ __device__ __forceinline__ uint64_t relinearise(const FastDiv* div, const uint64
   return key;
 }
 
+// Products are expanded in tiles of kSopTile consecutive list positions.  Each
+// product needs its block c (the last non-empty block starting at or before
+// it): every non-empty block that starts inside the tile marks its first
+// position with its index relative to the tile's first block, and a running
+// maximum over the tile hands every position its block.  (Each wave scans a
+// quarter of the tile; the maxima of the quarters before it are added when a
+// position is read.)
+constexpr int kSopWaves = kSopThreads / kWave;
+constexpr int kSopQuarter = kSopTile / kSopWaves;  // positions scanned by one wave
+static_assert(kSopWaves == 4, "the running maximum is combined over four quarters");
+
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, kWave);
+    if (lane >= o) x = t > x ? t : x;
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kSopThreads) void sop_expand_kernel(SopArgs sa, uint64_t f, uint64_t* __restrict__ keys,
                                                                  double* __restrict__ vals) {
-  __shared__ uint64_t s_boff[kSopTile + 1];
+  __shared__ uint32_t s_blk[kSopTile];     // block of each position, relative to c0
+  __shared__ uint32_t s_pre[kSopWaves];    // largest block index of the quarters before each quarter
   __shared__ uint64_t s_c[2];
   const uint64_t nzc = *sa.nzc_a;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t tiles = (f + kSopTile - 1) / kSopTile;
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const uint64_t p0 = tile * kSopTile;
@@ -96,32 +119,34 @@ __global__ __launch_bounds__(kSopThreads) void sop_expand_kernel(SopArgs sa, uin
       }
       s_c[threadIdx.x] = lo;
     }
+    for (int i = threadIdx.x; i < kSopTile; i += kSopThreads) s_blk[i] = 0;
     __syncthreads();
     const uint64_t c0 = s_c[0], c1 = s_c[1];
-    const uint64_t ncs = c1 - c0 + 1;
-    const bool in_lds = ncs <= (uint64_t)kSopTile;
-    if (in_lds)
-      for (uint64_t i = threadIdx.x; i < ncs; i += kSopThreads) s_boff[i] = sa.boff[c0 + i];
+    // blocks c0+1..c1 start inside the tile (at p0+1..p1); empty ones share the
+    // start of the next non-empty block and mark nothing
+    for (uint64_t c = c0 + 1 + threadIdx.x; c <= c1; c += kSopThreads) {
+      const uint64_t b = sa.boff[c];
+      if (b < sa.boff[c + 1]) s_blk[b - p0] = (uint32_t)(c - c0);
+    }
     __syncthreads();
-    for (uint64_t p = p0 + threadIdx.x; p <= p1; p += kSopThreads) {
-      uint64_t c;
-      if (in_lds) {
-        uint64_t lo = 0, hi = ncs - 1;
-        while (lo < hi) {
-          const uint64_t mid = (lo + hi + 1) >> 1;
-          if (s_boff[mid] <= p) lo = mid;
-          else hi = mid - 1;
-        }
-        c = c0 + lo;
-      } else {
-        uint64_t lo = c0, hi = c1;
-        while (lo < hi) {
-          const uint64_t mid = (lo + hi + 1) >> 1;
-          if (sa.boff[mid] <= p) lo = mid;
-          else hi = mid - 1;
-        }
-        c = lo;
-      }
+    uint32_t carry = 0;
+    for (int k = 0; k < kSopQuarter; k += kWave) {
+      const int q = w * kSopQuarter + k + lane;
+      uint32_t x = s_blk[q];
+      x = wave_inclusive_max(x > carry ? x : carry);
+      s_blk[q] = x;
+      carry = __shfl(x, kWave - 1, kWave);
+    }
+    if (lane == 0) s_pre[w] = carry;
+    __syncthreads();
+    const uint32_t pre1 = s_pre[0], pre2 = s_pre[1] > pre1 ? s_pre[1] : pre1, pre3 = s_pre[2] > pre2 ? s_pre[2] : pre2;
+    const uint32_t span = (uint32_t)(p1 - p0);
+    for (uint32_t q = threadIdx.x; q <= span; q += kSopThreads) {
+      const uint32_t qv = q / kSopQuarter;
+      const uint32_t pre = qv == 0 ? 0u : (qv == 1 ? pre1 : (qv == 2 ? pre2 : pre3));
+      const uint32_t lb = s_blk[q] > pre ? s_blk[q] : pre;
+      const uint64_t c = c0 + lb;
+      const uint64_t p = p0 + q;
       const uint64_t local = p - sa.boff[c];
       const uint32_t mb = sa.match[c];
       const uint32_t bstart = sa.brow_start[mb];
