@@ -84,13 +84,42 @@ __global__ void seg_compact_kernel(const uint64_t* __restrict__ livs, int64_t n,
   }
 }
 
+// The pointer arrays below are filled from the entries: entry e owns the
+// pointer slots [lo, hi) of the rows (or buckets) from just after the previous
+// entry's row up to its own, and writes e into them.  A lane fills its own
+// slots when there are at most kFillLane of them; longer runs (clustered rows
+// leave long runs of empty rows) are written by the whole wave, so no lane
+// writes millions of slots alone.  Every lane of the wave must call this.
+constexpr uint64_t kFillLane = 256;
+__device__ __forceinline__ void fill_slots(uint32_t* __restrict__ out, bool active, uint64_t lo, uint64_t hi,
+                                           uint32_t v) {
+  const bool wide = active && hi - lo > kFillLane;
+  if (active && !wide)
+    for (uint64_t r = lo; r < hi; ++r) out[r] = v;
+  const int lane = lane_id();
+  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
+    const int src = __builtin_ctzll(m);
+    const uint64_t a = __shfl(lo, src, kWave), b = __shfl(hi, src, kWave);
+    const uint32_t x = __shfl(v, src, kWave);
+    for (uint64_t r = a + lane; r < b; r += kWave) out[r] = x;
+  }
+}
+
 // bptr[r] = first B' entry of row r, for r in [0, k'] (bptr[k'] = nnz_b).
 __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv ndiv, uint64_t kp,
                                  uint32_t* __restrict__ bptr) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t lo = e == 0 ? 0 : fd_div(ndiv, livs[e - 1]) + 1;
-    const uint64_t hi = e == n ? kp : fd_div(ndiv, livs[e]);
-    for (uint64_t r = lo; r <= hi; ++r) bptr[r] = (uint32_t)e;
+  const int lane = lane_id();
+  // whole waves step together (fill_slots)
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 <= n;
+       e0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = e0 + lane;
+    const bool valid = e <= n;
+    uint64_t lo = 0, hi = 0;
+    if (valid) {
+      lo = e == 0 ? 0 : fd_div(ndiv, livs[e - 1]) + 1;
+      hi = (e == n ? kp : fd_div(ndiv, livs[e])) + 1;
+    }
+    fill_slots(bptr, valid, lo, hi, (uint32_t)e);
   }
 }
 
@@ -101,11 +130,18 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
 __global__ void bucket_ptr_kernel(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ count, int64_t cap,
                                   int shift, uint64_t nb, uint32_t* __restrict__ bkt) {
   const int64_t n = (int64_t)*count;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n && i <= cap;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t lo = i == 0 ? 0 : (ids[i - 1] >> shift) + 1;
-    const uint64_t hi = i == n ? nb : ids[i] >> shift;
-    for (uint64_t b = lo; b <= hi; ++b) bkt[b] = (uint32_t)i;
+  const int64_t last = n < cap ? n : cap;
+  const int lane = lane_id();
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 <= last;
+       i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + lane;
+    const bool valid = i <= last;
+    uint64_t lo = 0, hi = 0;
+    if (valid) {
+      lo = i == 0 ? 0 : (ids[i - 1] >> shift) + 1;
+      hi = (i == n ? nb : ids[i] >> shift) + 1;
+    }
+    fill_slots(bkt, valid, lo, hi, (uint32_t)i);
   }
 }
 
@@ -136,19 +172,27 @@ __global__ void dense_rows_len_kernel(RowArgs ra, uint64_t mp, uint32_t* __restr
                                       uint64_t* __restrict__ zero4) {
   const int64_t n = ra.nnz_a;
   if (blockIdx.x == 0 && threadIdx.x < 4) zero4[threadIdx.x] = 0;  // the classification's counters
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n; e += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t hi = mp;
-    if (e < n) {
-      uint64_t j;
-      hi = fd_divmod(ra.kdiv, ra.a_livs[e], j);
-      uint32_t st, l;
-      b_row<DENSE>(ra, j, st, l);
-      len[e] = l;
-      bstart[e] = st;
+  const int lane = lane_id();
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 <= n;
+       e0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = e0 + lane;
+    const bool valid = e <= n;
+    uint64_t lo = 0, hi = 0;
+    if (valid) {
+      hi = mp;
+      if (e < n) {
+        uint64_t j;
+        hi = fd_divmod(ra.kdiv, ra.a_livs[e], j);
+        uint32_t st, l;
+        b_row<DENSE>(ra, j, st, l);
+        len[e] = l;
+        bstart[e] = st;
+      }
+      ++hi;
+      lo = e == 0 ? 0 : fd_div(ra.kdiv, ra.a_livs[e - 1]) + 1;
+      if (e == n) *count = mp;
     }
-    const uint64_t lo = e == 0 ? 0 : fd_div(ra.kdiv, ra.a_livs[e - 1]) + 1;
-    for (uint64_t r = lo; r <= hi; ++r) row_start[r] = (uint32_t)e;
-    if (e == n) *count = mp;
+    fill_slots(row_start, valid, lo, hi, (uint32_t)e);
   }
 }
 

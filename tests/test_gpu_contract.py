@@ -306,6 +306,35 @@ def test_many_entry_rows_and_row_buckets(lco_lib, gpu_ctx, oracle_mod, lc):
         t.destroy()
 
 
+@pytest.mark.parametrize("lc", [[0, 2], [2, 0]])
+def test_clustered_rows_long_pointer_runs(lco_lib, gpu_ctx, oracle_mod, lc):
+    """Rows clustered at both ends of their ranges leave runs of thousands of
+    empty rows between them, which whole waves write: B's rows are the first and
+    last 300 of 2^22 (about 4.2 million empty row pointers of a singly
+    compressed B', 1022 empty buckets in the index of a doubly compressed one),
+    and A's rows are the first and last 150 of 4096 with 2400 entries (its row
+    starts are taken over all 4096 rows)."""
+    rng = np.random.default_rng(91)
+    m, k, n = 4096, 1 << 22, 300
+    brows = np.concatenate([np.arange(300), np.arange(k - 300, k)])
+    cb = np.array(sorted({(int(j), int(c)) for j in brows for c in rng.choice(n, 1 + int(j) % 3, replace=False)}),
+                  dtype=np.uint64)
+    vb = rng.integers(-4, 5, len(cb)).astype(np.float64)
+    vb[vb == 0] = 0.5
+    arows = np.concatenate([np.arange(150), np.arange(m - 150, m)])
+    absent = rng.choice(np.arange(300, k - 300), 4000, replace=False)
+    ca = np.array([(int(i), int(c)) for i in arows
+                   for c in np.concatenate([rng.choice(brows, 5, replace=False), rng.choice(absent, 3, replace=False)])],
+                  dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    assert m <= 2 * len(ca)
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], lc, exact=True)
+    for t in (ga, gb):
+        t.destroy()
+
+
 @pytest.mark.parametrize("lc", [[0, 1, 3, 4], [3, 4, 0, 1]])
 def test_wide_columns_every_algorithm(lco_lib, gpu_ctx, oracle_mod, lc):
     """Columns of the product beyond 2^32 (m' = 2^28 rows, n' = 2^34 columns):
