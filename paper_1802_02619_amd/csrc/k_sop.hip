@@ -30,7 +30,7 @@ struct SopArgs {
   const uint64_t* brow_id;
   const uint32_t* brow_start;
   const uint64_t* nzr_b;
-  const uint32_t* match;
+  const uint2* bseg;  // per join block: first entry and length of the matching B row
   const uint64_t* boff;
   int simple;  // output LIV = i + m*j
   int nfa, nfb;
@@ -43,7 +43,7 @@ struct SopArgs {
 constexpr int kSopThreads = 256;
 constexpr int kSopTile = 4096;  // products per tile
 
-__global__ void sop_join_kernel(SopArgs sa, int64_t upper, uint64_t* __restrict__ blk, uint32_t* __restrict__ match) {
+__global__ void sop_join_kernel(SopArgs sa, int64_t upper, uint64_t* __restrict__ blk, uint2* __restrict__ bseg) {
   const uint64_t nzc = *sa.nzc_a, nzr = *sa.nzr_b;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < upper; c += (int64_t)gridDim.x * blockDim.x) {
     if ((uint64_t)c >= nzc) break;
@@ -55,13 +55,14 @@ __global__ void sop_join_kernel(SopArgs sa, int64_t upper, uint64_t* __restrict_
       else hi = mid;
     }
     uint64_t b = 0;
+    uint2 seg = make_uint2(0u, 0u);
     if (lo < nzr && sa.brow_id[lo] == l) {
       const uint64_t ca = sa.acol_start[c + 1] - sa.acol_start[c];
-      const uint64_t cb = sa.brow_start[lo + 1] - sa.brow_start[lo];
-      b = ca * cb;
+      seg = make_uint2(sa.brow_start[lo], sa.brow_start[lo + 1] - sa.brow_start[lo]);
+      b = ca * seg.y;
     }
     blk[c] = b;
-    match[c] = (uint32_t)lo;
+    bseg[c] = seg;
   }
 }
 
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(kSopThreads) void sop_expand_kernel(SopArgs sa, uin
       const uint64_t c = c0 + lb;
       const uint64_t p = p0 + q;
       const uint64_t local = p - sa.boff[c];
-      const uint32_t mb = sa.match[c];
-      const uint32_t bstart = sa.brow_start[mb];
-      const uint64_t cb = sa.brow_start[mb + 1] - bstart;
+      const uint2 seg = sa.bseg[c];
+      const uint32_t bstart = seg.x;
+      const uint64_t cb = seg.y;
       uint64_t ia, ib;
       if (local < (1ull << 32)) {
         ia = (uint32_t)local / (uint32_t)cb;
@@ -222,12 +223,12 @@ lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   sa.brow_start = brows.starts;
   sa.nzr_b = brows.count;
   uint64_t* blk = s.get<uint64_t>(na);
-  uint32_t* match = s.get<uint32_t>(na);
+  uint2* bseg = s.get<uint2>(na);
   uint64_t* boff = s.get<uint64_t>(na + 1);
   memset_async(ctx, blk, 0, na * sizeof(uint64_t));
-  LCO_LAUNCH(ctx, "sop_join", sop_join_kernel, grid_for(ctx, na, 256), 256, 0, sa, na, blk, match);
+  LCO_LAUNCH(ctx, "sop_join", sop_join_kernel, grid_for(ctx, na, 256), 256, 0, sa, na, blk, bseg);
   scan_u64(ctx, blk, boff, na, boff + na);
-  sa.match = match;
+  sa.bseg = bseg;
   sa.boff = boff;
   const uint64_t* rb[1] = {boff + na};
   const uint64_t f = readback(ctx, rb, 1)[0];
