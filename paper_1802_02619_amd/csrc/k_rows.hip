@@ -10,9 +10,10 @@
 // LIV = col + n'*row.  Each output entry sums its products in ascending order
 // of the contracted index starting from 0.0.
 //
-// Setup: the row pointers of B' (or its non-empty rows when doubly
-// compressed), the rows of A' (row starts, and ids unless every row is
-// listed), and for every A' entry its product count and B' row start.  When
+// Setup: the row pointers of B' (or, when doubly compressed, its non-empty
+// rows and a bucket index over their ids), the rows of A' (row starts, and ids
+// unless every row is listed), and for every A' entry its product count and B'
+// row start.  When
 // few rows of A' are empty, one pass over A' lists all m' rows and writes the
 // per-entry data; otherwise head flags, a scan and a compaction list the
 // non-empty rows.  Small products do the whole setup in one block.
