@@ -102,42 +102,79 @@ def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(coords, vals, nnz_c_total: int, frac_den: int = 32):
-    """The oracle (single thread) on a bounded sample of the same step."""
+def host_cpu():
+    """Model name and core counts of the host CPU (from /proc/cpuinfo and the OS)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count(), "cores_available": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(coords, vals, reps: int = 3, frac_den: int = 32):
+    """The oracle (single thread, pinned to one core) on a bounded sample of the same step.
+
+    Runs before any GPU work: the oracle's permutation of the whole operand, then its
+    std::map contraction of a seeded sample of 1/frac_den of the output rows (all of
+    their products), each the median of `reps` runs; the step time is the
+    permutation pro-rated to the sample's share of the operand plus the sampled
+    contraction."""
     import numpy as np
 
     import oracle
-    dims = [SIDE] * 6
-    o = oracle.create(dims, coords, vals)
-    t0 = time.perf_counter()
-    p_full = oracle.permute(o, PERM)
-    t_perm = time.perf_counter() - t0
-    rng = np.random.default_rng(1234)
-    rows = np.unique(rng.integers(0, SIDE**3, SIDE**3 // frac_den)).astype(np.uint64)
-    keep = np.isin(p_full.livs % np.uint64(SIDE**3), rows)
-    sub = oracle.Tensor(p_full.dims, p_full.livs[keep], p_full.vals[keep])
-    t0 = time.perf_counter()
-    c_sub = oracle.contract(sub, LA, p_full, LB, LC)
-    t_con = time.perf_counter() - t0
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        dims = [SIDE] * 6
+        o = oracle.create(dims, coords, vals)
+        t_perm = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            p_full = oracle.permute(o, PERM)
+            t_perm.append(time.perf_counter() - t0)
+        rng = np.random.default_rng(1234)
+        rows = np.unique(rng.integers(0, SIDE**3, SIDE**3 // frac_den)).astype(np.uint64)
+        keep = np.isin(p_full.livs % np.uint64(SIDE**3), rows)
+        sub = oracle.Tensor(p_full.dims, p_full.livs[keep], p_full.vals[keep])
+        t_con = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            c_sub = oracle.contract(sub, LA, p_full, LB, LC)
+            t_con.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, mask)
+    tp, tc = statistics.median(t_perm), statistics.median(t_con)
     share = sub.nnz / p_full.nnz
-    t_step = t_perm * share + t_con
+    t_step = tp * share + tc
+    cpu = host_cpu()
     return {
         "value": c_sub.nnz / t_step,
         "unit": "output nnz/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{rows.size} of {SIDE**3} output rows ({share:.4f} of the operand): oracle permutation of "
-                   f"the full operand ({t_perm:.2f} s, pro-rated to the sample's share) + std::map contraction "
-                   f"of the sampled rows ({t_con:.2f} s, {c_sub.nnz} output nnz); single thread"),
-        "seconds": t_perm + t_con,
+        "sample": (f"{rows.size} of {SIDE**3} output rows ({share:.4f} of the operand, seed 1234): oracle "
+                   f"permutation of the full operand (median {tp:.2f} s of {reps}, pro-rated to the sample's "
+                   f"share) + std::map contraction of the sampled rows (median {tc:.2f} s of {reps}, "
+                   f"{c_sub.nnz} output nnz); one thread pinned to core {core}"),
+        "seconds": sum(t_perm) + sum(t_con),
+        "reps": reps,
+        "pinned_core": core,
+        "host_cpu": cpu["model"],
+        "host_logical_cores": cpu["logical_cores"],
+        "host_cores_available": cpu["cores_available"],
     }, (rows, c_sub)
 
 
 def fd_compose_nnz(dim: int, s: int) -> int:
     """Non-zeros of the FD Laplacian composed with itself (Dirichlet), closed form."""
-    if dim == 2:
-        return s * s + 4 * s * (s - 1) + 4 * (s - 1) ** 2 + 4 * s * (s - 2)
-    return s**3 + 6 * s * s * (s - 1) + 12 * s * (s - 1) ** 2 + 6 * s * s * (s - 2)
+    from tests.fd_closed_form import fd_square_nnz
+    return fd_square_nnz(dim, s)
 
 
 def fd_labels(dim: int):
@@ -202,6 +239,12 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
         return torch.equal(x.livs(), y.livs()) and torch.equal(x.vals().view(torch.int64), y.vals().view(torch.int64))
 
     ok_bits = all(same(keep["plain"][i], keep["batched"][i]) for i in sample)
+    # every batched output, entry by entry, against the closed-form composed stencil (on the device)
+    from tests.fd_closed_form import fd_square_matches
+    t0 = time.perf_counter()
+    bad_vals = [i for i, ((dim, side), o) in enumerate(zip(inst, keep["batched"]))
+                if not fd_square_matches(torch, o.livs(), o.vals(), side, dim)]
+    t_check = time.perf_counter() - t0
     for name, outs in keep.items():  # keep only the sampled plain outputs
         for i, o in enumerate(outs):
             if name == "batched" or i not in sample:
@@ -217,6 +260,8 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
     planned = {"create_s": t_plan, "launches": plan.launches()}
     pouts = plan.outputs()
     ok_plan = all(same(ref[i], pouts[i]) for i in sample) and all(o.nnz == e for o, e in zip(pouts, expect))
+    ok_plan = ok_plan and all(fd_square_matches(torch, o.livs(), o.vals(), side, dim)
+                              for (dim, side), o in zip(inst, pouts))
     for mode in ("execute", "graph"):
         fn = plan.execute if mode == "execute" else plan.graph_launch
         fn()  # warm (the graph is captured on its first launch)
@@ -246,8 +291,10 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
         "speedup_batched_vs_plain": res["plain"] / res["batched"],
         "instances_batched": stats[0], "instances_per_call": stats[1],
         "nnz_closed_form_ok": bool(ok_nnz), "sampled_bit_identical": bool(ok_bits), "sampled": len(sample),
+        "values_closed_form_ok": not bad_vals, "values_checked": count, "values_closed_form_failures": bad_vals[:8],
+        "values_check_s": t_check,
         "reps": reps, "planned": planned,
-        "speedup_graph_vs_plain": res["plain"] / planned["graph_s"],
+        "speedup_numeric_replay_vs_plain_full": res["plain"] / planned["graph_s"],
     }
 
 
@@ -446,14 +493,18 @@ def small_leg(lco, ctx, torch, np, L, reps: int):
 def hyper_leg(lco, ctx, torch, np, L, reps: int):
     """The order-4 hyper-sparse Kronecker pair (2^16 per mode, 2^24 draws each, duplicates summed),
     contracted over (2,3)x(0,1): the outer-product (SOP) path with B permuted (2,3,0,1)."""
-    dev = torch.device("cuda", 0)
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(2) as ex:  # the seeded PCG64 recipe on the host, both operands at once
+        host = list(ex.map(lambda seed: L.kronecker_hypersparse(16, 1 << 24, seed), (1, 2)))
     ops = []
-    for seed in (1, 2):
-        co, va = L.kronecker_hypersparse_torch(16, 1 << 24, seed, dev)
-        ops.append(lco.lco_create(ctx, [1 << 16] * 4, co.reshape(-1).contiguous(), va,
+    for co, va in host:
+        idx = torch.from_numpy(co.view(np.int64).reshape(-1)).to("cuda:0")
+        ops.append(lco.lco_create(ctx, [1 << 16] * 4, idx, torch.from_numpy(va).to("cuda:0"),
                                   lco.LCO_COORDS | lco.LCO_SUM_DUPLICATES))
-        del co, va
+        del idx
+    del host
     A, B = ops
+    assert (A.nnz, B.nnz) == (16777201, 16777183), (A.nnz, B.nnz)
     la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
     plan = lco.lco_plan_info(ctx, A, la, B, lb, lc).as_dict()
     C = lco.lco_contract(ctx, A, la, B, lb, lc)  # warm-up
@@ -502,8 +553,9 @@ def hyper_leg(lco, ctx, torch, np, L, reps: int):
         C.destroy()
         alt[name] = {"ms": statistics.median(tt) * 1e3, "bit_identical_to_selected": bool(same)}
     ref.destroy()
-    out = {"workload": "hyper-sparse Kronecker pair, order 4, 2^16 per mode, 2^24 draws each (device generator, "
-                       "seeds 1/2), contracted over (2,3)x(0,1)",
+    assert n_out == 118827201, n_out
+    out = {"workload": "hyper-sparse Kronecker pair, order 4, 2^16 per mode, 2^24 draws each (PCG64 seeds 1/2, "
+                       "duplicates summed), contracted over (2,3)x(0,1)",
            "nnz_a": A.nnz, "nnz_b": B.nnz, "nnz_out": n_out, "algo": plan["algo_name"],
            "permute_b": plan["permute_b"], "ms": ms, "output_nnz_per_s": n_out / (ms * 1e-3), "reps": reps,
            "forced": alt,
@@ -757,7 +809,7 @@ def main():
     ap.add_argument("--rp-reps", type=int, default=3, help="repetitions per permutation in that leg (0: skip)")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the replayed request trace (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=3)
     ap.add_argument("--serve-stress", type=float, default=4.0,
@@ -783,6 +835,13 @@ def main():
     import lco_inputs as L
     import paper_1802_02619_amd as lco
 
+    only = args.copy_probe_only or args.app_only or args.calibrate or args.rp_only or args.hyper_only
+    coords = vals = cb = None
+    if not only:
+        coords, vals = L.fd_laplacian(SIDE, 3)
+        if not args.no_cpu_baseline:
+            # the oracle runs first, on one pinned core, before anything touches the GPU
+            cb, (rows, c_sub) = cpu_baseline(coords, vals)
     torch.cuda.set_device(0)
     if args.copy_probe_only:
         print(json.dumps({"copy_GBps": copy_ceiling(torch), "bytes_each_way": 1 << 30}), flush=True)
@@ -801,7 +860,6 @@ def main():
     if args.hyper_only:
         print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps))}), flush=True)
         return
-    coords, vals = L.fd_laplacian(SIDE, 3)
     idx_d = torch.from_numpy(coords.view(np.int64).reshape(-1).copy()).to("cuda:0")
     val_d = torch.from_numpy(vals).to("cuda:0")
     A = lco.lco_create(ctx, [SIDE] * 6, idx_d, val_d, lco.LCO_COORDS)
@@ -928,8 +986,7 @@ def main():
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers,
                                      args.serve_stress)
-    if not args.no_cpu_baseline:
-        cb, (rows, c_sub) = cpu_baseline(coords, vals, nnz_c)
+    if cb is not None:
         # the sampled rows of the GPU result must equal the oracle's
         P = lco.lco_permute(ctx, A, PERM)
         C = lco.lco_contract(ctx, P, LA, P, LB, LC)

@@ -108,15 +108,19 @@ def kronecker_hypersparse(bits: int, draws: int, seed: int, probs=KRON_PROBS):
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     cum = np.cumsum(np.asarray(probs, dtype=np.float64))
-    coords = np.zeros((draws, 4), dtype=np.uint64)
+    cols = [np.zeros(draws, dtype=np.uint64) for _ in range(4)]
+    q = np.empty(draws, dtype=np.uint8)
     for b in range(bits):
         for (m0, m1) in ((0, 1), (2, 3)):
             u = rng.random(draws)
-            q = np.searchsorted(cum, u, side="right").astype(np.uint64)
-            coords[:, m0] |= (q >> np.uint64(1)) << np.uint64(b)
-            coords[:, m1] |= (q & np.uint64(1)) << np.uint64(b)
+            # quadrant = how many cumulative probabilities are <= u (a right-sided search)
+            np.less_equal(cum[0], u, out=q, casting="unsafe")
+            for c in cum[1:]:
+                q += u >= c
+            cols[m0] |= (q >> 1).astype(np.uint64) << np.uint64(b)
+            cols[m1] |= (q & 1).astype(np.uint64) << np.uint64(b)
     vals = rng.uniform(-1.0, 1.0, draws)
-    return coords, vals
+    return np.ascontiguousarray(np.stack(cols, axis=1)), vals
 
 
 def rtensor(bits: int, draws: int, seed: int, first_extra_bits: int = 0, probs=RTENSOR_PROBS,

@@ -44,15 +44,27 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ off, int co
   return lo;
 }
 
+// Row pointers of every instance's B' (k' + 1 slots each, from x.koff).  Whole
+// waves step together, so that fill_slots can hand a long run of empty rows
+// (clustered rows of B') to the whole wave.
 __global__ void bt_dense_ptr_kernel(const BInst* __restrict__ in, const int64_t* __restrict__ boff, int count,
                                     int64_t total, uint32_t* __restrict__ bptr) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int i = find_inst(boff, count, g);
-    const BInst& x = in[i];
-    const int64_t e = g - x.boff;  // 0..nnz_b
-    const uint64_t lo = e == 0 ? 0 : fd_div(x.ndiv, x.b_livs[e - 1]) + 1;
-    const uint64_t hi = e == x.nnz_b ? x.kp : fd_div(x.ndiv, x.b_livs[e]);
-    for (uint64_t r = lo; r <= hi; ++r) bptr[x.koff + r] = (uint32_t)e;
+  const int lane = lane_id();
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; g0 < total;
+       g0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = g0 + lane;
+    const bool valid = g < total;
+    uint64_t lo = 0, hi = 0;
+    uint32_t e32 = 0;
+    if (valid) {
+      const int i = find_inst(boff, count, g);
+      const BInst& x = in[i];
+      const int64_t e = g - x.boff;  // 0..nnz_b
+      lo = (uint64_t)x.koff + (e == 0 ? 0 : fd_div(x.ndiv, x.b_livs[e - 1]) + 1);
+      hi = (uint64_t)x.koff + (e == x.nnz_b ? x.kp : fd_div(x.ndiv, x.b_livs[e])) + 1;
+      e32 = (uint32_t)e;
+    }
+    fill_slots(bptr, valid, lo, hi, e32);
   }
 }
 

@@ -85,26 +85,7 @@ __global__ void seg_compact_kernel(const uint64_t* __restrict__ livs, int64_t n,
   }
 }
 
-// The pointer arrays below are filled from the entries: entry e owns the
-// pointer slots [lo, hi) of the rows (or buckets) from just after the previous
-// entry's row up to its own, and writes e into them.  A lane fills its own
-// slots when there are at most kFillLane of them; longer runs (clustered rows
-// leave long runs of empty rows) are written by the whole wave, so no lane
-// writes millions of slots alone.  Every lane of the wave must call this.
-constexpr uint64_t kFillLane = 256;
-__device__ __forceinline__ void fill_slots(uint32_t* __restrict__ out, bool active, uint64_t lo, uint64_t hi,
-                                           uint32_t v) {
-  const bool wide = active && hi - lo > kFillLane;
-  if (active && !wide)
-    for (uint64_t r = lo; r < hi; ++r) out[r] = v;
-  const int lane = lane_id();
-  for (uint64_t m = __ballot(wide); m; m &= m - 1) {
-    const int src = __builtin_ctzll(m);
-    const uint64_t a = __shfl(lo, src, kWave), b = __shfl(hi, src, kWave);
-    const uint32_t x = __shfl(v, src, kWave);
-    for (uint64_t r = a + lane; r < b; r += kWave) out[r] = x;
-  }
-}
+// The pointer arrays below are filled from the entries (fill_slots, row_core.h).
 
 // bptr[r] = first B' entry of row r, for r in [0, k'] (bptr[k'] = nnz_b).
 __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv ndiv, uint64_t kp,

@@ -222,3 +222,122 @@ def test_batch_plan_rejects_outer_product_and_entrywise(lco_lib, gpu_ctx):
     assert e.value.code == 7
     for t in ops:
         t.destroy()
+
+
+def test_batch_clustered_rows_with_fd_instances(lco_lib, gpu_ctx, oracle_mod):
+    """A forced row-by-row (CSR) instance whose B' rows are the first and last 300
+    of 2^22 -- about 4.2 million empty row pointers, written by whole waves in the
+    batched pointer fill -- batched together with FD compositions: every output
+    equals the per-call product and the oracle bit for bit."""
+    rng = np.random.default_rng(92)
+    items, refs, keep = [], [], []
+    for side, dim in ((10, 2), (9, 3)):
+        c, v = L.fd_laplacian(side, dim)
+        g = gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v)
+        keep.append(g)
+        la, lb = list(range(2 * dim)), list(range(dim, 3 * dim))
+        lc = list(range(dim)) + list(range(2 * dim, 3 * dim))
+        items.append((g, la, g, lb, lc))
+        o = oracle_mod.create([side] * (2 * dim), c, v)
+        refs.append(oracle_mod.contract(o, la, o, lb, lc))
+    m, k, n = 512, 1 << 22, 40
+    brows = np.concatenate([np.arange(300), np.arange(k - 300, k)])
+    cb = np.array(sorted({(int(j), int(c)) for j in brows for c in rng.choice(n, 1 + int(j) % 3, replace=False)}),
+                  dtype=np.uint64)
+    vb = rng.uniform(-1, 1, len(cb))
+    ca = np.array(sorted({(int(i), int(j)) for i in range(m) for j in rng.choice(brows, 4, replace=False)}),
+                  dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    ga, gb = gpu_create(lco_lib, gpu_ctx, [m, k], ca, va), gpu_create(lco_lib, gpu_ctx, [k, n], cb, vb)
+    keep += [ga, gb]
+    items.append((ga, [0, 1], gb, [1, 2], [0, 2], lco_lib.ALGO_IDS["CSR"]))
+    refs.append(oracle_mod.contract(oracle_mod.create([m, k], ca, va), [0, 1], oracle_mod.create([k, n], cb, vb),
+                                    [1, 2], [0, 2]))
+    items.append(items[0])
+    refs.append(refs[0])
+    outs = lco_lib.lco_contract_batch(gpu_ctx, items)
+    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call}", flush=True)
+    assert batched == 4 and per_call == 0
+    for it, out, ref in zip(items, outs, refs):
+        single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
+        got, alone = np_of(out), np_of(single)
+        assert np.array_equal(got[1], alone[1]) and np.array_equal(got[2], alone[2])
+        assert np.array_equal(got[1], ref.livs) and np.array_equal(got[2], ref.vals.view(np.uint64))
+        single.destroy()
+    for out in outs:
+        out.destroy()
+    for t in keep:
+        t.destroy()
+
+
+@pytest.mark.slow
+def test_batch_several_chunks_closed_form_and_oracle(lco_lib, gpu_ctx, oracle_mod):
+    """A batch of 3-D and 2-D FD self-compositions with more than 2^26 A' entries in
+    total, so it runs in two chunks (each with its own row lists, pool and output
+    offsets): every output of every instance equals the closed-form composed
+    stencil (checked on the device), the instances on both sides of the chunk
+    boundary and the first and last instance equal the oracle bit for bit, and a
+    planned batch of the same instances (whose largest size bucket is also split
+    into two chunks) gives the same outputs."""
+    import torch
+    from fd_closed_form import fd_square_matches
+    chunk = 1 << 26
+    inst = [(3, 40)] + [(3, 64)] * 36 + [(3, 40)] * 3 + [(2, 40 + (i % 21)) for i in range(30)] + \
+        [(3, 64)] * 3 + [(3, 41)]
+    distinct = {}
+    for dim, side in sorted(set(inst)):
+        c, v = L.fd_laplacian(side, dim)
+        distinct[(dim, side)] = (gpu_create(lco_lib, gpu_ctx, [side] * (2 * dim), c, v), c, v)
+    ops = []
+    for dim, side in inst:  # every instance owns its operand
+        src = distinct[(dim, side)][0]
+        ops.append(lco_lib.lco_create(gpu_ctx, src.dims, src.livs(), src.vals(), lco_lib.LCO_SORTED))
+    items = []
+    for a, (dim, _) in zip(ops, inst):
+        items.append((a, list(range(2 * dim)), a, list(range(dim, 3 * dim)),
+                      list(range(dim)) + list(range(2 * dim, 3 * dim))))
+    # the chunks the library forms (instances in order, each chunk up to 2^26 A' entries)
+    bounds, acc = [], 0
+    for i, a in enumerate(ops):
+        if acc and acc + a.nnz > chunk:
+            bounds.append(i)
+            acc = 0
+        acc += a.nnz
+    assert len(bounds) == 1 and inst[bounds[0] - 1][0] == 2 and inst[bounds[0]][0] == 2, bounds
+    print(f"several-chunk batch: {len(items)} instances, {sum(a.nnz for a in ops)} entries, boundary {bounds}",
+          flush=True)
+    outs = lco_lib.lco_contract_batch(gpu_ctx, items)
+    assert lco_lib.lco_batch_stats(gpu_ctx) == (len(items), 0)
+    torch.cuda.synchronize()
+    for i, (out, (dim, side)) in enumerate(zip(outs, inst)):
+        assert fd_square_matches(torch, out.livs(), out.vals(), side, dim), (i, dim, side)
+    for i in sorted({0, len(items) - 1} | {b - 1 for b in bounds} | set(bounds)):
+        dim, side = inst[i]
+        _, c, v = distinct[(dim, side)]
+        o = oracle_mod.create([side] * (2 * dim), c, v)
+        ref = oracle_mod.contract(o, *items[i][1:2], o, *items[i][3:5])
+        got = np_of(outs[i])
+        print(f"oracle check of instance {i} ({dim}-D, side {side})", flush=True)
+        assert np.array_equal(got[1], ref.livs) and np.array_equal(got[2], ref.vals.view(np.uint64)), i
+    plan = lco_lib.BatchPlan(gpu_ctx, items)
+    try:
+        info = plan.launches()
+        print("plan launches", [(x["bucket"], x["instances"]) for x in info], flush=True)
+        assert sum(x["instances"] for x in info) == len(items)
+        assert any(x["bucket"] == 10 for x in info) and sum(1 for x in info if x["bucket"] == 10) >= 2
+        for i, p in enumerate(plan.outputs()):
+            assert torch.equal(p.livs(), outs[i].livs()), i
+            assert torch.equal(p.vals().view(torch.int64), outs[i].vals().view(torch.int64)), i
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        for i, p in enumerate(plan.outputs()):
+            assert torch.equal(p.vals().view(torch.int64), outs[i].vals().view(torch.int64)), i
+    finally:
+        plan.destroy()
+    for out in outs:
+        out.destroy()
+    for a in ops:
+        a.destroy()
+    for g, _, _ in distinct.values():
+        g.destroy()

@@ -256,6 +256,143 @@ def test_map_and_sort_modes_agree(oracle_mod):
     assert np.array_equal(m.absum, s.absum)
 
 
+# ---------------------------------------------------------------- real-valued contraction pins
+#
+# Every pin above uses small integer values, whose sums are exact in any float
+# format.  The pins below use uniform(-1, 1) FP64 values and compare the oracle
+# with references computed independently of it: an exactly rounded sum of each
+# output entry's products (math.fsum over a brute-force enumeration of the
+# products, Section 2's definition of the product), and a dense (or
+# scipy.sparse) matrix product of the matricised operands (Section 5.2).  The
+# bound is that of recursive summation: an entry with k products, each rounded
+# once and added one at a time from 0.0, is within (k + 1) * u * sum|terms|
+# of the exact sum (u = 2^-53).  An oracle that summed in float32, dropped or
+# doubled a term, flipped a sign or transposed an operand misses it by orders of
+# magnitude.
+U64 = 2.0 ** -53
+
+
+def brute_products(dims_a, ca, va, la, dims_b, cb, vb, lb, lc):
+    """Dictionary output-LIV -> list of products, by enumerating every pair of
+    entries that agree on the shared labels (plain Python loops)."""
+    dims_of = {}
+    for lab, d in zip(la, dims_a):
+        dims_of[lab] = int(d)
+    for lab, d in zip(lb, dims_b):
+        dims_of[lab] = int(d)
+    shared = [x for x in la if x in lb]
+    out = {}
+    for i in range(len(va)):
+        ka = {lab: int(ca[i][r]) for r, lab in enumerate(la)}
+        for j in range(len(vb)):
+            kb = {lab: int(cb[j][r]) for r, lab in enumerate(lb)}
+            if any(ka[x] != kb[x] for x in shared):
+                continue
+            coord = {**ka, **kb}
+            liv, w = 0, 1
+            for lab in lc:  # default order: the first output mode is the least significant
+                liv += coord[lab] * w
+                w *= dims_of[lab]
+            out.setdefault(liv, []).append(float(va[i]) * float(vb[j]))
+    return out
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_real_values_vs_exact_sums(oracle_mod, n):
+    """Random FP64 operands over every partial-permutation matching of two order-n
+    tensors (contracted pairs), two output orders: each output entry is within the
+    recursive-summation bound of the exactly rounded sum of its products, its
+    Σ|products| matches, and the pattern is the set of positions with a product."""
+    rng = np.random.default_rng(700 + n)
+    checked = 0
+    for mi, match in enumerate(matchings(n)):
+        dims_a = [int(x) for x in rng.integers(2, 6, n)]
+        dims_b = [int(x) for x in rng.integers(2, 6, n)]
+        for (ia, ib) in match:
+            dims_b[ib] = dims_a[ia]
+        ca, va = L.random_sparse(rng, dims_a, 40)
+        cb, vb = L.random_sparse(rng, dims_b, 40)
+        a = oracle_mod.create(dims_a, ca, va)
+        b = oracle_mod.create(dims_b, cb, vb)
+        la = list(range(n))
+        lb = [n + j for j in range(n)]
+        for (ia, ib) in match:
+            lb[ib] = la[ia]
+        matched_a = {ia for ia, _ in match}
+        matched_b = {ib for _, ib in match}
+        lc = [la[i] for i in range(n) if i not in matched_a] + [lb[j] for j in range(n) if j not in matched_b]
+        for order in ((lc, lc[::-1]) if len(lc) > 1 else (lc,)):
+            c = oracle_mod.contract(a, la, b, lb, order)
+            prods = brute_products(dims_a, ca, va, la, dims_b, cb, vb, lb, order)
+            assert sorted(prods) == [int(x) for x in c.livs], (match, order)
+            for liv, val, absum in zip(c.livs.tolist(), c.vals.tolist(), c.absum.tolist()):
+                terms = prods[int(liv)]
+                exact = math.fsum(terms)
+                mag = math.fsum(abs(t) for t in terms)
+                bound = (len(terms) + 1) * U64 * mag
+                assert abs(val - exact) <= bound, (match, order, liv, val, exact)
+                assert abs(absum - mag) <= bound
+                checked += 1
+    assert checked > (150 if n == 2 else 1000)
+
+
+@pytest.mark.parametrize("bits", [4, 5, 6])
+def test_kronecker_pairs_real_values_vs_matrix_product(oracle_mod, bits):
+    """Scaled-down instances of the hyper-sparse Kronecker pair (2^bits per mode,
+    2^(bits+6) draws each, seeds 1 and 2, duplicates summed, uniform(-1, 1)
+    values), contracted over modes (3,4) x (1,2): the matricised product A @ B
+    computed by scipy.sparse in FP64, with |A| @ |B| as the magnitude of each
+    entry's terms; values within 1e-12 of that magnitude (the gate of the GPU
+    parity tests), the structural pattern exact, and the entries with the most
+    products within the recursive-summation bound of math.fsum."""
+    import scipy.sparse as sp
+    side = 1 << bits
+    n2 = side * side
+    draws = 1 << (bits + 6)
+    ops = []
+    for seed in (1, 2):
+        co, va = L.kronecker_hypersparse(bits, draws, seed)
+        ops.append((co, va, oracle_mod.create([side] * 4, co, va, sum_duplicates=True)))
+    (ca, va, a), (cb, vb, b) = ops
+    c = oracle_mod.contract(a, [0, 1, 2, 3], b, [2, 3, 4, 5], [0, 1, 4, 5])
+    # matricise from the raw coordinates (duplicates summed by the sparse constructor)
+    ra = ca[:, 0].astype(np.int64) + side * ca[:, 1].astype(np.int64)
+    ka = ca[:, 2].astype(np.int64) + side * ca[:, 3].astype(np.int64)
+    kb = cb[:, 0].astype(np.int64) + side * cb[:, 1].astype(np.int64)
+    nb = cb[:, 2].astype(np.int64) + side * cb[:, 3].astype(np.int64)
+    MA = sp.csr_matrix((va, (ra, ka)), shape=(n2, n2))
+    MB = sp.csr_matrix((vb, (kb, nb)), shape=(n2, n2))
+    MA.sum_duplicates()
+    MB.sum_duplicates()
+    ones_a = sp.csr_matrix((np.ones(MA.nnz), MA.indices, MA.indptr), shape=MA.shape)
+    ones_b = sp.csr_matrix((np.ones(MB.nnz), MB.indices, MB.indptr), shape=MB.shape)
+    P = (ones_a @ ones_b).tocoo()          # structural pattern (count of products per entry)
+    C = (MA @ MB).tocsr()
+    M = (abs(MA) @ abs(MB)).tocsr()
+    livs = P.row.astype(np.uint64) + np.uint64(n2) * P.col.astype(np.uint64)
+    order = np.argsort(livs)
+    livs = livs[order]
+    rows, cols = P.row[order], P.col[order]
+    assert c.nnz == livs.size > 0
+    assert np.array_equal(c.livs, livs)
+    ref = np.asarray(C[rows, cols]).ravel()
+    mag = np.asarray(M[rows, cols]).ravel()
+    assert np.all(np.abs(c.vals - ref) <= 1e-12 * mag)
+    assert np.all(np.abs(c.absum - mag) <= 1e-12 * mag)
+    # exactly rounded sums of the entries with the most products
+    count = P.data[order]
+    top = np.argsort(-count, kind="stable")[:32]
+    dA, dB = MA.tolil(), MB.tocsc()
+    for t in top:
+        i, j = int(rows[t]), int(cols[t])
+        arow = dA.rows[i]
+        terms = [float(dA[i, kk]) * float(dB[kk, j]) for kk in arow if dB[kk, j] != 0]
+        assert len(terms) == int(count[t])
+        exact = math.fsum(terms)
+        bound = (len(terms) + 1) * U64 * math.fsum(abs(x) for x in terms)
+        assert abs(c.vals[t] - exact) <= bound
+
+
 def test_contract_errors(oracle_mod):
     a = oracle_mod.create([3, 4], np.array([[0, 0]], np.uint64), [1.0])
     b = oracle_mod.create([5, 2], np.array([[0, 0]], np.uint64), [1.0])
