@@ -102,6 +102,11 @@ def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def note(msg: str):
+    """One progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def host_cpu():
     """Model name and core counts of the host CPU (from /proc/cpuinfo and the OS)."""
     model = "unknown"
@@ -400,6 +405,7 @@ def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: fl
         res = {}
         for name, kw in (("served", dict(workers=workers, max_batch=256, plain=False)),
                          ("serial_plain", dict(workers=1, max_batch=1, plain=True))):
+            note(f"serving: {name} replay at x{scale:g} ({n} requests)")
             srv = lco.Server(0, **kw)
             try:
                 lat, nnz, bs, kept, bad, wall = replay(srv, scale)
@@ -819,6 +825,7 @@ def main():
     ap.add_argument("--app-only", action="store_true", help="run only the combinatorial Laplacian leg")
     ap.add_argument("--rp-only", action="store_true", help="run only the permutation-table leg")
     ap.add_argument("--hyper-only", action="store_true", help="run only the hyper-sparse (SOP) leg")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched leg")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the selector calibration sweeps (R-TENSORs, Sections 5.2.3-5.2.5)")
     ap.add_argument("--calibrate-reps", type=int, default=3)
@@ -835,12 +842,14 @@ def main():
     import lco_inputs as L
     import paper_1802_02619_amd as lco
 
-    only = args.copy_probe_only or args.app_only or args.calibrate or args.rp_only or args.hyper_only
+    only = (args.copy_probe_only or args.app_only or args.calibrate or args.rp_only or args.hyper_only or
+            args.batch_only)
     coords = vals = cb = None
     if not only:
         coords, vals = L.fd_laplacian(SIDE, 3)
         if not args.no_cpu_baseline:
             # the oracle runs first, on one pinned core, before anything touches the GPU
+            note("cpu baseline (oracle, one pinned core)")
             cb, (rows, c_sub) = cpu_baseline(coords, vals)
     torch.cuda.set_device(0)
     if args.copy_probe_only:
@@ -859,6 +868,10 @@ def main():
         return
     if args.hyper_only:
         print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps))}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": batched_leg(lco, ctx, torch, np, L, max(1, args.batch_count),
+                                                 max(1, args.batch_reps))}), flush=True)
         return
     idx_d = torch.from_numpy(coords.view(np.int64).reshape(-1).copy()).to("cuda:0")
     val_d = torch.from_numpy(vals).to("cuda:0")
@@ -973,17 +986,24 @@ def main():
         "kernels": kernels,
         "kernels_steps": prof_steps,
     }
+    note(f"main step done: {ms_per_step:.3f} ms/step")
     if args.small_reps > 0:
+        note("leg: small")
         out["small"] = small_leg(lco, ctx, torch, np, L, args.small_reps)
     if args.hyper_reps > 0:
+        note("leg: hyper_sparse")
         out["hyper_sparse"] = hyper_leg(lco, ctx, torch, np, L, args.hyper_reps)
     if args.app_reps > 0:
+        note("leg: laplacian")
         out["laplacian"] = app_leg(lco, ctx, torch, np, L, args.app_n, args.app_reps)
     if args.rp_reps > 0:
+        note("leg: rp_table")
         out["rp_table"] = rp_leg(lco, ctx, torch, np, L, args.rp_n, args.rp_reps)
     if args.batch_count > 0:
+        note("leg: batched")
         out["batched"] = batched_leg(lco, ctx, torch, np, L, args.batch_count, args.batch_reps)
     if args.serve_seconds > 0:
+        note("leg: serving")
         out["serving"] = serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers,
                                      args.serve_stress)
     if cb is not None:
