@@ -269,39 +269,52 @@ typedef struct {
 } lco_contract_desc;
 
 /* Batched products: outs[i] receives the product of descs[i], bit-identical to
- * what lco_contract returns for the same arguments.  Instances whose plan is
- * CSR/CSC/CSRNA/CSCNA (after any operand rearrangement), that have no
- * entrywise label and whose rows of A' each have at most 64 products run
- * together, every phase as one launch over all of them, with two stream
- * synchronisations for the whole batch; outputs of those instances share one
- * device allocation that is released with the last of them.  Other instances
- * (doubly compressed, outer product, entrywise, long rows) run through the
- * per-call path.  Errors are those of lco_contract; on error no
- * output handle survives. */
+ * what lco_contract returns for the same arguments (Section 5.2's three steps,
+ * applied per instance).  Instances whose plan is CSR/CSC/CSRNA/CSCNA (after
+ * any operand rearrangement) and that have no entrywise label are batched.
+ * Those whose rows of A' are listed densely (at most 2 nnz(A') + 64 rows and at
+ * most 2^20 of them, k' < 2^34) run in the persistent engine: one launch of a
+ * persistent grid computes every instance's multiplication datatype, symbolic
+ * counts and output offsets from a device work queue, one host synchronisation
+ * reads the output sizes, and a second persistent launch writes every
+ * instance's product.  The other batched instances run in chunks of at most
+ * 2^26 A' entries, one launch per phase.  Outputs of batched instances share
+ * device allocations that are released with the last of their tensors.  An
+ * instance with a row of more than 64 products or entries, and every
+ * instance that is not batched (doubly compressed, outer product, entrywise),
+ * runs through the per-call path.  Errors are those of lco_contract; on error
+ * no output handle survives. */
 lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs);
-/* How many instances of the last lco_contract_batch call ran batched / per call. */
-lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call);
+/* How many instances of the last lco_contract_batch call ran batched / per
+ * call, and how many of the batched ones ran in the persistent engine
+ * (`persistent` may be NULL). */
+lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call, int64_t* persistent);
 
-/* Planned batches.  lco_batch_plan_create does all the shape-dependent work of
- * a batch once -- operand and output rearrangements (kept as value gathers),
- * the multiplication datatypes, every row's shape and output offset -- and
- * allocates and computes the outputs.  lco_batch_plan_execute then recomputes
- * every output's values from the operands' current values: only numeric
- * launches on the context's stream, no allocation, no host synchronisation, so
- * it can be captured in a HIP graph; lco_batch_plan_graph_launch captures it
- * once into a graph owned by the plan and replays that graph.  The operands'
- * LIVs (sparsity patterns) must not change after planning; their values may.
+/* Planned batches.  lco_batch_plan_create does the shape-dependent host work
+ * of a batch once -- operand and output rearrangements (kept as value
+ * gathers), the output sizes and one device allocation holding every output --
+ * and computes the outputs.  lco_batch_plan_execute then recomputes the whole
+ * batch from the operands' current values: the value gathers and ONE launch of
+ * the persistent engine, which rebuilds every instance's multiplication
+ * datatype, counts its rows, places them and writes the products (the same
+ * offsets every time), with no allocation and no host synchronisation, so it
+ * can be captured in a HIP graph; lco_batch_plan_graph_launch captures it once
+ * into a graph owned by the plan and replays that graph.  The operands' LIVs
+ * (sparsity patterns) must not change after planning; their values may.
  *
- * While planning, an autotuner picks for every group of instances of similar
- * size (A' non-zeros within a factor of 4) the row-engine branch (accumulator
- * or sort-based, both of which sum every output in the same order, so the
- * result does not depend on the choice) and the launch width, by timing the
- * candidates on the group itself; choices are kept in the context and reused.
+ * While planning, an autotuner picks for every size bucket (A' non-zeros
+ * within a factor of 4) the row-engine branch (accumulator or sort-based, both
+ * of which sum every output in the same order, so the result does not depend
+ * on the choice) and the number of 64-row chunks per work item of the
+ * persistent engine, by timing the candidates on the bucket's own instances;
+ * choices are kept in the context and reused by later plans and by
+ * lco_contract_batch.
  *
- * Only instances that the batched path runs completely (row-wise or
- * column-wise singly compressed products whose rows have at most 64 products)
- * can be planned; others give LCO_E_UNSUPPORTED.  The outputs belong to the
- * plan (lco_batch_plan_output returns borrowed handles, valid until
+ * Only instances that the persistent engine runs completely (row-wise or
+ * column-wise singly compressed products without entrywise labels, rows of A'
+ * listed densely, every row with at most 64 products and entries) can be
+ * planned; others give LCO_E_UNSUPPORTED.  The outputs belong to the plan
+ * (lco_batch_plan_output returns borrowed handles, valid until
  * lco_batch_plan_destroy). */
 typedef struct lco_batch_plan_s* lco_batch_plan;
 lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_batch_plan* out);
@@ -309,12 +322,13 @@ lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc
 lco_tensor lco_batch_plan_output(lco_batch_plan p, int i);
 lco_status lco_batch_plan_execute(lco_ctx ctx, lco_batch_plan p);
 lco_status lco_batch_plan_graph_launch(lco_ctx ctx, lco_batch_plan p);
-/* The i-th numeric launch of the plan: its size bucket (floor(log2(nnz of A'))/2),
- * instances, chosen branch (LCO_ALG_CSR = accumulator, LCO_ALG_CSRNA =
- * sort-based), blocks per compute unit, and the measured time of the choice
- * (0 when it came from an earlier plan).  LCO_E_ARG past the last launch. */
+/* The i-th size bucket of the plan: the bucket (floor(log2(nnz of A'))/2), its
+ * instances, the chosen branch (LCO_ALG_CSR = accumulator, LCO_ALG_CSRNA =
+ * sort-based), 64-row chunks per work item, and the measured time of the
+ * bucket's numeric phase with that choice (0 when it came from an earlier
+ * plan).  LCO_E_ARG past the last bucket. */
 lco_status lco_batch_plan_launch_info(lco_batch_plan p, int i, int* bucket, int* instances, int* algo,
-                                      int* blocks_per_cu, double* ms);
+                                      int* group, double* ms);
 lco_status lco_batch_plan_destroy(lco_batch_plan p);
 
 /* ------------------------------------------------------------------ serving

@@ -155,7 +155,7 @@ def load_library():
                                              ctypes.POINTER(ctypes.c_double)]),
             "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
             "lco_contract_batch": (i32, [vp, i32, ctypes.POINTER(ContractDesc), ctypes.POINTER(ctypes.c_void_p)]),
-            "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+            "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "lco_classify": (i32, [u64, u64, i64, ctypes.POINTER(i32)]),
             "lco_select": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "lco_plan_contract": (i32, [i32, pu64, pi32, i64, i32, pu64, pi32, i64, i32, pi32, u32,
@@ -453,7 +453,7 @@ class BatchPlan:
         _check(load_library().lco_batch_plan_graph_launch(self.ctx.handle, self.handle))
 
     def launches(self):
-        """Per numeric launch: size bucket, instances, branch, blocks per CU, tuned time (ms)."""
+        """Per size bucket: bucket, instances, branch, 64-row chunks per work item, tuned time (ms)."""
         L = load_library()
         out = []
         i = 0
@@ -465,7 +465,7 @@ class BatchPlan:
             if st != 0:
                 return out
             out.append({"bucket": b.value, "instances": n.value, "branch": ALGOS[a.value],
-                        "blocks_per_cu": g.value, "tuned_ms": ms.value})
+                        "chunks_per_item": g.value, "tuned_ms": ms.value})
             i += 1
 
     def destroy(self):
@@ -520,9 +520,10 @@ class Server:
 
 
 def lco_batch_stats(ctx: Context):
-    b, p = ctypes.c_int64(), ctypes.c_int64()
-    _check(load_library().lco_batch_stats(ctx.handle, ctypes.byref(b), ctypes.byref(p)))
-    return b.value, p.value
+    """(batched, per_call, persistent) instance counts of the last lco_contract_batch call."""
+    b, p, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().lco_batch_stats(ctx.handle, ctypes.byref(b), ctypes.byref(p), ctypes.byref(q)))
+    return b.value, p.value, q.value
 
 
 def lco_plan_info(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Plan:

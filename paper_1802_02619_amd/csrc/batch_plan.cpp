@@ -1,6 +1,9 @@
 // Planned batches: the shape-dependent work of a batch of contractions done
-// once, the numeric work re-run (and graph-captured) on demand, with an
-// autotuner for the row-engine branch and launch width of each size bucket.
+// once (operand rearrangements, output sizes, the output pool), then the whole
+// batch -- multiplication datatypes, symbolic counts, offsets and numeric
+// products of every instance -- re-run as one persistent launch, which a HIP
+// graph can capture.  An autotuner picks the row-engine branch and the work
+// item size of each size bucket.
 #include <algorithm>
 #include <map>
 
@@ -9,6 +12,7 @@
 namespace lco {
 lco_status set_error(const Error& e);
 lco_status set_error_msg(lco_status s, const char* msg);
+void persist_params(lco_ctx ctx, PJob& j, bool selector_acc);
 }  // namespace lco
 
 using namespace lco;
@@ -22,8 +26,8 @@ struct Gather {
   double* dst;
 };
 
-struct LaunchInfo {
-  int bucket = 0, instances = 0, algo = LCO_ALG_CSR, blocks_per_cu = 0;
+struct BucketInfo {
+  int bucket = 0, instances = 0, algo = LCO_ALG_CSR, group = 0;
   double ms = 0.0;
 };
 
@@ -34,15 +38,22 @@ struct lco_batch_plan_s {
   std::vector<lco_tensor> outs;   // the outputs (owned)
   std::vector<lco_tensor> owned;  // rearranged operands and outputs in the natural product order
   KeptBuffers keep;
-  std::vector<Gather> pre, post;  // value gathers before and after the numeric launches
-  std::vector<BatchLaunch> launches;
-  std::vector<LaunchInfo> info;
+  std::vector<Gather> pre, post;  // value gathers before and after the persistent launch
+  PersistBatch* pb = nullptr;
+  Pool* pool = nullptr;
+  uint64_t total = 0;
+  std::vector<BucketInfo> info;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
+
+uint64_t* pool_livs(lco_batch_plan P) { return P->pool ? (uint64_t*)P->pool->base : nullptr; }
+double* pool_vals(lco_batch_plan P) {
+  return P->pool ? (double*)((char*)P->pool->base + P->total * 8) : nullptr;
+}
 
 // `in` rearranged by `plan`, with the gather that refreshes its values: returns the
 // rearranged tensor (LIVs final) and appends dst[i] = src[idx[i]] to `gathers`.
@@ -63,19 +74,22 @@ lco_tensor permuted_with_gather(lco_batch_plan P, const lco_tensor_s* in, const 
   return t;
 }
 
-void run_numeric(lco_ctx ctx, lco_batch_plan P) {
+// The whole batch from the operands' current values: value gathers of the
+// rearranged operands, one persistent launch (every phase of every instance),
+// value gathers of the rearranged outputs.
+void run_all(lco_ctx ctx, lco_batch_plan P) {
   for (const Gather& g : P->pre) gather_values(ctx, g.src, g.idx, g.n, g.dst);
-  for (const BatchLaunch& L : P->launches) batch_numeric(ctx, L);
+  if (P->pb) P->pb->launch(0, 5, pool_livs(P), pool_vals(P), P->total);
   for (const Gather& g : P->post) gather_values(ctx, g.src, g.idx, g.n, g.dst);
 }
 
-double time_launch(lco_ctx ctx, const BatchLaunch& L) {
+double time_numeric(lco_ctx ctx, lco_batch_plan P) {
   hipEvent_t a, b;
   LCO_HIP(hipEventCreate(&a));
   LCO_HIP(hipEventCreate(&b));
-  batch_numeric(ctx, L);  // warm
+  P->pb->launch(5, 5, pool_livs(P), pool_vals(P), P->total);  // warm
   LCO_HIP(hipEventRecord(a, ctx->stream));
-  batch_numeric(ctx, L);
+  P->pb->launch(5, 5, pool_livs(P), pool_vals(P), P->total);
   LCO_HIP(hipEventRecord(b, ctx->stream));
   LCO_HIP(hipEventSynchronize(b));
   float ms = 0.f;
@@ -85,42 +99,56 @@ double time_launch(lco_ctx ctx, const BatchLaunch& L) {
   return ms;
 }
 
-// Autotuner: the branch and blocks per compute unit of one launch, timed on the launch itself.
-void tune_launch(lco_ctx ctx, BatchLaunch& L, int bucket, LaunchInfo& info) {
-  const int key = bucket * 2 + (L.acc ? 1 : 0);
-  auto it = ctx->tune.find(key);
-  if (it != ctx->tune.end()) {
-    L.acc = it->second.first != 0;
-    L.grid = batch_grid(ctx, L.rows, L.chunk_rows, it->second.second);
-    info.ms = 0.0;
-  } else {
-    const bool timer_was_on = ctx->timer.on;
-    ctx->timer.on = false;
-    double best = 1e30;
-    int best_acc = L.acc, best_bpc = 0;
-    for (int acc = 1; acc >= 0; --acc) {
-      for (int bpc : {4, 8, 16}) {
-        BatchLaunch c = L;
-        c.acc = acc != 0;
-        c.grid = batch_grid(ctx, L.rows, L.chunk_rows, bpc);
-        const double ms = time_launch(ctx, c);
-        if (ms < best) {
-          best = ms;
-          best_acc = acc;
-          best_bpc = bpc;
+// Autotuner: for each size bucket without a choice in the context, the branch
+// (accumulator or sort-based) and the 64-row chunks per work item, timed on
+// the numeric phase of the bucket's own instances.  Every candidate computes
+// the same values, so the outputs stay valid.
+void tune_buckets(lco_ctx ctx, lco_batch_plan P, std::vector<PJob>& jobs, const std::vector<bool>& sel_acc) {
+  std::map<int, std::vector<int>> buckets;
+  for (size_t i = 0; i < jobs.size(); ++i) buckets[jobs[i].bucket].push_back((int)i);
+  const bool timer_was_on = ctx->timer.on;
+  ctx->timer.on = false;
+  for (auto& kv : buckets) {
+    const std::vector<int>& idx = kv.second;
+    BucketInfo bi;
+    bi.bucket = kv.first;
+    bi.instances = (int)idx.size();
+    const int key = kv.first * 2 + (sel_acc[idx[0]] ? 1 : 0);
+    bool mixed = false;  // instances of one bucket whose selected branches differ keep their own choices
+    for (int i : idx) mixed = mixed || sel_acc[i] != sel_acc[idx[0]];
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end() && !mixed) {
+      std::vector<bool> active(jobs.size(), false);
+      for (int i : idx) active[i] = true;
+      double best = 1e30;
+      int best_acc = 1, best_group = 1;
+      for (int acc = 1; acc >= 0; --acc) {
+        for (int group : {1, 4, 16}) {
+          for (int i : idx) P->pb->set_params(i, acc != 0, group);
+          P->pb->upload_params();
+          P->pb->set_items(active);
+          const double ms = time_numeric(ctx, P);
+          if (ms < best) {
+            best = ms;
+            best_acc = acc;
+            best_group = group;
+          }
         }
       }
+      ctx->tune[key] = {best_acc, best_group};
+      bi.ms = best;
     }
-    ctx->timer.on = timer_was_on;
-    ctx->tune[key] = {best_acc, best_bpc};
-    L.acc = best_acc != 0;
-    L.grid = batch_grid(ctx, L.rows, L.chunk_rows, best_bpc);
-    info.ms = best;
+    for (int i : idx) {
+      persist_params(ctx, jobs[i], sel_acc[i]);
+      P->pb->set_params(i, jobs[i].acc, jobs[i].group);
+    }
+    bi.algo = jobs[idx[0]].acc ? LCO_ALG_CSR : LCO_ALG_CSRNA;
+    bi.group = jobs[idx[0]].group;
+    P->info.push_back(bi);
   }
-  info.algo = L.acc ? LCO_ALG_CSR : LCO_ALG_CSRNA;
-  info.blocks_per_cu = ctx->tune[key].second;
-  // the outputs hold this launch's results (every candidate computes the same values)
-  batch_numeric(ctx, L);
+  ctx->timer.on = timer_was_on;
+  P->pb->upload_params();
+  P->pb->set_items(std::vector<bool>(jobs.size(), true));
 }
 
 void destroy_plan(lco_batch_plan P) {
@@ -132,6 +160,8 @@ void destroy_plan(lco_batch_plan P) {
   for (lco_tensor t : P->outs)
     if (t) lco_destroy(t);
   for (lco_tensor t : P->owned) lco_destroy(t);
+  if (P->pool) release_pool(P->pool);
+  delete P->pb;
   P->keep.release();
   delete P;
 }
@@ -176,8 +206,8 @@ lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc
       rearranged[{t, key}] = r;
       return r;
     };
-    // jobs grouped by (branch, size bucket)
-    std::map<std::pair<int, int>, std::vector<BatchJob>> groups;
+    std::vector<PJob> jobs;
+    std::vector<bool> sel_acc;
     for (int i = 0; i < count; ++i) {
       const ContractDetail& d = plans[i];
       if (d.empty) {
@@ -188,43 +218,46 @@ lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc
       const bool rowwise = algo == LCO_ALG_CSR || algo == LCO_ALG_CSRNA;
       const lco_tensor_s* A = operand(descs[i].a, d.pub.permute_a, d.perm_a);
       const lco_tensor_s* B = operand(descs[i].b, d.pub.permute_b, d.perm_b);
-      BatchJob j;
+      PJob j{};
       j.index = i;
       j.A = rowwise ? A : B;
       j.B = rowwise ? B : A;
-      j.kp = d.pub.k;
-      j.np = rowwise ? d.pub.n : d.pub.m;
+      j.mp = d.em;
+      j.kp = d.ek;
+      j.np = d.en;
       j.order_c = d.order_c;
       for (int r = 0; r < d.order_c; ++r) j.natural_dims[r] = d.natural_dims[r];
+      if (!persist_eligible(j.mp, j.kp, j.A->nnz, j.B->nnz))
+        fail(LCO_E_UNSUPPORTED, "lco_batch_plan_create: instance " + std::to_string(i) +
+                                    " has mostly empty rows of A' or exceeds the batched engine's sizes");
       const bool acc = algo == LCO_ALG_CSR || algo == LCO_ALG_CSC;
-      const int bucket = bits_for((uint64_t)j.A->nnz) / 2;
-      groups[{bucket, acc ? 1 : 0}].push_back(j);
+      persist_params(ctx, j, acc);
+      jobs.push_back(j);
+      sel_acc.push_back(acc);
     }
     std::vector<lco_tensor> natural(count, nullptr);
-    for (auto& kv : groups) {
-      const std::vector<BatchJob>& jobs = kv.second;
-      size_t i = 0;
-      while (i < jobs.size()) {
-        std::vector<BatchJob> chunk;
-        int64_t entries = 0;
-        while (i < jobs.size() && (chunk.empty() || entries + jobs[i].A->nnz <= kBatchChunkEntries)) {
-          entries += jobs[i].A->nnz;
-          chunk.push_back(jobs[i++]);
-        }
-        BatchLaunch L;
-        const std::vector<int> redo = batch_group(ctx, chunk, kv.first.second != 0, natural.data(), &P->keep, &L);
-        for (const BatchJob& j : chunk)
-          if (natural[j.index]) P->owned.push_back(natural[j.index]);
-        if (!redo.empty())
-          fail(LCO_E_UNSUPPORTED, "lco_batch_plan_create: instance " + std::to_string(redo[0]) +
-                                      " has a row with more than 64 products");
-        LaunchInfo info;
-        info.bucket = kv.first.first;
-        info.instances = (int)chunk.size();
-        tune_launch(ctx, L, kv.first.first, info);
-        P->launches.push_back(L);
-        P->info.push_back(info);
+    if (!jobs.empty()) {
+      P->pb = new PersistBatch(ctx, jobs, nullptr, &P->keep);
+      P->pb->launch(0, 4, nullptr, nullptr, 0);
+      P->pb->read_sizes();
+      for (size_t i = 0; i < jobs.size(); ++i)
+        if (P->pb->fallback()[i])
+          fail(LCO_E_UNSUPPORTED, "lco_batch_plan_create: instance " + std::to_string(jobs[i].index) +
+                                      " has a row with more than 64 products or entries");
+      P->total = P->pb->total();
+      if (P->total) {
+        P->pool = new_pool(ctx, P->total * 16);
+        P->pb->launch(5, 5, pool_livs(P), pool_vals(P), P->total);
       }
+      for (size_t i = 0; i < jobs.size(); ++i) {
+        const PJob& j = jobs[i];
+        const uint64_t off = P->pb->offsets()[i], n = P->pb->sizes()[i];
+        natural[j.index] = n ? pool_tensor(ctx, P->pool, j.order_c, j.natural_dims, pool_livs(P) + off,
+                                           pool_vals(P) + off, (int64_t)n)
+                             : new_tensor(ctx, j.order_c, j.natural_dims, 0);
+        P->owned.push_back(natural[j.index]);
+      }
+      tune_buckets(ctx, P, jobs, sel_acc);
     }
     // outputs in the order of c_labels
     for (int i = 0; i < count; ++i) {
@@ -263,7 +296,7 @@ lco_status lco_batch_plan_execute(lco_ctx ctx, lco_batch_plan p) {
   if (!ctx || !p || p->ctx->device != ctx->device) return set_error_msg(LCO_E_ARG, "lco_batch_plan_execute: bad argument");
   try {
     LCO_HIP(hipSetDevice(ctx->device));
-    run_numeric(ctx, p);
+    run_all(ctx, p);
     return LCO_OK;
   } catch (const Error& e) {
     return set_error(e);
@@ -276,7 +309,7 @@ lco_status lco_batch_plan_graph_launch(lco_ctx ctx, lco_batch_plan p) {
   try {
     LCO_HIP(hipSetDevice(ctx->device));
     if (!p->exec) {
-      // capture the numeric launches once, on a stream of the plan's own
+      // capture the batch once, on a stream of the plan's own
       if (!p->cap) LCO_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
       hipStream_t saved = ctx->stream;
       const bool timer_was_on = ctx->timer.on;
@@ -285,7 +318,7 @@ lco_status lco_batch_plan_graph_launch(lco_ctx ctx, lco_batch_plan p) {
       hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         try {
-          run_numeric(ctx, p);
+          run_all(ctx, p);
         } catch (...) {
           hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(p->cap, &g);
@@ -308,15 +341,15 @@ lco_status lco_batch_plan_graph_launch(lco_ctx ctx, lco_batch_plan p) {
   }
 }
 
-lco_status lco_batch_plan_launch_info(lco_batch_plan p, int i, int* bucket, int* instances, int* algo,
-                                      int* blocks_per_cu, double* ms) {
-  if (!p || i < 0 || i >= (int)p->info.size() || !bucket || !instances || !algo || !blocks_per_cu || !ms)
+lco_status lco_batch_plan_launch_info(lco_batch_plan p, int i, int* bucket, int* instances, int* algo, int* group,
+                                      double* ms) {
+  if (!p || i < 0 || i >= (int)p->info.size() || !bucket || !instances || !algo || !group || !ms)
     return set_error_msg(LCO_E_ARG, "lco_batch_plan_launch_info: bad argument");
-  const LaunchInfo& x = p->info[i];
+  const BucketInfo& x = p->info[i];
   *bucket = x.bucket;
   *instances = x.instances;
   *algo = x.algo;
-  *blocks_per_cu = x.blocks_per_cu;
+  *group = x.group;
   *ms = x.ms;
   return LCO_OK;
 }

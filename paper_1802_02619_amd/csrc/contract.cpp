@@ -111,6 +111,62 @@ lco_status set_error_msg(lco_status s, const char* msg);
 
 using namespace lco;
 
+namespace lco {
+
+// Chunks per work item of the persistent engine when no tuned value is known.
+constexpr int kDefaultGroup = 4;
+
+// The persistent engine's choice for one instance: the tuned branch and chunks
+// per item of its size bucket, else the selector's branch.
+void persist_params(lco_ctx ctx, PJob& j, bool selector_acc) {
+  j.acc = selector_acc;
+  j.group = kDefaultGroup;
+  j.bucket = bits_for((uint64_t)j.A->nnz) / 2;
+  auto it = ctx->tune.find(j.bucket * 2 + (selector_acc ? 1 : 0));
+  if (it != ctx->tune.end()) {
+    j.acc = it->second.first != 0;
+    j.group = it->second.second;
+  }
+}
+
+// Runs jobs through the persistent engine: one launch sizes every output (setup,
+// symbolic count, scans), one host synchronisation reads the sizes, and one
+// launch writes every output into a shared pool.  Fills outs[job.index] and
+// returns the indices that need the per-call path.
+std::vector<int> persist_group(lco_ctx ctx, const std::vector<PJob>& jobs, lco_tensor* outs) {
+  std::vector<int> redo;
+  if (jobs.empty()) return redo;
+  Scratch s(ctx);
+  PersistBatch pb(ctx, jobs, &s, nullptr);
+  pb.launch(0, 4, nullptr, nullptr, 0);
+  pb.read_sizes();
+  const uint64_t total = pb.total();
+  if (total > ((uint64_t)1 << 40)) fail(LCO_E_OOM, "batch: output pool beyond 2^40 entries");
+  Pool* pool = total ? new_pool(ctx, total * 16) : nullptr;
+  uint64_t* pl = pool ? (uint64_t*)pool->base : nullptr;
+  double* pv = pool ? (double*)((char*)pool->base + total * 8) : nullptr;
+  try {
+    if (total) pb.launch(5, 5, pl, pv, total);
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      const PJob& j = jobs[i];
+      if (pb.fallback()[i]) {
+        redo.push_back(j.index);
+        continue;
+      }
+      const uint64_t off = pb.offsets()[i], n = pb.sizes()[i];
+      outs[j.index] = n ? pool_tensor(ctx, pool, j.order_c, j.natural_dims, pl + off, pv + off, (int64_t)n)
+                        : new_tensor(ctx, j.order_c, j.natural_dims, 0);
+    }
+  } catch (...) {
+    if (pool) release_pool(pool);
+    throw;
+  }
+  if (pool) release_pool(pool);  // the tensors hold the remaining references
+  return redo;
+}
+
+}  // namespace lco
+
 extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contract_desc* descs, lco_tensor* outs) {
   if (!ctx || count < 0 || (count && (!descs || !outs))) return set_error_msg(LCO_E_ARG, "lco_contract_batch: bad argument");
   for (int i = 0; i < count; ++i) outs[i] = nullptr;
@@ -127,6 +183,7 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
     }
     LCO_HIP(hipSetDevice(ctx->device));
     std::vector<BatchJob> acc_jobs, na_jobs;
+    std::vector<PJob> pjobs;
     std::vector<int> percall, batched;
     for (int i = 0; i < count; ++i) {
       const ContractDetail& d = plans[i];
@@ -151,19 +208,36 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
         temps.push_back(permuted(ctx, B, d.perm_b));
         B = temps.back();
       }
-      BatchJob j;
-      j.index = i;
-      j.A = rowwise ? A : B;
-      j.B = rowwise ? B : A;
-      j.kp = d.pub.k;
-      j.np = rowwise ? d.pub.n : d.pub.m;
-      j.order_c = d.order_c;
-      for (int r = 0; r < d.order_c; ++r) j.natural_dims[r] = d.natural_dims[r];
-      (algo == LCO_ALG_CSR || algo == LCO_ALG_CSC ? acc_jobs : na_jobs).push_back(j);
+      const bool acc = algo == LCO_ALG_CSR || algo == LCO_ALG_CSC;
+      const lco_tensor_s* Ap = rowwise ? A : B;
+      const lco_tensor_s* Bp = rowwise ? B : A;
+      if (persist_eligible(d.em, d.ek, Ap->nnz, Bp->nnz)) {
+        PJob j{};
+        j.index = i;
+        j.A = Ap;
+        j.B = Bp;
+        j.mp = d.em;
+        j.kp = d.ek;
+        j.np = d.en;
+        j.order_c = d.order_c;
+        for (int r = 0; r < d.order_c; ++r) j.natural_dims[r] = d.natural_dims[r];
+        persist_params(ctx, j, acc);
+        pjobs.push_back(j);
+      } else {
+        BatchJob j;
+        j.index = i;
+        j.A = Ap;
+        j.B = Bp;
+        j.kp = d.pub.k;
+        j.np = rowwise ? d.pub.n : d.pub.m;
+        j.order_c = d.order_c;
+        for (int r = 0; r < d.order_c; ++r) j.natural_dims[r] = d.natural_dims[r];
+        (acc ? acc_jobs : na_jobs).push_back(j);
+      }
       batched.push_back(i);
     }
-    // each group runs in chunks of bounded total entries (bounded scratch, 32-bit entry indices)
-    std::vector<int> redo;
+    std::vector<int> redo = persist_group(ctx, pjobs, outs);
+    // the rest (rows of A' listed sparsely) in chunks of bounded total entries
     auto run_chunks = [&](const std::vector<BatchJob>& jobs, bool acc) {
       size_t i = 0;
       while (i < jobs.size()) {
@@ -190,6 +264,7 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
     for (lco_tensor t : temps) lco_destroy(t);
     ctx->batch_stats[0] = (int64_t)batched.size() - (int64_t)redo.size();
     ctx->batch_stats[1] = (int64_t)percall.size();
+    ctx->batch_stats[2] = (int64_t)pjobs.size();
     return LCO_OK;
   } catch (const Error& e) {
     for (lco_tensor t : temps) lco_destroy(t);
@@ -208,9 +283,10 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
   }
 }
 
-extern "C" lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call) {
+extern "C" lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call, int64_t* persistent) {
   if (!ctx || !batched || !per_call) return set_error_msg(LCO_E_ARG, "lco_batch_stats: bad argument");
   *batched = ctx->batch_stats[0];
   *per_call = ctx->batch_stats[1];
+  if (persistent) *persistent = ctx->batch_stats[2];
   return LCO_OK;
 }

@@ -68,8 +68,9 @@ struct lco_ctx_s {
   uint64_t readback_seq = 0;       // last sequence number published in the buffer's flag word
   lco::Timer timer;
   uint32_t* dev_err = nullptr; // device word: set by a kernel that gave up a bounded wait
-  int64_t batch_stats[2] = {0, 0};  // last batch on this context: instances batched, run per call
-  // batch-plan autotuner: (size bucket, selected branch) -> (branch, blocks per CU)
+  int64_t batch_stats[3] = {0, 0, 0};  // last batch on this context: instances batched, run per call, of the
+                                     // batched those in the persistent engine
+  // batched-engine autotuner: (size bucket, selected branch) -> (branch, 64-row chunks per work item)
   std::map<int, std::pair<int, int>> tune;
   // selector crossovers: doubly compressed, no accumulator, outer product
   double cross[3] = {3.0, 3.0, 3.0};

@@ -107,6 +107,66 @@ void batch_numeric(lco_ctx ctx, const BatchLaunch& L);
 std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, bool acc, lco_tensor* outs,
                              KeptBuffers* keep = nullptr, BatchLaunch* launch = nullptr);
 
+// ---------------------------------------------------------------- persistent batched engine (k_persist.hip)
+
+// Rows of A' per instance up to which an instance runs in the persistent engine
+// (each instance's chunk counts are scanned by one wave).
+constexpr uint64_t kPersistMaxRows = uint64_t(1) << 20;
+
+// One instance of a persistent batch, in the row-engine roles.
+struct PJob {
+  int index;              // position in the caller's batch
+  const lco_tensor_s* A;  // A' (rows of the product)
+  const lco_tensor_s* B;  // B'
+  uint64_t mp, kp, np;    // rows of A', contracted size, columns of B'
+  bool acc;               // accumulator (CSR/CSC) or none (CSRNA/CSCNA)
+  int group;              // 64-row chunks per work item
+  int bucket;             // size bucket (autotuner key)
+  int order_c;
+  uint64_t natural_dims[LCO_MAX_ORDER];
+};
+// Rows of A' listed densely (few empty rows), sizes within the engine's limits.
+bool persist_eligible(uint64_t mp, uint64_t kp, int64_t nnz_a, int64_t nnz_b);
+
+// The device state of a persistent batch: descriptors, work-item tables and
+// the per-entry, per-row and per-chunk arrays of every instance (from `s`, or
+// kept in `keep` when the batch is re-run).  Launches enqueue on the context's
+// stream.
+class PersistBatch {
+ public:
+  PersistBatch(lco_ctx ctx, const std::vector<PJob>& jobs, Scratch* s, KeptBuffers* keep);
+  ~PersistBatch();
+  PersistBatch(const PersistBatch&) = delete;
+  PersistBatch& operator=(const PersistBatch&) = delete;
+  // Instances whose numeric phase the following launches run (all, after
+  // construction; phases 0-4 always cover every instance), and the work items
+  // of every phase from the current chunks-per-item choices.
+  void set_items(const std::vector<bool>& active);
+  // Branch and chunks per item of instance i; take effect after upload_params() and set_items().
+  void set_params(int i, bool acc, int group);
+  void upload_params();
+  // One reset and one persistent launch running phases [first, last] (0: setup ... 4: output
+  // offsets; 5: numeric into the pool of `capacity` entries at out_livs / out_vals).
+  void launch(int first, int last, uint64_t* out_livs, double* out_vals, uint64_t capacity);
+  // After a launch of phases 0-4: each instance's output size and pool offset, and
+  // whether it must take the per-call path (one host synchronisation).
+  void read_sizes();
+  const std::vector<uint64_t>& sizes() const { return sizes_; }
+  const std::vector<uint64_t>& offsets() const { return offsets_; }
+  const std::vector<uint32_t>& fallback() const { return fallback_; }
+  uint64_t total() const { return total_; }
+  int grid() const;
+
+ private:
+  struct Dev;
+  lco_ctx ctx_;
+  Dev* dev_;
+  std::vector<uint32_t> pre_;
+  std::vector<uint64_t> sizes_, offsets_;
+  std::vector<uint32_t> fallback_;
+  uint64_t total_ = 0;
+};
+
 // Simple outer product (Section 5.2.5) of A (column-major) and B (row-major).
 lco_tensor sop_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B, const ContractDetail& d);
 

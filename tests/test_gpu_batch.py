@@ -62,9 +62,10 @@ def test_batch_mixed_instances_equal_per_call(lco_lib, gpu_ctx, oracle_mod):
     refs.append(None)
 
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
-    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
-    print(f"batched={batched} per_call={per_call}", flush=True)
+    batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
     assert batched >= 6 and per_call >= 4  # FD compositions batch; long rows / DCSR / SOP fall back
+    assert persistent >= 7  # the FD compositions and the long-row instance (sent on to the per-call path)
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
@@ -111,9 +112,10 @@ def test_batch_mixed_column_widths(lco_lib, gpu_ctx, oracle_mod):
     refs.append(oracle_mod.contract(oracle_mod.create(da, ca, va), [0, 1, 2], oracle_mod.create(db, cb, vb),
                                     [2, 3, 4], [0, 1, 3, 4]))
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
-    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
-    print(f"batched={batched} per_call={per_call}", flush=True)
-    assert batched == 3 and per_call == 0
+    batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
+    # the wide instance's rows of A' are mostly empty: it runs in the chunked engine
+    assert batched == 3 and per_call == 0 and persistent == 2
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
@@ -143,7 +145,7 @@ def test_batch_many_small_fd(lco_lib, gpu_ctx, oracle_mod):
         sizes.append(s * s + 4 * s * (s - 1) + 4 * (s - 1) ** 2 + 4 * s * (s - 2) if dim == 2 else
                      s**3 + 6 * s * s * (s - 1) + 12 * s * (s - 1) ** 2 + 6 * s * s * (s - 2))
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
-    assert lco_lib.lco_batch_stats(gpu_ctx) == (200, 0)
+    assert lco_lib.lco_batch_stats(gpu_ctx) == (200, 0, 200)
     for it, out, n in zip(items, outs, sizes):
         assert out.nnz == n
     for k in (0, 57, 199):
@@ -256,9 +258,9 @@ def test_batch_clustered_rows_with_fd_instances(lco_lib, gpu_ctx, oracle_mod):
     items.append(items[0])
     refs.append(refs[0])
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
-    batched, per_call = lco_lib.lco_batch_stats(gpu_ctx)
-    print(f"batched={batched} per_call={per_call}", flush=True)
-    assert batched == 4 and per_call == 0
+    batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
+    print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
+    assert batched == 4 and per_call == 0 and persistent == 4
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
@@ -272,17 +274,16 @@ def test_batch_clustered_rows_with_fd_instances(lco_lib, gpu_ctx, oracle_mod):
 
 
 @pytest.mark.slow
-def test_batch_several_chunks_closed_form_and_oracle(lco_lib, gpu_ctx, oracle_mod):
-    """A batch of 3-D and 2-D FD self-compositions with more than 2^26 A' entries in
-    total, so it runs in two chunks (each with its own row lists, pool and output
-    offsets): every output of every instance equals the closed-form composed
-    stencil (checked on the device), the instances on both sides of the chunk
-    boundary and the first and last instance equal the oracle bit for bit, and a
-    planned batch of the same instances (whose largest size bucket is also split
-    into two chunks) gives the same outputs."""
+def test_batch_large_persistent_closed_form_and_oracle(lco_lib, gpu_ctx, oracle_mod):
+    """A batch of 3-D and 2-D FD self-compositions with more than 2^26 A' entries
+    in total (more than one chunk of the chunked engine holds), all in the
+    persistent engine: every output of every instance equals the closed-form
+    composed stencil (checked on the device); the first and last instance and
+    the instances holding each eighth of the rows (where the work queues of
+    the XCDs meet) equal the oracle bit for bit; a planned batch of the same
+    instances gives the same outputs, also after a graph replay."""
     import torch
     from fd_closed_form import fd_square_matches
-    chunk = 1 << 26
     inst = [(3, 40)] + [(3, 64)] * 36 + [(3, 40)] * 3 + [(2, 40 + (i % 21)) for i in range(30)] + \
         [(3, 64)] * 3 + [(3, 41)]
     distinct = {}
@@ -297,22 +298,18 @@ def test_batch_several_chunks_closed_form_and_oracle(lco_lib, gpu_ctx, oracle_mo
     for a, (dim, _) in zip(ops, inst):
         items.append((a, list(range(2 * dim)), a, list(range(dim, 3 * dim)),
                       list(range(dim)) + list(range(2 * dim, 3 * dim))))
-    # the chunks the library forms (instances in order, each chunk up to 2^26 A' entries)
-    bounds, acc = [], 0
-    for i, a in enumerate(ops):
-        if acc and acc + a.nnz > chunk:
-            bounds.append(i)
-            acc = 0
-        acc += a.nnz
-    assert len(bounds) == 1 and inst[bounds[0] - 1][0] == 2 and inst[bounds[0]][0] == 2, bounds
-    print(f"several-chunk batch: {len(items)} instances, {sum(a.nnz for a in ops)} entries, boundary {bounds}",
+    entries = sum(a.nnz for a in ops)
+    assert entries > 1 << 26
+    rows = np.cumsum([side ** dim for dim, side in inst])
+    eighths = sorted({int(np.searchsorted(rows, rows[-1] * q // 8, side="right")) for q in range(1, 8)})
+    print(f"large batch: {len(items)} instances, {entries} entries, queue splits in instances {eighths}",
           flush=True)
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
-    assert lco_lib.lco_batch_stats(gpu_ctx) == (len(items), 0)
+    assert lco_lib.lco_batch_stats(gpu_ctx) == (len(items), 0, len(items))
     torch.cuda.synchronize()
     for i, (out, (dim, side)) in enumerate(zip(outs, inst)):
         assert fd_square_matches(torch, out.livs(), out.vals(), side, dim), (i, dim, side)
-    for i in sorted({0, len(items) - 1} | {b - 1 for b in bounds} | set(bounds)):
+    for i in sorted({0, len(items) - 1} | set(eighths)):
         dim, side = inst[i]
         _, c, v = distinct[(dim, side)]
         o = oracle_mod.create([side] * (2 * dim), c, v)
@@ -323,16 +320,17 @@ def test_batch_several_chunks_closed_form_and_oracle(lco_lib, gpu_ctx, oracle_mo
     plan = lco_lib.BatchPlan(gpu_ctx, items)
     try:
         info = plan.launches()
-        print("plan launches", [(x["bucket"], x["instances"]) for x in info], flush=True)
+        print("plan buckets", [(x["bucket"], x["instances"], x["branch"], x["chunks_per_item"]) for x in info],
+              flush=True)
         assert sum(x["instances"] for x in info) == len(items)
-        assert any(x["bucket"] == 10 for x in info) and sum(1 for x in info if x["bucket"] == 10) >= 2
         for i, p in enumerate(plan.outputs()):
             assert torch.equal(p.livs(), outs[i].livs()), i
             assert torch.equal(p.vals().view(torch.int64), outs[i].vals().view(torch.int64)), i
-        plan.graph_launch()
-        torch.cuda.synchronize()
-        for i, p in enumerate(plan.outputs()):
-            assert torch.equal(p.vals().view(torch.int64), outs[i].vals().view(torch.int64)), i
+        for rep in range(2):
+            plan.graph_launch()
+            torch.cuda.synchronize()
+            for i, p in enumerate(plan.outputs()):
+                assert torch.equal(p.vals().view(torch.int64), outs[i].vals().view(torch.int64)), (rep, i)
     finally:
         plan.destroy()
     for out in outs:
