@@ -13,32 +13,46 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// Wave-wide scans and reductions on DPP lane moves (no LDS traffic, no lane
+// address registers).  row_shr:n moves each lane's value n lanes up within its
+// row of 16 (lanes with no source read 0); row_bcast:15 copies lane 15 of each
+// row into the next row and row_bcast:31 copies lane 31 into rows 2 and 3,
+// each only into the rows the row mask selects.  All 64 lanes must be active.
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, ZERO);
+}
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint64_t dpp_move(uint64_t x) {
+  return ((uint64_t)dpp_move<CTRL, ROWS, ZERO>((uint32_t)(x >> 32)) << 32) | dpp_move<CTRL, ROWS, ZERO>((uint32_t)x);
+}
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// Inclusive prefix sum over the wave (lane order): Hillis-Steele steps of 1,
+// 2, 4 and 8 lanes within each row, then the totals of rows 0 and 2 into rows
+// 1 and 3, then the total of rows 0-1 into rows 2 and 3.
 template <class T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    T t = __shfl_up(x, o, kWave);
-    if (lane >= o) x += t;
-  }
+  x += dpp_move<kDppRowShr + 1, 0xf, true>(x);
+  x += dpp_move<kDppRowShr + 2, 0xf, true>(x);
+  x += dpp_move<kDppRowShr + 4, 0xf, true>(x);
+  x += dpp_move<kDppRowShr + 8, 0xf, true>(x);
+  x += dpp_move<kDppRowBcast15, 0xa, false>(x);
+  x += dpp_move<kDppRowBcast31, 0xc, false>(x);
   return x;
 }
 
+__device__ __forceinline__ uint32_t lane_value(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ uint64_t lane_value(uint64_t x, int l) {
+  return ((uint64_t)lane_value((uint32_t)(x >> 32), l) << 32) | lane_value((uint32_t)x, l);
+}
+
+// Sum over the wave, returned to every lane.
 template <class T>
 __device__ __forceinline__ T wave_reduce_sum(T x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
-template <class T>
-__device__ __forceinline__ T wave_reduce_max(T x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    T y = __shfl_xor(x, o, kWave);
-    x = y > x ? y : x;
-  }
-  return x;
+  return lane_value(wave_inclusive_scan(x), kWave - 1);
 }
 
 // Exclusive scan of one value per thread over the block; returns the block total

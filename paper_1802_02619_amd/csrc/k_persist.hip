@@ -38,8 +38,14 @@ namespace {
 constexpr int kPhases = 6;
 constexpr int64_t kSetupTile = 8192;  // entries per item of phases 0 and 1
 constexpr int kCtlStride = 32;         // control words sit 256 bytes apart
+// Work queues: kSubQueues per XCD, each holding a contiguous range of a
+// phase's items (so that the queue heads, one atomic per item taken, are
+// spread over many addresses).
+constexpr uint32_t kSubQueues = 8;
+constexpr uint32_t kQueues = kXcds * kSubQueues;
+static_assert(kQueues == (uint32_t)kWave, "one queue per lane in the search for leftover items");
 // control block: queue heads [phase][queue], done counts [phase], results
-constexpr int kCtlDone = kPhases * (int)kXcds;
+constexpr int kCtlDone = kPhases * (int)kQueues;
 constexpr int kCtlRes = kCtlDone + kPhases;
 constexpr int kCtlWords = (kCtlRes + 1) * kCtlStride;
 constexpr uint64_t kSpinLimit = 1ull << 24;  // polls of a completion count before giving up
@@ -87,7 +93,7 @@ struct PArgs {
 };
 
 __device__ __forceinline__ uint64_t* ctl_head(uint64_t* ctl, int p, uint32_t q) {
-  return ctl + (p * (int)kXcds + (int)q) * kCtlStride;
+  return ctl + (p * (int)kQueues + (int)q) * kCtlStride;
 }
 __device__ __forceinline__ uint64_t* ctl_done(uint64_t* ctl, int p) { return ctl + (kCtlDone + p) * kCtlStride; }
 __device__ __forceinline__ uint64_t* ctl_res(uint64_t* ctl) { return ctl + kCtlRes * kCtlStride; }
@@ -95,6 +101,18 @@ __device__ __forceinline__ uint64_t* ctl_res(uint64_t* ctl) { return ctl + kCtlR
 __device__ __forceinline__ uint64_t shfl0_u64(uint64_t x) {
   return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
          (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// An instance descriptor in scalar registers: every word is read by the wave
+// and made uniform, so that the fields need no vector registers.
+__device__ __forceinline__ PInst load_inst(const PInst* __restrict__ inst, int i) {
+  static_assert(sizeof(PInst) % 4 == 0, "PInst is read in 32-bit words");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(inst + i);
+  PInst x;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&x);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(PInst) / 4); ++k) dst[k] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[k]);
+  return x;
 }
 
 // Instance owning item k of a phase: the largest i < count with pre[i] <= k
@@ -116,19 +134,31 @@ __device__ __forceinline__ int find_owner(const uint32_t* __restrict__ pre, int 
 
 // ---------------------------------------------------------------- phases 0 and 1
 
+// Entries per lane and step of the setup phases: every load of a step is
+// issued before its stores, so a wave keeps several loads in flight.
+constexpr int kSetupUnroll = 4;
+
 // Row pointers of B' from B' entries [e_lo, e_hi) (entry nnz_b is the terminal).
 __device__ __forceinline__ void p_bptr(const PArgs& g, const PInst& x, int64_t e_lo, int64_t e_hi, int lane) {
   const int64_t n = x.nnz_b;
   uint32_t* bp = g.bptr + x.koff;
-  for (int64_t e0 = e_lo; e0 < e_hi; e0 += kWave) {
-    const int64_t e = e0 + lane;
-    const bool valid = e < e_hi;
-    uint64_t lo = 0, hi = 0;
-    if (valid) {
-      lo = e == 0 ? 0 : fd_div(x.ndiv, x.b_livs[e - 1]) + 1;
-      hi = (e == n ? x.kp : fd_div(x.ndiv, x.b_livs[e])) + 1;
+  const uint64_t* __restrict__ bl = x.b_livs;
+  for (int64_t e0 = e_lo; e0 < e_hi; e0 += kSetupUnroll * kWave) {
+    uint64_t lo[kSetupUnroll], hi[kSetupUnroll];
+    bool valid[kSetupUnroll];
+#pragma unroll
+    for (int u = 0; u < kSetupUnroll; ++u) {
+      const int64_t e = e0 + u * kWave + lane;
+      valid[u] = e < e_hi;
+      lo[u] = 0;
+      hi[u] = 0;
+      if (valid[u]) {
+        lo[u] = e == 0 ? 0 : fd_div(x.ndiv, bl[e - 1]) + 1;
+        hi[u] = (e == n ? x.kp : fd_div(x.ndiv, bl[e])) + 1;
+      }
     }
-    fill_slots(bp, valid, lo, hi, (uint32_t)e);
+#pragma unroll
+    for (int u = 0; u < kSetupUnroll; ++u) fill_slots(bp, valid[u], lo[u], hi[u], (uint32_t)(e0 + u * kWave + lane));
   }
 }
 
@@ -136,25 +166,44 @@ __device__ __forceinline__ void p_bptr(const PArgs& g, const PInst& x, int64_t e
 // row start and length, from A' entries [e_lo, e_hi) (entry nnz_a is the terminal).
 __device__ __forceinline__ void p_rows(const PArgs& g, const PInst& x, int64_t e_lo, int64_t e_hi, int lane) {
   const int64_t n = x.nnz_a;
-  const uint32_t* bp = g.bptr + x.koff;
+  const uint32_t* __restrict__ bp = g.bptr + x.koff;
+  const uint64_t* __restrict__ al = x.a_livs;
   uint32_t* rs = g.row_start + x.roff;
-  for (int64_t e0 = e_lo; e0 < e_hi; e0 += kWave) {
-    const int64_t e = e0 + lane;
-    const bool valid = e < e_hi;
-    uint64_t lo = 0, hi = 0;
-    if (valid) {
-      hi = x.mp;
-      if (e < n) {
-        uint64_t j;
-        hi = fd_divmod(x.kdiv, x.a_livs[e], j);
-        const uint32_t st = bp[j];
-        g.elen[x.eoff + e] = bp[j + 1] - st;
-        g.bstart[x.eoff + e] = st;
+  for (int64_t e0 = e_lo; e0 < e_hi; e0 += kSetupUnroll * kWave) {
+    uint64_t lo[kSetupUnroll], hi[kSetupUnroll], j[kSetupUnroll];
+    uint32_t st[kSetupUnroll], en[kSetupUnroll];
+    bool valid[kSetupUnroll];
+#pragma unroll
+    for (int u = 0; u < kSetupUnroll; ++u) {
+      const int64_t e = e0 + u * kWave + lane;
+      valid[u] = e < e_hi;
+      lo[u] = 0;
+      hi[u] = x.mp;
+      j[u] = 0;
+      if (valid[u]) {
+        if (e < n) hi[u] = fd_divmod(x.kdiv, al[e], j[u]);
+        lo[u] = e == 0 ? 0 : fd_div(x.kdiv, al[e - 1]) + 1;
       }
-      ++hi;
-      lo = e == 0 ? 0 : fd_div(x.kdiv, x.a_livs[e - 1]) + 1;
     }
-    fill_slots(rs, valid, lo, hi, (uint32_t)e);
+#pragma unroll
+    for (int u = 0; u < kSetupUnroll; ++u) {
+      const int64_t e = e0 + u * kWave + lane;
+      st[u] = 0;
+      en[u] = 0;
+      if (valid[u] && e < n) {
+        st[u] = bp[j[u]];
+        en[u] = bp[j[u] + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSetupUnroll; ++u) {
+      const int64_t e = e0 + u * kWave + lane;
+      if (valid[u] && e < n) {
+        g.elen[x.eoff + e] = en[u] - st[u];
+        g.bstart[x.eoff + e] = st[u];
+      }
+      fill_slots(rs, valid[u], lo[u], valid[u] ? hi[u] + 1 : 0, (uint32_t)e);
+    }
   }
 }
 
@@ -195,10 +244,15 @@ __device__ __forceinline__ void p_chunk(const PArgs& g, const PInst& x, int inst
     bool out = ne > (uint32_t)kWave;
     if (!out) {
       uint64_t f = 0, mx = 0;
-      for (uint32_t e = m_s0; e < m_s1; ++e) {
-        const uint64_t l = elen[e];
-        f += l;
-        mx = l > mx ? l : mx;
+      for (uint32_t e0 = m_s0; e0 < m_s1; e0 += 8) {
+        uint32_t l[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) l[k] = e0 + k < m_s1 ? elen[e0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          f += l[k];
+          mx = l[k] > mx ? l[k] : mx;
+        }
       }
       if (f > 0 && small_row(f, ne)) {
         uint32_t lw = 0;
@@ -283,8 +337,14 @@ __device__ __forceinline__ uint64_t wave_scan_counts(const uint32_t* __restrict_
 
 // MODE: bit 0 compiles phases 0-4 (setup, symbolic, scans), bit 1 phase 5 (numeric).
 constexpr int kModeSize = 1, kModeNumeric = 2, kModeAll = 3;
+// BRANCH: the numeric row code compiled in: the accumulator only, the
+// sort-based branch only, or both (chosen per instance).  Each is compiled
+// alone where the batch allows it, since the code of both together needs more
+// registers.  The symbolic count is the same for both branches, so phase 2
+// always counts with the accumulator.
+constexpr int kBranchNa = 0, kBranchAcc = 1, kBranchBoth = 2;
 
-template <bool NARROW, int MODE>
+template <bool NARROW, int MODE, int BRANCH>
 __device__ __forceinline__ void run_item(const PArgs& g, int p, uint64_t k, PLds& L, int lane) {
   if constexpr ((MODE & kModeSize) == 0) {
     if (p != 5) return;
@@ -312,15 +372,15 @@ __device__ __forceinline__ void run_item(const PArgs& g, int p, uint64_t k, PLds
   }
   if (p == 3) {
     const int i = (int)k;
-    const PInst& x = g.inst[i];
+    const PInst x = load_inst(g.inst, i);
     const uint64_t t = wave_scan_counts(g.chunk_sum + x.coff, g.chunk_off + x.coff, x.nchunks, lane);
     if (lane == 0) g.total[i] = g.fallback[i] ? 0 : t;
     return;
   }
   const int pi = p == 5 ? 3 : p;
   const uint32_t* pre = g.ipre + (size_t)pi * (g.count + 1);
-  const int i = find_owner(pre, g.count, (uint32_t)k);
-  const PInst& x = g.inst[i];
+  const int i = __builtin_amdgcn_readfirstlane(find_owner(pre, g.count, (uint32_t)k));
+  const PInst x = load_inst(g.inst, i);
   const uint64_t t = k - pre[i];
   if (p == 0) {
     const int64_t lo = (int64_t)t * kSetupTile, hi = lo + kSetupTile < x.nnz_b + 1 ? lo + kSetupTile : x.nnz_b + 1;
@@ -335,16 +395,13 @@ __device__ __forceinline__ void run_item(const PArgs& g, int p, uint64_t k, PLds
   const uint64_t c0 = t * x.group, c1 = c0 + x.group < x.nchunks ? c0 + x.group : (uint64_t)x.nchunks;
   if constexpr ((MODE & kModeNumeric) == 0) p = 2;
   if (p == 2) {
-    for (uint64_t c = c0; c < c1; ++c) {
-      if (x.acc) p_chunk<true, false, NARROW>(g, x, i, c, L.sym, lane);
-      else p_chunk<false, false, NARROW>(g, x, i, c, L.sym, lane);
-    }
+    for (uint64_t c = c0; c < c1; ++c) p_chunk<true, false, NARROW>(g, x, i, c, L.sym, lane);
     return;
   }
   // phase 5: instances sent to the per-call path, or a pool too small, write nothing
   if (g.fallback[i] || ctl_res(g.ctl)[2]) return;
   for (uint64_t c = c0; c < c1; ++c) {
-    if (x.acc) p_chunk<true, true, NARROW>(g, x, i, c, L.num, lane);
+    if (BRANCH == kBranchAcc || (BRANCH == kBranchBoth && x.acc)) p_chunk<true, true, NARROW>(g, x, i, c, L.num, lane);
     else p_chunk<false, true, NARROW>(g, x, i, c, L.num, lane);
   }
 }
@@ -370,29 +427,46 @@ __device__ __forceinline__ bool wait_phase(const PArgs& g, int p, int lane) {
   return ok != 0;
 }
 
-template <bool NARROW, int MODE>
-__global__ __launch_bounds__(kRowThreads, MODE == 1 ? 8 : 6) void bt_persist_kernel(PArgs g) {
+// The sizing launch is held to 8 waves per SIMD (64 VGPRs), the launches with
+// the numeric phase to 6 (80 VGPRs), the fastest bounds measured.
+template <bool NARROW, int MODE, int BRANCH>
+__global__ __launch_bounds__(kRowThreads, MODE == kModeSize ? 8 : 6) void bt_persist_kernel(
+    const PArgs* __restrict__ gp) {
+  // the arguments are read from device memory where they are used (scalar
+  // loads), rather than held in registers for the whole kernel
+  const PArgs& g = *gp;
   __shared__ PLds s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t home = blockIdx.x % kXcds;
+  // queue q = XCD * kSubQueues + sub holds the q-th of kQueues contiguous ranges of
+  // every phase's items; a wave drains its home queue, then takes leftovers,
+  // preferring the other queues of its own XCD
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t sub = ((blockIdx.x / kXcds) * kRowWaves + (uint32_t)w) % kSubQueues;
+  const uint32_t cand = ((xcd + (uint32_t)lane / kSubQueues) % kXcds) * kSubQueues + (sub + (uint32_t)lane) % kSubQueues;
   for (int p = g.first; p <= g.last; ++p) {
     if (p > g.first && !wait_phase(g, p - 1, lane)) return;
     if ((MODE & kModeNumeric) && p == 5) tab_clear(s_lds[w].num, lane);
     const uint64_t n = g.n[p];
     uint64_t did = 0;
-    for (uint32_t s = 0; s < kXcds; ++s) {
-      const uint32_t q = (home + s) % kXcds;
-      const uint64_t lo = n * q / kXcds, len = n * (q + 1) / kXcds - lo;
-      uint64_t* head = ctl_head(g.ctl, p, q);
-      while (true) {
-        uint64_t k = ~0ull;
-        if (lane == 0 && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
-          k = atomicAdd((unsigned long long*)head, 1ull);
-        k = shfl0_u64(k);
-        if (k >= len) break;
-        run_item<NARROW, MODE>(g, p, lo + k, s_lds[w], lane);
+    uint32_t cur = xcd * kSubQueues + sub;
+    for (;;) {
+      const uint64_t lo = n * cur / kQueues, len = n * (cur + 1) / kQueues - lo;
+      uint64_t* head = ctl_head(g.ctl, p, cur);
+      uint64_t k = ~0ull;
+      if (lane == 0 && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
+        k = atomicAdd((unsigned long long*)head, 1ull);
+      k = shfl0_u64(k);
+      if (k < len) {
+        run_item<NARROW, MODE, BRANCH>(g, p, lo + k, s_lds[w], lane);
         ++did;
+        continue;
       }
+      // this queue is drained: look for a queue with items left, one queue per lane
+      const uint64_t clo = n * cand / kQueues, clen = n * (cand + 1) / kQueues - clo;
+      const bool left = __hip_atomic_load(ctl_head(g.ctl, p, cand), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < clen;
+      const uint64_t m = __ballot(left);
+      if (!m) break;
+      cur = readlane_u32(cand, __builtin_ctzll(m));
     }
     if (did) {
       __threadfence();
@@ -401,25 +475,31 @@ __global__ __launch_bounds__(kRowThreads, MODE == 1 ? 8 : 6) void bt_persist_ker
   }
 }
 
-// Clears the control block and the fallback flags before a launch (a kernel,
-// so that the launch can be captured in a graph).
-__global__ void bt_persist_reset_kernel(uint64_t* __restrict__ ctl, uint32_t* __restrict__ fallback, int count,
-                                        bool clear_fallback) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kCtlWords; i += gridDim.x * blockDim.x) ctl[i] = 0;
+// Clears the control block and the fallback flags before a launch and stores
+// the launch's arguments where the persistent grid reads them (a kernel, so
+// that the launch can be captured in a graph).
+__global__ void bt_persist_reset_kernel(PArgs a, PArgs* __restrict__ dst, bool clear_fallback) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kCtlWords; i += gridDim.x * blockDim.x) a.ctl[i] = 0;
   if (clear_fallback)
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) fallback[i] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += gridDim.x * blockDim.x) a.fallback[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = a;
 }
 
-using PersistKernel = void (*)(PArgs);
-PersistKernel persist_kernel(bool narrow, int mode) {
-  if (narrow) {
-    if (mode == kModeSize) return bt_persist_kernel<true, kModeSize>;
-    if (mode == kModeNumeric) return bt_persist_kernel<true, kModeNumeric>;
-    return bt_persist_kernel<true, kModeAll>;
+using PersistKernel = void (*)(const PArgs*);
+template <bool NARROW>
+PersistKernel persist_kernel_w(int mode, int branch) {
+  if (mode == kModeSize) return bt_persist_kernel<NARROW, kModeSize, kBranchAcc>;
+  if (mode == kModeNumeric) {
+    if (branch == kBranchAcc) return bt_persist_kernel<NARROW, kModeNumeric, kBranchAcc>;
+    if (branch == kBranchNa) return bt_persist_kernel<NARROW, kModeNumeric, kBranchNa>;
+    return bt_persist_kernel<NARROW, kModeNumeric, kBranchBoth>;
   }
-  if (mode == kModeSize) return bt_persist_kernel<false, kModeSize>;
-  if (mode == kModeNumeric) return bt_persist_kernel<false, kModeNumeric>;
-  return bt_persist_kernel<false, kModeAll>;
+  if (branch == kBranchAcc) return bt_persist_kernel<NARROW, kModeAll, kBranchAcc>;
+  if (branch == kBranchNa) return bt_persist_kernel<NARROW, kModeAll, kBranchNa>;
+  return bt_persist_kernel<NARROW, kModeAll, kBranchBoth>;
+}
+PersistKernel persist_kernel(bool narrow, int mode, int branch) {
+  return narrow ? persist_kernel_w<true>(mode, branch) : persist_kernel_w<false>(mode, branch);
 }
 
 template <class T>
@@ -438,10 +518,12 @@ struct PersistBatch::Dev {
   std::vector<PInst> host;
   PInst* inst = nullptr;
   uint32_t* ipre = nullptr;
+  PArgs* dargs = nullptr;  // the current launch's arguments on the device
   PArgs a{};
   uint64_t items[kPhases] = {};
   bool narrow = true;
-  int grid[4] = {0, 0, 0, 0};  // by mode: blocks that fill every compute unit
+  int grid[4][3] = {};  // by mode and branch: blocks that fill every compute unit
+  std::vector<bool> active;  // instances whose numeric phase the launches run
 };
 
 PersistBatch::PersistBatch(lco_ctx ctx, const std::vector<PJob>& jobs, Scratch* s, KeptBuffers* keep)
@@ -482,6 +564,7 @@ PersistBatch::PersistBatch(lco_ctx ctx, const std::vector<PJob>& jobs, Scratch* 
   a.count = count;
   D.inst = take<PInst>(ctx, s, keep, count);
   D.ipre = take<uint32_t>(ctx, s, keep, 4 * (size_t)(count + 1));
+  D.dargs = take<PArgs>(ctx, s, keep, 1);
   a.inst = D.inst;
   a.ipre = D.ipre;
   a.bptr = take<uint32_t>(ctx, s, keep, K);
@@ -499,18 +582,20 @@ PersistBatch::PersistBatch(lco_ctx ctx, const std::vector<PJob>& jobs, Scratch* 
   a.err = ctx->dev_err;
   upload_params();
   for (int mode : {kModeSize, kModeNumeric, kModeAll}) {
-    int bpc = 0;
-    LCO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, (const void*)persist_kernel(D.narrow, mode),
-                                                         kRowThreads, 0));
-    const int g = ctx->num_cus * std::max(1, bpc);
-    D.grid[mode] = (g + (int)kXcds - 1) / (int)kXcds * (int)kXcds;
+    for (int branch : {kBranchNa, kBranchAcc, kBranchBoth}) {
+      int bpc = 0;
+      LCO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &bpc, (const void*)persist_kernel(D.narrow, mode, branch), kRowThreads, 0));
+      const int g = ctx->num_cus * std::max(1, bpc);
+      D.grid[mode][branch] = (g + (int)kXcds - 1) / (int)kXcds * (int)kXcds;
+    }
   }
   set_items(std::vector<bool>(count, true));
 }
 
 PersistBatch::~PersistBatch() { delete dev_; }
 
-int PersistBatch::grid() const { return dev_->grid[kModeAll]; }
+int PersistBatch::grid() const { return dev_->grid[kModeAll][kBranchAcc]; }
 
 void PersistBatch::set_items(const std::vector<bool>& active) {
   Dev& D = *dev_;
@@ -533,6 +618,7 @@ void PersistBatch::set_items(const std::vector<bool>& active) {
   }
   D.items[3] = (uint64_t)count;
   D.items[4] = 1;
+  D.active = active;
   LCO_HIP(hipMemcpyAsync(D.ipre, pre.data(), sizeof(uint32_t) * pre.size(), hipMemcpyHostToDevice, ctx_->stream));
   pre_.swap(pre);
 }
@@ -558,17 +644,25 @@ void PersistBatch::launch(int first, int last, uint64_t* out_livs, double* out_v
   a.out_livs = out_livs;
   a.out_vals = out_vals;
   a.capacity = capacity;
-  LCO_LAUNCH(ctx_, "bt_persist_reset", bt_persist_reset_kernel, 1, 256, 0, a.ctl, a.fallback, a.count, first == 0);
+  LCO_LAUNCH(ctx_, "bt_persist_reset", bt_persist_reset_kernel, 1, 256, 0, a, D.dargs, first == 0);
   if (first < 0 || last > 5 || first > last || (first != 0 && first != 5) || (first == 0 && last < 4))
     fail(LCO_E_ARG, "batch: a persistent launch runs phases 0-4, 5 alone, or 0-5");
   const int mode = first == 5 ? kModeNumeric : last == 5 ? kModeAll : kModeSize;
   const char* name = mode == kModeSize ? "bt_persist_size" : mode == kModeNumeric ? "bt_persist_num" : "bt_persist";
+  // the numeric branches the launch needs: those of the instances whose numeric phase it runs
+  bool any_acc = false, any_na = false;
+  for (size_t i = 0; i < D.host.size(); ++i) {
+    if (!D.active[i]) continue;
+    any_acc = any_acc || D.host[i].acc;
+    any_na = any_na || !D.host[i].acc;
+  }
+  const int branch = mode == kModeSize ? kBranchAcc : any_acc && any_na ? kBranchBoth : any_na ? kBranchNa : kBranchAcc;
   // no more blocks than the largest phase has items for their waves (small batches), at least one per XCD
   uint64_t most = 1;
   for (int p = first; p <= last; ++p) most = std::max<uint64_t>(most, a.n[p]);
   const uint64_t want = (most + kRowWaves - 1) / kRowWaves;
-  const int grid = (int)std::min<uint64_t>((uint64_t)D.grid[mode], (want + kXcds - 1) / kXcds * kXcds);
-  LCO_LAUNCH(ctx_, name, persist_kernel(D.narrow, mode), grid, kRowThreads, 0, a);
+  const int grid = (int)std::min<uint64_t>((uint64_t)D.grid[mode][branch], (want + kXcds - 1) / kXcds * kXcds);
+  LCO_LAUNCH(ctx_, name, persist_kernel(D.narrow, mode, branch), grid, kRowThreads, 0, (const PArgs*)D.dargs);
 }
 
 void PersistBatch::read_sizes() {

@@ -99,7 +99,8 @@ void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
     Request* r = batch[i];
     st[i] = lco_contract(ctx, r->a, r->la.data(), r->b, r->lb.data(), r->c_order, r->lc.data(), r->flags, &outs[i]);
   };
-  if (s->cfg.plain) {
+  if (s->cfg.plain || n == 1) {
+    // a batch of one takes the per-call path, which is the faster one for a single product
     for (int i = 0; i < n; ++i) alone(i);
   } else {
     std::vector<lco_contract_desc> d(n);
