@@ -181,6 +181,24 @@ const double* lco_vals(lco_tensor t);
  * Errors: LCO_E_ARG (not a permutation), LCO_E_OOM. */
 lco_status lco_permute(lco_ctx ctx, lco_tensor in, const int* perm, lco_tensor* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * lco_permute that writes into caller-owned device arrays and takes every
+ * temporary buffer from a fixed workspace of LCO_NOALLOC_SCRATCH_BYTES inside
+ * the library (one per device, set up by lco_ctx_create on that device and
+ * held until the process ends).  out_livs / out_vals: device arrays of
+ * in->nnz entries each (unused when nnz is 0) that receive the permuted
+ * tensor in its default order; out_dims: host array of `order` entries that
+ * receives dims[perm[r]].  The result equals lco_permute's bit for bit.  Calls
+ * that overlap on one device (several streams or threads) race on the shared
+ * workspace; the workspace keeps the last call's contents, and every call
+ * clears what it needs.  Errors: those of lco_permute, and
+ * LCO_E_UNSUPPORTED when nnz exceeds LCO_NOALLOC_MAX_NNZ. */
+#define LCO_NOALLOC_MAX_NNZ (1 << 20)
+#define LCO_NOALLOC_SCRATCH_BYTES (24u << 20)
+lco_status lco_permute_noalloc(lco_ctx ctx, lco_tensor in, const int* perm, uint64_t* out_livs, double* out_vals,
+                               uint64_t* out_dims);
+
 /* -------------------------------------------------------------- contraction */
 
 /* Sparsity classes of a matricised operand (Section 5.1): a dimension is

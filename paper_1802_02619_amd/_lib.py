@@ -16,6 +16,7 @@ import threading
 __all__ = [
     "LcoError", "Context", "Tensor", "Plan", "RpPlan", "load_library", "library_path",
     "lco_ctx_create", "lco_ctx_destroy", "lco_ctx_synchronize", "lco_create", "lco_destroy", "lco_permute",
+    "lco_permute_noalloc", "LCO_NOALLOC_MAX_NNZ",
     "lco_contract", "lco_add", "lco_contract_batch", "lco_batch_stats", "ContractDesc", "Server", "lco_read",
     "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_only", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
@@ -148,6 +149,7 @@ def load_library():
             "lco_livs": (vp, [vp]),
             "lco_vals": (vp, [vp]),
             "lco_permute": (i32, [vp, vp, pi32, pvp]),
+            "lco_permute_noalloc": (i32, [vp, vp, pi32, vp, vp, pu64]),
             "lco_contract": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, pvp]),
             "lco_add": (i32, [vp, ctypes.c_double, vp, pi32, ctypes.c_double, vp, pi32, pi32, pvp]),
             "lco_ctx_set_crossovers": (i32, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -347,6 +349,19 @@ def lco_permute(ctx: Context, t: Tensor, perm) -> Tensor:
     h = ctypes.c_void_p()
     _check(L.lco_permute(ctx.handle, t.handle, _i32arr(perm), ctypes.byref(h)))
     return Tensor(ctx, h)
+
+
+LCO_NOALLOC_MAX_NNZ = 1 << 20  # include/lco.h
+
+
+def lco_permute_noalloc(ctx: Context, t: Tensor, perm, out_livs, out_vals):
+    """lco_permute into caller-owned device tensors (int64 / float64, t.nnz entries each), with no device
+    allocation by the library; returns the output dimensions."""
+    L = load_library()
+    dims = (ctypes.c_uint64 * max(1, t.order))()
+    _check(L.lco_permute_noalloc(ctx.handle, t.handle, _i32arr(perm), ctypes.c_void_p(out_livs.data_ptr()),
+                                 ctypes.c_void_p(out_vals.data_ptr()), dims))
+    return [int(dims[r]) for r in range(t.order)]
 
 
 def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Tensor:

@@ -133,6 +133,14 @@ Scratch::Scratch(lco_ctx ctx) : ctx_(ctx) {
 void* Scratch::raw(size_t bytes) {
   Arena& a = ctx_->arena;
   bytes = (bytes + 255) & ~(size_t)255;
+  if (a.fixed) {
+    if (a.used + bytes > a.fixed_cap) fail(LCO_E_OOM, "scratch: the operation needs more than the fixed workspace");
+    char* p = a.fixed + a.used;
+    a.used += bytes;
+    a.in_use += bytes;
+    a.high_water = std::max(a.high_water, a.in_use);
+    return p;
+  }
   if (a.chunks.empty() || a.used + bytes > a.chunks.back().cap) {
     size_t cap = std::max<size_t>(bytes, (size_t)32 << 20);
     if (!a.chunks.empty()) cap = std::max(cap, a.chunks.back().cap * 2);
@@ -151,6 +159,11 @@ void* Scratch::raw(size_t bytes) {
 Scratch::~Scratch() {
   Arena& a = ctx_->arena;
   ctx_->scratch_depth--;
+  if (a.fixed) {
+    a.used = ctx_->scratch_depth == 0 ? 0 : mark_used_;
+    a.in_use = ctx_->scratch_depth == 0 ? 0 : mark_in_use_;
+    return;
+  }
   if (ctx_->scratch_depth == 0) {
     if (a.chunks.size() > 1) {
       // the op outgrew the main chunk: release everything (stream-ordered); the
@@ -169,6 +182,16 @@ Scratch::~Scratch() {
     a.in_use = mark_in_use_;
   }
 }
+
+FixedScratch::FixedScratch(lco_ctx ctx, void* base, size_t bytes) : ctx_(ctx) {
+  if (ctx->scratch_depth != 0) fail(LCO_E_ARG, "fixed workspace inside another operation");
+  saved_ = std::move(ctx->arena);
+  ctx->arena = Arena{};
+  ctx->arena.fixed = static_cast<char*>(base);
+  ctx->arena.fixed_cap = bytes;
+}
+
+FixedScratch::~FixedScratch() { ctx_->arena = std::move(saved_); }
 
 void memset_async(lco_ctx ctx, void* p, int v, size_t bytes) {
   if (bytes) LCO_HIP(hipMemsetAsync(p, v, bytes, ctx->stream));
@@ -354,6 +377,7 @@ lco_status lco_ctx_create(int device, void* hip_stream, lco_alloc_fn alloc, lco_
   LCO_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) fail(LCO_E_ARG, "lco_ctx_create: no such device");
   LCO_HIP(hipSetDevice(device));
+  noalloc_init_device(device);
   lco_ctx c = new lco_ctx_s;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;

@@ -49,6 +49,10 @@ struct Arena {
   size_t used = 0;            // bytes used in the current (last) chunk
   size_t high_water = 0;      // total bytes in use at the peak of the current op
   size_t in_use = 0;
+  // A fixed workspace (not null): scratch is carved from it and never
+  // allocated; a request beyond fixed_cap fails with LCO_E_OOM.
+  char* fixed = nullptr;
+  size_t fixed_cap = 0;
 };
 
 }  // namespace lco
@@ -125,6 +129,21 @@ class Scratch {
   lco_ctx ctx_;
   size_t mark_chunk_, mark_used_, mark_in_use_;
 };
+
+// The context's scratch taken from a fixed device workspace for the lifetime of
+// this object (the previous arena is put back afterwards).
+class FixedScratch {
+ public:
+  FixedScratch(lco_ctx ctx, void* base, size_t bytes);
+  ~FixedScratch();
+ private:
+  lco_ctx ctx_;
+  Arena saved_;
+};
+
+// Called once per context creation with the context's device current: sets up
+// the device's fixed workspace of the no-allocation entry points.
+void noalloc_init_device(int device);
 
 // small host<->device helpers on the context stream
 void memset_async(lco_ctx ctx, void* p, int v, size_t bytes);
