@@ -304,6 +304,40 @@ def batched_leg(lco, ctx, torch, np, L, count: int, reps: int):
     }
 
 
+def batch_profile_leg(lco, ctx, torch, np, L, count: int):
+    """The batched work of the batched leg alone (for profilers): two lco_contract_batch calls over the
+    same instances, then a planned batch executed once and replayed once as a graph."""
+    inst = L.batched_fd_instances(count)
+    distinct = {}
+    for dim, side in sorted(set(inst)):
+        c, v = L.fd_laplacian(side, dim)
+        distinct[(dim, side)] = lco.lco_create(ctx, [side] * (2 * dim),
+                                               torch.from_numpy(c.view(np.int64).reshape(-1).copy()).to("cuda:0"),
+                                               torch.from_numpy(v).to("cuda:0"), lco.LCO_COORDS)
+    ops = [lco.lco_create(ctx, distinct[k].dims, distinct[k].livs(), distinct[k].vals(), lco.LCO_SORTED)
+           for k in inst]
+    for t in distinct.values():
+        t.destroy()
+    items = [(a, *fd_labels(dim)[:1], a, *fd_labels(dim)[1:]) for a, (dim, _) in zip(ops, inst)]
+    out = {}
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = lco.lco_contract_batch(ctx, items)
+        torch.cuda.synchronize()
+        out[f"batched_s_{rep}"] = time.perf_counter() - t0
+        for o in outs:
+            o.destroy()
+    plan = lco.BatchPlan(ctx, items)
+    plan.execute()
+    plan.graph_launch()
+    torch.cuda.synchronize()
+    plan.destroy()
+    for a in ops:
+        a.destroy()
+    return out
+
+
 def serving_leg(lco, ctx, torch, np, L, seconds: float, workers: int, stress: float):
     """Replay a Poisson request trace in real time against the continuous-batching server, then
     the same trace against serial plain calls (one worker, one request at a time, FIFO).  With
@@ -827,6 +861,9 @@ def main():
     ap.add_argument("--rp-only", action="store_true", help="run only the permutation-table leg")
     ap.add_argument("--hyper-only", action="store_true", help="run only the hyper-sparse (SOP) leg")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched leg")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--batch-profile", action="store_true",
+                    help="run only the batched work of the batched leg, without the per-call loop and checks")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the selector calibration sweeps (R-TENSORs, Sections 5.2.3-5.2.5)")
     ap.add_argument("--calibrate-reps", type=int, default=3)
@@ -844,7 +881,7 @@ def main():
     import paper_1802_02619_amd as lco
 
     only = (args.copy_probe_only or args.app_only or args.calibrate or args.rp_only or args.hyper_only or
-            args.batch_only)
+            args.batch_only or args.batch_profile or args.serve_only)
     coords = vals = cb = None
     if not only:
         coords, vals = L.fd_laplacian(SIDE, 3)
@@ -869,6 +906,14 @@ def main():
         return
     if args.hyper_only:
         print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps))}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers,
+                                                 args.serve_stress)}), flush=True)
+        return
+    if args.batch_profile:
+        print(json.dumps({"batch_profile": batch_profile_leg(lco, ctx, torch, np, L, max(1, args.batch_count))}),
+              flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batched": batched_leg(lco, ctx, torch, np, L, max(1, args.batch_count),

@@ -291,12 +291,14 @@ typedef struct {
  * applied per instance).  Instances whose plan is CSR/CSC/CSRNA/CSCNA (after
  * any operand rearrangement) and that have no entrywise label are batched.
  * Those whose rows of A' are listed densely (at most 2 nnz(A') + 64 rows and at
- * most 2^20 of them, k' < 2^34) run in the persistent engine: one launch of a
- * persistent grid computes every instance's multiplication datatype, symbolic
+ * most 2^20 of them, at most 2^21 A' entries, k' < 2^34) run in the persistent
+ * engine when there are at least 32 of them (fewer run in the chunked engine
+ * below): one launch of a persistent grid computes every instance's multiplication datatype, symbolic
  * counts and output offsets from a device work queue, one host synchronisation
  * reads the output sizes, and a second persistent launch writes every
- * instance's product.  The other batched instances run in chunks of at most
- * 2^26 A' entries, one launch per phase.  Outputs of batched instances share
+ * instance's product.  The other batched instances run in the chunked engine:
+ * chunks of at most 2^26 A' entries, one launch per phase over all the
+ * instances of a chunk.  Outputs of batched instances share
  * device allocations that are released with the last of their tensors.  An
  * instance with a row of more than 64 products or entries, and every
  * instance that is not batched (doubly compressed, outer product, entrywise),
@@ -330,8 +332,8 @@ lco_status lco_batch_stats(lco_ctx ctx, int64_t* batched, int64_t* per_call, int
  *
  * Only instances that the persistent engine runs completely (row-wise or
  * column-wise singly compressed products without entrywise labels, rows of A'
- * listed densely, every row with at most 64 products and entries) can be
- * planned; others give LCO_E_UNSUPPORTED.  The outputs belong to the plan
+ * listed densely, within its size limits above, every row with at most 64
+ * products and entries) can be planned; others give LCO_E_UNSUPPORTED.  The outputs belong to the plan
  * (lco_batch_plan_output returns borrowed handles, valid until
  * lco_batch_plan_destroy). */
 typedef struct lco_batch_plan_s* lco_batch_plan;

@@ -3,6 +3,8 @@
 // order does not already give the layout the chosen algorithm needs;
 // (2) build the multiplication datatype and multiply (row engine or SOP);
 // (3) map the product back: permute it into the output label order if needed.
+#include <algorithm>
+
 #include "rows.h"
 
 namespace lco {
@@ -115,6 +117,11 @@ namespace lco {
 
 // Chunks per work item of the persistent engine when no tuned value is known.
 constexpr int kDefaultGroup = 4;
+// Instances from which a batch runs in the persistent engine: its phases
+// (each with a grid-wide wait) cost about half a millisecond, which a handful
+// of products does not amortise; smaller batches (a server's batches of a few
+// requests among them) run in the chunked engine, one launch per phase.
+constexpr size_t kPersistMinInstances = 32;
 
 // The persistent engine's choice for one instance: the tuned branch and chunks
 // per item of its size bucket, else the selector's branch.
@@ -235,6 +242,21 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
         (acc ? acc_jobs : na_jobs).push_back(j);
       }
       batched.push_back(i);
+    }
+    if (!pjobs.empty() && pjobs.size() < kPersistMinInstances) {
+      // too few for the persistent engine: the chunked engine takes them
+      for (const PJob& p : pjobs) {
+        BatchJob j;
+        j.index = p.index;
+        j.A = p.A;
+        j.B = p.B;
+        j.kp = p.kp;
+        j.np = p.np;
+        j.order_c = p.order_c;
+        for (int r = 0; r < p.order_c; ++r) j.natural_dims[r] = p.natural_dims[r];
+        (p.acc ? acc_jobs : na_jobs).push_back(j);
+      }
+      pjobs.clear();
     }
     std::vector<int> redo = persist_group(ctx, pjobs, outs);
     // the rest (rows of A' listed sparsely) in chunks of bounded total entries

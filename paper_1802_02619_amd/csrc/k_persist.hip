@@ -27,7 +27,10 @@
 // Rows are computed by the same device code as the per-call engine
 // (row_core.h), so each result is bit-identical to the per-call result.
 #include <algorithm>
+#include <array>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "row_core.h"
 
@@ -113,6 +116,14 @@ __device__ __forceinline__ PInst load_inst(const PInst* __restrict__ inst, int i
 #pragma unroll
   for (int k = 0; k < (int)(sizeof(PInst) / 4); ++k) dst[k] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[k]);
   return x;
+}
+
+// Items of queue q among a phase's n items: lo, lo + kSubQueues, ... (len of them).
+__device__ __forceinline__ void queue_range(uint64_t n, uint32_t q, uint64_t& lo, uint64_t& len) {
+  const uint32_t x = q / kSubQueues, j = q % kSubQueues;
+  const uint64_t xlo = n * x / kXcds, xhi = n * (x + 1) / kXcds;
+  lo = xlo + j;
+  len = xhi > lo ? (xhi - lo + kSubQueues - 1) / kSubQueues : 0;
 }
 
 // Instance owning item k of a phase: the largest i < count with pre[i] <= k
@@ -321,14 +332,28 @@ __device__ __forceinline__ void p_chunk(const PArgs& g, const PInst& x, int inst
 // ---------------------------------------------------------------- phases 3 and 4: scans by one wave
 
 // Exclusive scan of n 32-bit counts into 64-bit offsets; returns the total.
+// Each lane takes 16 consecutive counts per step (independent loads), so a
+// step covers 1024 counts with one wave-wide scan.
+constexpr int kScanPerLane = 16;
 __device__ __forceinline__ uint64_t wave_scan_counts(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
                                                      uint64_t n, int lane) {
   uint64_t run = 0;
-  for (uint64_t b = 0; b < n; b += kWave) {
-    const uint64_t v = b + lane < n ? in[b + lane] : 0;
-    const uint64_t incl = wave_inclusive_scan(v);
-    if (b + lane < n) out[b + lane] = run + incl - v;
-    run += __shfl(incl, kWave - 1, kWave);
+  for (uint64_t b = 0; b < n; b += (uint64_t)kScanPerLane * kWave) {
+    const uint64_t first = b + (uint64_t)lane * kScanPerLane;
+    uint32_t v[kScanPerLane];
+#pragma unroll
+    for (int k = 0; k < kScanPerLane; ++k) v[k] = first + k < n ? in[first + k] : 0u;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerLane; ++k) mine += v[k];
+    const uint64_t incl = wave_inclusive_scan(mine);
+    uint64_t at = run + incl - mine;
+#pragma unroll
+    for (int k = 0; k < kScanPerLane; ++k) {
+      if (first + k < n) out[first + k] = at;
+      at += v[k];
+    }
+    run += lane_value(incl, kWave - 1);
   }
   return run;
 }
@@ -350,16 +375,27 @@ __device__ __forceinline__ void run_item(const PArgs& g, int p, uint64_t k, PLds
     if (p != 5) return;
   }
   if (p == 4) {
-    // every instance's place in the pool, in instance order
+    // every instance's place in the pool, in instance order (16 instances per lane per step)
     uint64_t run = 0;
     uint32_t anyfb = 0;
-    for (int b = 0; b < g.count; b += kWave) {
-      const int i = b + lane;
-      const uint64_t v = i < g.count ? g.total[i] : 0;
-      anyfb |= (i < g.count && g.fallback[i]) ? 1u : 0u;
-      const uint64_t incl = wave_inclusive_scan(v);
-      if (i < g.count) g.base[i] = run + incl - v;
-      run += __shfl(incl, kWave - 1, kWave);
+    for (int b = 0; b < g.count; b += kScanPerLane * kWave) {
+      const int first = b + lane * kScanPerLane;
+      uint64_t v[kScanPerLane];
+      uint64_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < kScanPerLane; ++k) {
+        v[k] = first + k < g.count ? g.total[first + k] : 0;
+        anyfb |= (first + k < g.count && g.fallback[first + k]) ? 1u : 0u;
+        mine += v[k];
+      }
+      const uint64_t incl = wave_inclusive_scan(mine);
+      uint64_t at = run + incl - mine;
+#pragma unroll
+      for (int k = 0; k < kScanPerLane; ++k) {
+        if (first + k < g.count) g.base[first + k] = at;
+        at += v[k];
+      }
+      run += lane_value(incl, kWave - 1);
     }
     anyfb = __ballot(anyfb != 0) ? 1u : 0u;
     if (lane == 0) {
@@ -437,8 +473,10 @@ __global__ __launch_bounds__(kRowThreads, MODE == kModeSize ? 8 : 6) void bt_per
   const PArgs& g = *gp;
   __shared__ PLds s_lds[kRowWaves];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  // queue q = XCD * kSubQueues + sub holds the q-th of kQueues contiguous ranges of
-  // every phase's items; a wave drains its home queue, then takes leftovers,
+  // queue q = XCD * kSubQueues + sub: XCD x owns the x-th of kXcds contiguous
+  // ranges of every phase's items, and its sub-queue j every kSubQueues-th item
+  // of that range from the j-th on, so that the waves of one XCD sweep its
+  // range together; a wave drains its home queue, then takes leftovers,
   // preferring the other queues of its own XCD
   const uint32_t xcd = blockIdx.x % kXcds;
   const uint32_t sub = ((blockIdx.x / kXcds) * kRowWaves + (uint32_t)w) % kSubQueues;
@@ -450,19 +488,21 @@ __global__ __launch_bounds__(kRowThreads, MODE == kModeSize ? 8 : 6) void bt_per
     uint64_t did = 0;
     uint32_t cur = xcd * kSubQueues + sub;
     for (;;) {
-      const uint64_t lo = n * cur / kQueues, len = n * (cur + 1) / kQueues - lo;
+      uint64_t lo, len;
+      queue_range(n, cur, lo, len);
       uint64_t* head = ctl_head(g.ctl, p, cur);
       uint64_t k = ~0ull;
       if (lane == 0 && __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
         k = atomicAdd((unsigned long long*)head, 1ull);
       k = shfl0_u64(k);
       if (k < len) {
-        run_item<NARROW, MODE, BRANCH>(g, p, lo + k, s_lds[w], lane);
+        run_item<NARROW, MODE, BRANCH>(g, p, lo + k * kSubQueues, s_lds[w], lane);
         ++did;
         continue;
       }
       // this queue is drained: look for a queue with items left, one queue per lane
-      const uint64_t clo = n * cand / kQueues, clen = n * (cand + 1) / kQueues - clo;
+      uint64_t clo, clen;
+      queue_range(n, cand, clo, clen);
       const bool left = __hip_atomic_load(ctl_head(g.ctl, p, cand), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < clen;
       const uint64_t m = __ballot(left);
       if (!m) break;
@@ -511,7 +551,7 @@ T* take(lco_ctx ctx, Scratch* s, KeptBuffers* keep, size_t n) {
 
 bool persist_eligible(uint64_t mp, uint64_t kp, int64_t nnz_a, int64_t nnz_b) {
   return nnz_a > 0 && nnz_b > 0 && mp <= 2 * (uint64_t)nnz_a + kWave && mp <= kPersistMaxRows &&
-         kp < ((uint64_t)1 << 34) && nnz_a < (int64_t)UINT32_MAX && nnz_b < (int64_t)UINT32_MAX;
+         nnz_a <= kPersistMaxEntries && kp < ((uint64_t)1 << 34) && nnz_b < (int64_t)UINT32_MAX;
 }
 
 struct PersistBatch::Dev {
@@ -581,14 +621,27 @@ PersistBatch::PersistBatch(lco_ctx ctx, const std::vector<PJob>& jobs, Scratch* 
   a.ctl = take<uint64_t>(ctx, s, keep, kCtlWords);
   a.err = ctx->dev_err;
   upload_params();
-  for (int mode : {kModeSize, kModeNumeric, kModeAll}) {
-    for (int branch : {kBranchNa, kBranchAcc, kBranchBoth}) {
-      int bpc = 0;
-      LCO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &bpc, (const void*)persist_kernel(D.narrow, mode, branch), kRowThreads, 0));
-      const int g = ctx->num_cus * std::max(1, bpc);
-      D.grid[mode][branch] = (g + (int)kXcds - 1) / (int)kXcds * (int)kXcds;
+  // blocks that fill every compute unit, by mode and branch (the same for every batch on a device)
+  static std::mutex grid_mu;
+  static std::map<std::pair<int, int>, std::array<int, 12>> grid_cache;  // (device, narrow) -> grids
+  {
+    std::lock_guard<std::mutex> lk(grid_mu);
+    auto it = grid_cache.find({ctx->device, D.narrow ? 1 : 0});
+    if (it == grid_cache.end()) {
+      std::array<int, 12> gr{};
+      for (int mode : {kModeSize, kModeNumeric, kModeAll}) {
+        for (int branch : {kBranchNa, kBranchAcc, kBranchBoth}) {
+          int bpc = 0;
+          LCO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &bpc, (const void*)persist_kernel(D.narrow, mode, branch), kRowThreads, 0));
+          const int g = ctx->num_cus * std::max(1, bpc);
+          gr[mode * 3 + branch] = (g + (int)kXcds - 1) / (int)kXcds * (int)kXcds;
+        }
+      }
+      it = grid_cache.emplace(std::make_pair(ctx->device, D.narrow ? 1 : 0), gr).first;
     }
+    for (int mode = 0; mode < 4; ++mode)
+      for (int branch = 0; branch < 3; ++branch) D.grid[mode][branch] = mode ? it->second[mode * 3 + branch] : 0;
   }
   set_items(std::vector<bool>(count, true));
 }

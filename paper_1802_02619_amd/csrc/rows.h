@@ -110,8 +110,11 @@ std::vector<int> batch_group(lco_ctx ctx, const std::vector<BatchJob>& jobs, boo
 // ---------------------------------------------------------------- persistent batched engine (k_persist.hip)
 
 // Rows of A' per instance up to which an instance runs in the persistent engine
-// (each instance's chunk counts are scanned by one wave).
+// (each instance's chunk counts are scanned by one wave), and A' entries: the
+// engine is for many small and medium products; a larger one keeps the GPU
+// busy alone, and its setup phases run faster as separate launches.
 constexpr uint64_t kPersistMaxRows = uint64_t(1) << 20;
+constexpr int64_t kPersistMaxEntries = int64_t(1) << 21;
 
 // One instance of a persistent batch, in the row-engine roles.
 struct PJob {

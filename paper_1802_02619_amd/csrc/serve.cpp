@@ -3,15 +3,18 @@
 // Each worker thread owns a HIP stream (default priority) and a context that
 // allocates with stream-ordered hipMallocAsync.  A free worker takes every
 // pending request that fits the device-memory budget, in arrival order, and
-// runs them as one batched contraction; requests arriving meanwhile wait for
-// the next free worker, so the batches of different workers overlap on the
-// device.  A request's result does not depend on the batch it ran in: the
+// runs them as one batched contraction (a batch of one as a plain call);
+// requests arriving meanwhile wait for the next free worker, so the batches of
+// different workers overlap on the device.  An outer-product or doubly
+// compressed request runs in a batch of its own, and waits while another such
+// request is on the GPU.  A request's result does not depend on the batch it ran in: the
 // batched path computes every row with the same device code and summation
 // order as the per-call path.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 
@@ -32,7 +35,8 @@ struct Request {
   std::vector<int> la, lb, lc;  // never empty, so .data() is valid for order-0 operands
   int c_order = 0;
   uint32_t flags = 0;
-  bool solo = false;
+  bool solo = false;   // runs in a batch of its own
+  bool heavy = false;  // outer product or doubly compressed: also one at a time
   uint64_t est = 0;      // estimated device footprint (bytes)
   uint64_t charged = 0;  // what was taken from the budget
   Clock::time_point arrival, start;
@@ -58,9 +62,17 @@ struct lco_server_s {
   lco_server_config cfg{};
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_done;
+  // Idle workers wait on their own condition variable; new work wakes the
+  // worker that went idle last, so that at low load one warm worker (thread,
+  // stream and scratch) serves the requests.
+  std::vector<std::unique_ptr<std::condition_variable>> cv_worker;
+  std::vector<int> idle;     // stack of idle workers
+  std::vector<char> woken;   // per worker: woken by wake_one
+
   std::deque<Request*> pending, done;
   uint64_t budget_left = 0;
+  bool heavy_running = false;  // an outer-product or doubly compressed request is on the GPU
   int64_t next_ticket = 0;
   int64_t outstanding = 0;  // submitted and not yet complete
   bool stop = false;
@@ -71,13 +83,25 @@ struct lco_server_s {
 
 namespace {
 
+// Called with the lock held: wakes the worker that went idle last.
+void wake_one(lco_server s) {
+  if (s->idle.empty()) return;
+  const int w = s->idle.back();
+  s->idle.pop_back();
+  s->woken[w] = 1;
+  s->cv_worker[w]->notify_one();
+}
+
 // Called with the lock held: moves the next batch out of `pending`.
 bool take_batch(lco_server s, std::vector<Request*>& batch) {
   const uint64_t total = s->cfg.hbm_budget;
   for (auto it = s->pending.begin(); it != s->pending.end() && (int)batch.size() < s->cfg.max_batch;) {
     Request* r = *it;
     const bool idle = s->budget_left == total && batch.empty();
-    if ((r->est > s->budget_left && !idle) || (r->solo && !batch.empty())) {
+    // the outer-product and doubly compressed requests (sorts of every product)
+    // also run one at a time: two of them on the GPU together would each take
+    // about twice as long
+    if ((r->est > s->budget_left && !idle) || (r->solo && !batch.empty()) || (r->heavy && s->heavy_running)) {
       ++it;
       continue;
     }
@@ -85,6 +109,7 @@ bool take_batch(lco_server s, std::vector<Request*>& batch) {
     s->budget_left -= r->charged;
     batch.push_back(r);
     it = s->pending.erase(it);
+    if (r->heavy) s->heavy_running = true;
     if (r->solo) break;
   }
   return !batch.empty();
@@ -119,6 +144,7 @@ void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
     std::lock_guard<std::mutex> lk(s->mu);
     for (int i = 0; i < n; ++i) {
       Request* r = batch[i];
+      if (r->heavy) s->heavy_running = false;
       r->res.status = st[i];
       r->res.out = st[i] == LCO_OK ? outs[i] : nullptr;
       r->res.latency_ms = ms_between(r->arrival, t_done);
@@ -128,9 +154,11 @@ void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
       s->done.push_back(r);
       s->outstanding--;
     }
+    // a finished batch frees budget (and possibly the running solo request):
+    // another worker may now take what this one does not
+    if (!s->pending.empty()) wake_one(s);
   }
   s->cv_done.notify_all();
-  s->cv_work.notify_all();
 }
 
 void worker_main(lco_server s, int w) {
@@ -140,8 +168,16 @@ void worker_main(lco_server s, int w) {
     batch.clear();
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return take_batch(s, batch) || (s->stop && s->pending.empty()); });
-      if (batch.empty()) return;
+      for (;;) {
+        if (take_batch(s, batch)) break;
+        if (s->stop && s->pending.empty()) return;
+        s->idle.push_back(w);
+        s->cv_worker[w]->wait(lk, [&] { return s->woken[w] || s->stop; });
+        s->woken[w] = 0;
+        s->idle.erase(std::remove(s->idle.begin(), s->idle.end(), w), s->idle.end());
+      }
+      // more work than this batch: let another worker look at it
+      if (!s->pending.empty()) wake_one(s);
     }
     const Clock::time_point t_start = Clock::now();
     for (Request* r : batch) r->start = t_start;
@@ -153,8 +189,8 @@ void release(lco_server s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+    for (auto& cv : s->cv_worker) cv->notify_all();
   }
-  s->cv_work.notify_all();
   for (std::thread& t : s->threads)
     if (t.joinable()) t.join();
   for (Request* r : s->done) {
@@ -202,6 +238,8 @@ lco_status lco_server_create(int device, const lco_server_config* cfg, lco_serve
       if (r != LCO_OK) fail(r, "lco_server_create: context creation failed");
       s->ctxs.push_back(c);
     }
+    s->woken.assign(cfg->workers, 0);
+    for (int w = 0; w < cfg->workers; ++w) s->cv_worker.emplace_back(new std::condition_variable);
     for (int w = 0; w < cfg->workers; ++w) s->threads.emplace_back(worker_main, s, w);
   } catch (const Error& e) {
     release(s);
@@ -241,6 +279,7 @@ lco_status lco_server_submit(lco_server s, const lco_contract_desc* d, int64_t* 
                                          algo == LCO_ALG_CSCNA);
     const int64_t nn = d->a->nnz + d->b->nnz;
     r->solo = !plan.empty && (!rowwise || (s->cfg.solo_nnz > 0 && nn > s->cfg.solo_nnz));
+    r->heavy = !plan.empty && !rowwise;
     r->est = footprint(plan, d->a->nnz, d->b->nnz, rowwise || plan.empty);
     r->arrival = Clock::now();
     {
@@ -249,8 +288,8 @@ lco_status lco_server_submit(lco_server s, const lco_contract_desc* d, int64_t* 
       *ticket = r->res.ticket;
       s->pending.push_back(r);
       s->outstanding++;
+      wake_one(s);
     }
-    s->cv_work.notify_one();
     return LCO_OK;
   } catch (const Error& e) {
     return set_error(e);

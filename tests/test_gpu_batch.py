@@ -61,11 +61,23 @@ def test_batch_mixed_instances_equal_per_call(lco_lib, gpu_ctx, oracle_mod):
     items.append((gl, [0, 1], ge, [1, 2], [0, 2]))
     refs.append(None)
 
+    # a batch of fewer than 32 instances that the persistent engine could take runs in the chunked engine
+    small = lco_lib.lco_contract_batch(gpu_ctx, items)
+    b_small, p_small, q_small = lco_lib.lco_batch_stats(gpu_ctx)
+    assert q_small == 0 and b_small >= 6
+    for it, out in zip(items, small):
+        single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
+        got, alone = np_of(out), np_of(single)
+        assert np.array_equal(got[1], alone[1]) and np.array_equal(got[2], alone[2])
+        single.destroy()
+    for out in small:
+        out.destroy()
+    items, refs = items * 4, refs * 4  # enough instances for the persistent engine
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
     batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
     print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
-    assert batched >= 6 and per_call >= 4  # FD compositions batch; long rows / DCSR / SOP fall back
-    assert persistent >= 7  # the FD compositions and the long-row instance (sent on to the per-call path)
+    assert batched >= 24 and per_call >= 16  # FD compositions batch; long rows / DCSR / SOP fall back
+    assert persistent >= 28  # the FD compositions and the long-row instance (sent on to the per-call path)
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
@@ -111,11 +123,12 @@ def test_batch_mixed_column_widths(lco_lib, gpu_ctx, oracle_mod):
     items.append((ga, [0, 1, 2], gb, [2, 3, 4], [0, 1, 3, 4], lco_lib.ALGO_IDS["CSR"]))
     refs.append(oracle_mod.contract(oracle_mod.create(da, ca, va), [0, 1, 2], oracle_mod.create(db, cb, vb),
                                     [2, 3, 4], [0, 1, 3, 4]))
+    items, refs = items * 16, refs * 16
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
     batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
     print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
-    # the wide instance's rows of A' are mostly empty: it runs in the chunked engine
-    assert batched == 3 and per_call == 0 and persistent == 2
+    # the wide instances' rows of A' are mostly empty: they run in the chunked engine
+    assert batched == 48 and per_call == 0 and persistent == 32
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
@@ -257,10 +270,11 @@ def test_batch_clustered_rows_with_fd_instances(lco_lib, gpu_ctx, oracle_mod):
                                     [1, 2], [0, 2]))
     items.append(items[0])
     refs.append(refs[0])
+    items, refs = items * 8, refs * 8
     outs = lco_lib.lco_contract_batch(gpu_ctx, items)
     batched, per_call, persistent = lco_lib.lco_batch_stats(gpu_ctx)
     print(f"batched={batched} per_call={per_call} persistent={persistent}", flush=True)
-    assert batched == 4 and per_call == 0 and persistent == 4
+    assert batched == 32 and per_call == 0 and persistent == 32
     for it, out, ref in zip(items, outs, refs):
         single = lco_lib.lco_contract(gpu_ctx, *it[:5], it[5] if len(it) > 5 else 0)
         got, alone = np_of(out), np_of(single)
