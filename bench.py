@@ -533,7 +533,8 @@ def small_leg(lco, ctx, torch, np, L, reps: int):
 
 def hyper_leg(lco, ctx, torch, np, L, reps: int):
     """The order-4 hyper-sparse Kronecker pair (2^16 per mode, 2^24 draws each, duplicates summed),
-    contracted over (2,3)x(0,1): the outer-product (SOP) path with B permuted (2,3,0,1)."""
+    contracted over (2,3)x(0,1): index-sparse x index-sparse, where the selector measured on MI355X takes
+    DCSC (no rearrangement) and the paper's table SOP (B permuted (2,3,0,1)); both are timed."""
     import concurrent.futures as cf
     with cf.ThreadPoolExecutor(2) as ex:  # the seeded PCG64 recipe on the host, both operands at once
         host = list(ex.map(lambda seed: L.kronecker_hypersparse(16, 1 << 24, seed), (1, 2)))
@@ -548,6 +549,10 @@ def hyper_leg(lco, ctx, torch, np, L, reps: int):
     assert (A.nnz, B.nnz) == (16777201, 16777183), (A.nnz, B.nnz)
     la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
     plan = lco.lco_plan_info(ctx, A, la, B, lb, lc).as_dict()
+    paper_ctx = lco.lco_ctx_create(0)
+    lco.lco_ctx_use_paper_selector(paper_ctx)
+    paper_algo = lco.lco_plan_info(paper_ctx, A, la, B, lb, lc).as_dict()["algo_name"]
+    paper_ctx.destroy()
     C = lco.lco_contract(ctx, A, la, B, lb, lc)  # warm-up
     C.destroy()
     t = []
@@ -573,10 +578,10 @@ def hyper_leg(lco, ctx, torch, np, L, reps: int):
             kernels[name] = {"launches_per_rep": n_l, "ms_per_rep": tot}
     lco.lco_timing_reset(ctx)
     ms = statistics.median(t) * 1e3
-    # the same product through the doubly-compressed column path (no operand permute, no product sort)
+    # the same product through the other algorithms of the cell (SOP: the paper's table's choice)
     ref = lco.lco_contract(ctx, A, la, B, lb, lc)
     alt = {}
-    for name in ("DCSC", "DCSR"):
+    for name in [x for x in ("SOP", "DCSC", "DCSR") if x != plan["algo_name"]]:
         f = lco.ALGO_IDS[name]
         C = lco.lco_contract(ctx, A, la, B, lb, lc, f)
         C.destroy()
@@ -599,7 +604,7 @@ def hyper_leg(lco, ctx, torch, np, L, reps: int):
                        "duplicates summed), contracted over (2,3)x(0,1)",
            "nnz_a": A.nnz, "nnz_b": B.nnz, "nnz_out": n_out, "algo": plan["algo_name"],
            "permute_b": plan["permute_b"], "ms": ms, "output_nnz_per_s": n_out / (ms * 1e-3), "reps": reps,
-           "forced": alt,
+           "paper_table_algo": paper_algo, "forced": alt,
            "kernels": dict(sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_rep"])[:12])}
     A.destroy()
     B.destroy()
@@ -750,8 +755,9 @@ def rp_leg(lco, ctx, torch, np, L, n: int, reps: int):
 def calibrate_leg(lco, ctx, torch, np, L, reps: int):
     """The paper's hyper-sparsity sweeps (Sections 5.2.3-5.2.5) repeated on this GPU with R-TENSORs
     (Section 5.2.1): column-sparsity (a_ijk b_ljk, CSC vs DCSC), row-sparsity (a_ijk b_lmk, CSC vs CSCNA) and
-    index-sparsity (M x N x N tensors with M = N^2, a_ijk b_ljk, CSC vs SOP).  Each point times both forced
-    algorithms end to end (median of `reps`); the crossover is where the alternative starts to win for good."""
+    index-sparsity (M x N x N tensors with M = N^2, a_ijk b_ljk, CSC vs SOP, and DCSC beside both).  Each point
+    times the forced algorithms end to end (median of `reps`); a crossover is where the alternative starts to win
+    for good."""
     dev = torch.device("cuda", 0)
 
     def make(bits, draws, seed, extra=0):
@@ -776,8 +782,11 @@ def calibrate_leg(lco, ctx, torch, np, L, reps: int):
         return statistics.median(t)
 
     tuned_ctx = lco.lco_ctx_create(0)
-    lco.lco_ctx_set_crossovers(tuned_ctx, *lco.MI355X_CROSSOVERS)
-    totals = {"paper_ms": 0.0, "mi355x_ms": 0.0}
+    lco.lco_ctx_use_mi355x_selector(tuned_ctx)
+    paper_ctx = lco.lco_ctx_create(0)
+    lco.lco_ctx_use_paper_selector(paper_ctx)
+    totals = {"paper_ms": 0.0, "mi355x_ms": 0.0, "changed_points": 0, "changed_paper_ms": 0.0,
+              "changed_mi355x_ms": 0.0}
 
     def crossover(rows):
         rows = sorted(rows, key=lambda r: r["sparsity"])
@@ -795,8 +804,9 @@ def calibrate_leg(lco, ctx, torch, np, L, reps: int):
         "row_sparsity": {"spec": "a_ijk b_lmk", "alt": "CSCNA", "draws": (100_000, 200_000, 300_000),
                          "bits": range(8, 14), "extra": 0, "lab": ([0, 1, 2], [3, 4, 2], [0, 1, 3, 4]),
                          "paper_crossover": 3, "paper_threshold": 3},
-        "index_sparsity": {"spec": "a_ijk b_ljk, M x N x N with M = N^2", "alt": "SOP", "draws": (50_000, 100_000),
-                           "bits": range(7, 13), "extra": None, "lab": ([0, 1, 2], [3, 1, 2], [0, 3]),
+        "index_sparsity": {"spec": "a_ijk b_ljk, M x N x N with M = N^2", "alt": "SOP", "alt2": "DCSC",
+                           "draws": (50_000, 100_000, 1_000_000),
+                           "bits": range(7, 16), "extra": None, "lab": ([0, 1, 2], [3, 1, 2], [0, 3]),
                            "paper_crossover": 6, "paper_threshold": 3},
     }
     out = {}
@@ -810,29 +820,49 @@ def calibrate_leg(lco, ctx, torch, np, L, reps: int):
                 a = make(bits, draws, seed, extra)
                 b = make(bits, draws, seed + 1, extra)
                 seed += 2
-                plan = lco.lco_plan_info(ctx, a, la, b, lb, lc).as_dict()
+                plan = lco.lco_plan_info(paper_ctx, a, la, b, lb, lc).as_dict()
                 sp = (plan["k"] if name == "column_sparsity" else plan["m"]) / max(1, a.nnz)
                 t_csc = timed(a, la, b, lb, lc, "CSC")
                 t_alt = timed(a, la, b, lb, lc, e["alt"])
-                t_paper = timed(a, la, b, lb, lc, "auto")
+                t_alt2 = timed(a, la, b, lb, lc, e["alt2"]) if "alt2" in e else None
+                t_paper = timed(a, la, b, lb, lc, "auto", paper_ctx)
                 t_tuned = timed(a, la, b, lb, lc, "auto", tuned_ctx)
                 totals["paper_ms"] += t_paper
                 totals["mi355x_ms"] += t_tuned
                 tuned = lco.lco_plan_info(tuned_ctx, a, la, b, lb, lc).as_dict()
+                if tuned["algo_name"] != plan["algo_name"]:
+                    totals["changed_points"] += 1
+                    totals["changed_paper_ms"] += t_paper
+                    totals["changed_mi355x_ms"] += t_tuned
                 rows.append({"draws": draws, "bits": bits, "nnz_a": a.nnz, "sparsity": sp, "csc_ms": t_csc,
                              "alt_ms": t_alt, "ratio": t_csc / t_alt, "selected": plan["algo_name"],
                              "selected_mi355x": tuned["algo_name"], "auto_ms": t_paper, "auto_mi355x_ms": t_tuned})
+                if t_alt2 is not None:
+                    rows[-1].update({"alt2_ms": t_alt2, "ratio_alt_over_alt2": t_alt / t_alt2,
+                                     "ratio_csc_over_alt2": t_csc / t_alt2})
                 print(f"calibration {name} draws={draws} bits={bits} sparsity={sp:.2f} "
-                      f"CSC {t_csc:.3f} ms {e['alt']} {t_alt:.3f} ms", file=sys.stderr, flush=True)
+                      f"CSC {t_csc:.3f} ms {e['alt']} {t_alt:.3f} ms"
+                      + (f" {e['alt2']} {t_alt2:.3f} ms" if t_alt2 is not None else "")
+                      + f" auto {tuned['algo_name']} {t_tuned:.3f} ms", file=sys.stderr, flush=True)
                 a.destroy()
                 b.destroy()
+        if "alt2" in e:
+            out[name + "_" + e["alt2"].lower()] = {
+                "product": e["spec"], "alternatives": [e["alt"], e["alt2"]],
+                "crossover_vs_csc": crossover([{"sparsity": r["sparsity"], "ratio": r["ratio_csc_over_alt2"]}
+                                               for r in rows]),
+                "crossover_vs_sop": crossover([{"sparsity": r["sparsity"], "ratio": r["ratio_alt_over_alt2"]}
+                                               for r in rows])}
         out[name] = {"product": e["spec"], "alternative": e["alt"], "crossover": crossover(rows),
                      "paper_crossover_E8400": e["paper_crossover"], "paper_threshold": e["paper_threshold"],
                      "points": rows}
     tuned_ctx.destroy()
+    paper_ctx.destroy()
     out["selector_total"] = {**totals, "crossovers_paper": list(lco.PAPER_CROSSOVERS),
                              "crossovers_mi355x": list(lco.MI355X_CROSSOVERS),
-                             "note": "sum over every sweep point of the automatic choice's median time"}
+                             "index_algorithm_mi355x": lco.MI355X_INDEX_ALGORITHM,
+                             "note": "sums over every sweep point (and over the points whose choice differs) of the "
+                                     "automatic choice's median time"}
     return out
 
 

@@ -94,28 +94,43 @@ lco_status lco_ctx_synchronize(lco_ctx ctx);
  * and an orientation from the operands' hyper-sparsity classes (ratio of a
  * matricised dimension to the non-zeros above 3).  Sections 5.2.3-5.2.5
  * measure where each specialised algorithm actually starts to win against CSC
- * (about 10 for DCSC, 3 for CSCNA, 6 for SOP on the paper's CPU).  With
- * crossovers set, a chosen DCSC/DCSR gives way to CSC/CSR (same orientation)
- * while the operand's relevant hyper-sparsity (A's columns, B's rows) is at most
- * `doubly_compressed`; CSCNA/CSRNA to CSC/CSR while A's rows / B's columns are at
- * most `no_accumulator`; SOP to CSC or CSR (fewest rearrangements) while the
- * smallest of the four ratios is at most `outer_product`.  The default, 3 for
- * all three, is the paper's table unchanged.  Every algorithm sums each output
- * in the same order, so only the speed changes.  Applies to lco_contract,
- * lco_plan_info, batches and batch plans made on this context.  Errors:
- * LCO_E_ARG (NULL, or a value below 3 or not finite). */
+ * (about 10 for DCSC, 3 for CSCNA, 6 for SOP on the paper's CPU).  A
+ * context's selector keeps the table's classes, cell and orientation and
+ * refines the cell's choice with three crossovers: a chosen DCSC/DCSR gives
+ * way to CSC/CSR (same orientation) while the operand's relevant
+ * hyper-sparsity (A's columns, B's rows) is at most `doubly_compressed`;
+ * CSCNA/CSRNA to CSC/CSR while A's rows / B's columns are at most
+ * `no_accumulator`; the index-sparse x index-sparse cell's algorithm to CSC or
+ * CSR (fewest rearrangements, then n > m) while the smallest of the four
+ * ratios is at most `outer_product`.  Above that, that cell runs SOP (the
+ * paper's table) or DCSC/DCSR in the same orientation (see
+ * lco_ctx_set_index_algorithm).  Crossovers of 3 and SOP in the index cell are
+ * the paper's table unchanged.  A new context starts with the values measured
+ * on MI355X (LCO_MI355X_*).  Every algorithm sums each output in the same
+ * order, so only the speed changes.  Applies to lco_contract, lco_plan_info,
+ * batches, batch plans and servers made on this context.  Errors: LCO_E_ARG
+ * (NULL, or a value below 3 or not finite). */
 lco_status lco_ctx_set_crossovers(lco_ctx ctx, double doubly_compressed, double no_accumulator,
                                   double outer_product);
 lco_status lco_ctx_get_crossovers(lco_ctx ctx, double* doubly_compressed, double* no_accumulator,
                                   double* outer_product);
-/* Crossovers measured on MI355X with the paper's R-TENSOR sweeps (the
+/* The algorithm of the index-sparse x index-sparse cell above the
+ * `outer_product` crossover: LCO_ALG_SOP (the paper's table, Section 5.2.5) or
+ * the doubly compressed accumulator algorithms (LCO_ALG_DCSC or LCO_ALG_DCSR;
+ * either selects the pair, oriented as above).  The getter reports
+ * LCO_ALG_SOP or LCO_ALG_DCSC.  Errors: LCO_E_ARG (NULL, another algorithm). */
+lco_status lco_ctx_set_index_algorithm(lco_ctx ctx, int algo);
+lco_status lco_ctx_get_index_algorithm(lco_ctx ctx, int* algo);
+/* The selector measured on MI355X with the paper's R-TENSOR sweeps (the
  * benchmark's calibration leg): DCSC overtakes CSC above a column-sparsity of
- * about 16; SOP overtakes CSC above an index-sparsity of about 59; CSCNA and CSC
- * take the same time at every row-sparsity (the accumulator is a per-row LDS
- * table here, not a dense array of the row count), so NA keeps the paper's 3. */
-#define LCO_MI355X_DC_CROSSOVER 16.0
+ * about 8; CSCNA and CSC take the same time at every row-sparsity (the
+ * accumulator is a per-row LDS table here, not a dense array of the row count),
+ * so NA keeps the paper's 3; in the index-sparse cell DCSC is faster than SOP
+ * at every index-sparsity measured and overtakes CSC above about 30. */
+#define LCO_MI355X_DC_CROSSOVER 8.0
 #define LCO_MI355X_NA_CROSSOVER 3.0
-#define LCO_MI355X_SOP_CROSSOVER 59.0
+#define LCO_MI355X_INDEX_CROSSOVER 30.0
+#define LCO_MI355X_INDEX_ALGORITHM LCO_ALG_DCSC
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels (off by default; costs two events per

@@ -21,6 +21,8 @@ __all__ = [
     "BatchPlan", "lco_plan_info", "lco_plan_contract", "lco_plan_permute", "lco_classify", "lco_select",
     "lco_fastdiv_host", "lco_timing_enable", "lco_timing_only", "lco_timing_reset", "lco_timing_query", "lco_timing_kernels",
     "lco_ctx_set_crossovers", "lco_ctx_get_crossovers", "MI355X_CROSSOVERS", "PAPER_CROSSOVERS",
+    "lco_ctx_set_index_algorithm", "lco_ctx_get_index_algorithm", "lco_ctx_use_paper_selector",
+    "lco_ctx_use_mi355x_selector", "MI355X_INDEX_ALGORITHM",
     "lco_version", "LCO_SORTED", "LCO_COORDS", "LCO_SUM_DUPLICATES", "ALGOS", "ALGO_IDS", "CLASSES",
     "LCO_ALG_AUTO", "LCO_ALG_CSC", "LCO_ALG_CSR", "LCO_ALG_DCSC", "LCO_ALG_DCSR", "LCO_ALG_CSCNA",
     "LCO_ALG_CSRNA", "LCO_ALG_SOP", "LCO_SPARSE", "LCO_ROW_SPARSE", "LCO_COL_SPARSE", "LCO_INDEX_SPARSE",
@@ -155,6 +157,8 @@ def load_library():
             "lco_ctx_set_crossovers": (i32, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
             "lco_ctx_get_crossovers": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double)]),
+            "lco_ctx_set_index_algorithm": (i32, [vp, i32]),
+            "lco_ctx_get_index_algorithm": (i32, [vp, pi32]),
             "lco_plan_info": (i32, [vp, vp, pi32, vp, pi32, i32, pi32, u32, ctypes.POINTER(Plan)]),
             "lco_contract_batch": (i32, [vp, i32, ctypes.POINTER(ContractDesc), ctypes.POINTER(ctypes.c_void_p)]),
             "lco_batch_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -372,10 +376,11 @@ def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_label
     return Tensor(ctx, h)
 
 
-# selector crossovers (doubly compressed, no accumulator, outer product): the paper's table as is, and
-# those measured on MI355X (LCO_MI355X_*_CROSSOVER in include/lco.h)
+# selector crossovers (doubly compressed, no accumulator, index cell): the paper's table as is, and
+# those measured on MI355X (LCO_MI355X_* in include/lco.h), a new context's default
 PAPER_CROSSOVERS = (3.0, 3.0, 3.0)
-MI355X_CROSSOVERS = (16.0, 3.0, 59.0)
+MI355X_CROSSOVERS = (8.0, 3.0, 30.0)
+MI355X_INDEX_ALGORITHM = "DCSC"
 
 
 def lco_ctx_set_crossovers(ctx: Context, doubly_compressed: float, no_accumulator: float, outer_product: float):
@@ -387,6 +392,30 @@ def lco_ctx_get_crossovers(ctx: Context):
     d, n, o = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(load_library().lco_ctx_get_crossovers(ctx.handle, ctypes.byref(d), ctypes.byref(n), ctypes.byref(o)))
     return (d.value, n.value, o.value)
+
+
+def lco_ctx_set_index_algorithm(ctx: Context, algo):
+    """The index-sparse x index-sparse cell's algorithm above its crossover: "SOP" or "DCSC"/"DCSR"."""
+    _check(load_library().lco_ctx_set_index_algorithm(ctx.handle, ALGO_IDS[algo] if isinstance(algo, str) else
+                                                      int(algo)))
+
+
+def lco_ctx_get_index_algorithm(ctx: Context) -> str:
+    a = ctypes.c_int()
+    _check(load_library().lco_ctx_get_index_algorithm(ctx.handle, ctypes.byref(a)))
+    return ALGOS[a.value]
+
+
+def lco_ctx_use_paper_selector(ctx: Context):
+    """The paper's table unchanged: crossovers of 3 and SOP in the index-sparse cell."""
+    lco_ctx_set_crossovers(ctx, *PAPER_CROSSOVERS)
+    lco_ctx_set_index_algorithm(ctx, "SOP")
+
+
+def lco_ctx_use_mi355x_selector(ctx: Context):
+    """The selector measured on MI355X (a new context's default)."""
+    lco_ctx_set_crossovers(ctx, *MI355X_CROSSOVERS)
+    lco_ctx_set_index_algorithm(ctx, MI355X_INDEX_ALGORITHM)
 
 
 def lco_add(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, alpha: float = 1.0,

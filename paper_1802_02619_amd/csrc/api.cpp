@@ -592,7 +592,7 @@ lco_status lco_contract(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_tens
   if (a->ctx->device != ctx->device || b->ctx->device != ctx->device)
     fail(LCO_E_ARG, "lco_contract: tensor lives on another device");
   ContractDetail d = plan_contract(a->order, a->dims, a_labels, a->nnz, b->order, b->dims, b_labels, b->nnz,
-                                   c_order, c_labels, flags, ctx->cross);
+                                   c_order, c_labels, flags, &ctx->sel);
   LCO_HIP(hipSetDevice(ctx->device));
   *out = contract_run(ctx, a, b, d);
   return LCO_OK;
@@ -605,9 +605,27 @@ lco_status lco_ctx_set_crossovers(lco_ctx ctx, double doubly_compressed, double 
   if (!ctx) fail(LCO_E_ARG, "lco_ctx_set_crossovers: ctx is NULL");
   for (double x : {doubly_compressed, no_accumulator, outer_product})
     if (!(x >= 3.0) || std::isinf(x)) fail(LCO_E_ARG, "lco_ctx_set_crossovers: crossovers must be finite and >= 3");
-  ctx->cross[0] = doubly_compressed;
-  ctx->cross[1] = no_accumulator;
-  ctx->cross[2] = outer_product;
+  ctx->sel.cross[0] = doubly_compressed;
+  ctx->sel.cross[1] = no_accumulator;
+  ctx->sel.cross[2] = outer_product;
+  return LCO_OK;
+  LCO_CATCH
+}
+
+lco_status lco_ctx_set_index_algorithm(lco_ctx ctx, int algo) {
+  LCO_TRY
+  if (!ctx) fail(LCO_E_ARG, "lco_ctx_set_index_algorithm: ctx is NULL");
+  if (algo != LCO_ALG_SOP && algo != LCO_ALG_DCSC && algo != LCO_ALG_DCSR)
+    fail(LCO_E_ARG, "lco_ctx_set_index_algorithm: algo must be SOP, DCSC or DCSR");
+  ctx->sel.index_dc = algo != LCO_ALG_SOP;
+  return LCO_OK;
+  LCO_CATCH
+}
+
+lco_status lco_ctx_get_index_algorithm(lco_ctx ctx, int* algo) {
+  LCO_TRY
+  if (!ctx || !algo) fail(LCO_E_ARG, "lco_ctx_get_index_algorithm: bad argument");
+  *algo = ctx->sel.index_dc ? LCO_ALG_DCSC : LCO_ALG_SOP;
   return LCO_OK;
   LCO_CATCH
 }
@@ -617,9 +635,9 @@ lco_status lco_ctx_get_crossovers(lco_ctx ctx, double* doubly_compressed, double
   LCO_TRY
   if (!ctx || !doubly_compressed || !no_accumulator || !outer_product)
     fail(LCO_E_ARG, "lco_ctx_get_crossovers: bad argument");
-  *doubly_compressed = ctx->cross[0];
-  *no_accumulator = ctx->cross[1];
-  *outer_product = ctx->cross[2];
+  *doubly_compressed = ctx->sel.cross[0];
+  *no_accumulator = ctx->sel.cross[1];
+  *outer_product = ctx->sel.cross[2];
   return LCO_OK;
   LCO_CATCH
 }
@@ -644,7 +662,7 @@ lco_status lco_plan_info(lco_ctx ctx, lco_tensor a, const int* a_labels, lco_ten
   LCO_TRY
   if (!out || !ctx || !a || !b) fail(LCO_E_ARG, "lco_plan_info: bad argument");
   ContractDetail d = plan_contract(a->order, a->dims, a_labels, a->nnz, b->order, b->dims, b_labels, b->nnz,
-                                   c_order, c_labels, flags, ctx->cross);
+                                   c_order, c_labels, flags, &ctx->sel);
   *out = d.pub;
   return LCO_OK;
   LCO_CATCH

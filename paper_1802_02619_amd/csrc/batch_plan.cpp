@@ -187,7 +187,7 @@ lco_status lco_batch_plan_create(lco_ctx ctx, int count, const lco_contract_desc
       if (x.a->ctx->device != ctx->device || x.b->ctx->device != ctx->device)
         fail(LCO_E_ARG, "lco_batch_plan_create: tensor lives on another device");
       plans[i] = plan_contract(x.a->order, x.a->dims, x.a_labels, x.a->nnz, x.b->order, x.b->dims, x.b_labels,
-                               x.b->nnz, x.c_order, x.c_labels, x.flags, ctx->cross);
+                               x.b->nnz, x.c_order, x.c_labels, x.flags, &ctx->sel);
       const int algo = plans[i].pub.algo;
       if (!plans[i].empty && ((algo != LCO_ALG_CSR && algo != LCO_ALG_CSC && algo != LCO_ALG_CSRNA &&
                                algo != LCO_ALG_CSCNA) || plans[i].n_entrywise))

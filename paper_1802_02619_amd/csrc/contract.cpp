@@ -186,7 +186,7 @@ extern "C" lco_status lco_contract_batch(lco_ctx ctx, int count, const lco_contr
       if (x.a->ctx->device != ctx->device || x.b->ctx->device != ctx->device)
         fail(LCO_E_ARG, "lco_contract_batch: tensor lives on another device");
       plans[i] = plan_contract(x.a->order, x.a->dims, x.a_labels, x.a->nnz, x.b->order, x.b->dims, x.b_labels,
-                               x.b->nnz, x.c_order, x.c_labels, x.flags, ctx->cross);
+                               x.b->nnz, x.c_order, x.c_labels, x.flags, &ctx->sel);
     }
     LCO_HIP(hipSetDevice(ctx->device));
     std::vector<BatchJob> acc_jobs, na_jobs;

@@ -10,8 +10,8 @@
 // LIV = col + n'*row.  Each output entry sums its products in ascending order
 // of the contracted index starting from 0.0.
 //
-// Setup: the row pointers of B' (or, when doubly compressed, its non-empty
-// rows and a bucket index over their ids), the rows of A' (row starts, and ids
+// Setup: the row pointers of B' (or, when doubly compressed, a hash table of
+// its non-empty rows keyed by row id), the rows of A' (row starts, and ids
 // unless every row is listed), and for every A' entry its product count and B'
 // row start.  When
 // few rows of A' are empty, one pass over A' lists all m' rows and writes the
@@ -45,22 +45,21 @@ __device__ __forceinline__ void b_row(const RowArgs& ra, uint64_t j, uint32_t& s
     start = ra.bptr[j];
     len = ra.bptr[j + 1] - start;
   } else {
-    // the rows whose ids share j's bucket, then a search among them
-    const uint64_t b = j >> ra.bshift;
-    uint32_t lo = ra.bkt[b];
-    const uint32_t end = ra.bkt[b + 1];
-    uint32_t hi = end;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (ra.brow_id[mid] < j) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo < end && ra.brow_id[lo] == j) {
-      start = ra.brow_start[lo];
-      len = ra.brow_start[lo + 1] - start;
-    } else {
-      start = 0;
-      len = 0;
+    // linear probing from the id's home slot; the table always holds an empty slot
+    uint64_t slot = dc_home(j, ra.dc_shift);
+    for (;;) {
+      const ulonglong2 e = ra.dc_tab[slot];
+      if (e.x == j) {
+        start = (uint32_t)e.y;
+        len = (uint32_t)(e.y >> 32);
+        return;
+      }
+      if (e.x == kDcEmpty) {
+        start = 0;
+        len = 0;
+        return;
+      }
+      slot = (slot + 1) & ra.dc_mask;
     }
   }
 }
@@ -105,25 +104,65 @@ __global__ void dense_ptr_kernel(const uint64_t* __restrict__ livs, int64_t n, F
   }
 }
 
-// Bucket index of the non-empty row ids of a doubly compressed B' (ids[0..*count),
-// ascending, below k'): bkt[b] = first i with ids[i] >> shift >= b, for b in
-// [0, nb] where nb = ((k' - 1) >> shift) + 1, so bkt[nb] = *count.  `cap`
-// bounds *count.
-__global__ void bucket_ptr_kernel(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ count, int64_t cap,
-                                  int shift, uint64_t nb, uint32_t* __restrict__ bkt) {
-  const int64_t n = (int64_t)*count;
-  const int64_t last = n < cap ? n : cap;
+// Hash table of a doubly compressed B' (slots of {row id, start | length << 32},
+// cap a power of two above the row count): every slot empty first.
+__global__ void dc_clear_kernel(ulonglong2* __restrict__ tab, uint64_t cap) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
+    tab[i] = make_ulonglong2(kDcEmpty, 0);
+}
+
+// Then the first entry of every row inserts the row: its end is the next row's
+// first entry, found in the wave's window of 64 entries or, for the window's
+// last row, by a galloping search past the window.  Whole waves step together.
+__global__ void dc_table_kernel(const uint64_t* __restrict__ livs, int64_t n, FastDiv div,
+                                ulonglong2* __restrict__ tab, int shift, uint64_t mask) {
   const int lane = lane_id();
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 <= last;
-       i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + lane;
-    const bool valid = i <= last;
-    uint64_t lo = 0, hi = 0;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 < n;
+       e0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = e0 + lane;
+    const bool valid = e < n;
+    uint64_t j = 0;
+    bool head = false;
     if (valid) {
-      lo = i == 0 ? 0 : (ids[i - 1] >> shift) + 1;
-      hi = (i == n ? nb : ids[i] >> shift) + 1;
+      j = fd_div(div, livs[e]);
+      head = e == 0 || fd_div(div, livs[e - 1]) != j;
     }
-    fill_slots(bkt, valid, lo, hi, (uint32_t)i);
+    const uint64_t heads = __ballot(head);
+    if (!head) continue;
+    const uint64_t later = lane == kWave - 1 ? 0 : heads & (~0ull << (lane + 1));
+    int64_t end;
+    if (later) {
+      end = e0 + __builtin_ctzll(later);
+    } else {
+      // every entry from e to the window's end lies in row j
+      int64_t known = (e0 + kWave < n ? e0 + kWave : n) - 1;
+      int64_t step = kWave;
+      int64_t hi = known + step;
+      while (hi < n && fd_div(div, livs[hi]) == j) {
+        known = hi;
+        step <<= 1;
+        hi = known + step;
+      }
+      if (hi > n) hi = n;
+      int64_t lo = known + 1;  // the end lies in [lo, hi]
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (fd_div(div, livs[mid]) == j) lo = mid + 1;
+        else hi = mid;
+      }
+      end = lo;
+    }
+    const uint64_t v = (uint64_t)(uint32_t)e | ((uint64_t)(uint32_t)(end - e) << 32);
+    uint64_t slot = dc_home(j, shift);
+    for (;;) {
+      const unsigned long long prev =
+          atomicCAS((unsigned long long*)&tab[slot].x, (unsigned long long)kDcEmpty, (unsigned long long)j);
+      if (prev == kDcEmpty) {
+        tab[slot].y = v;
+        break;
+      }
+      slot = (slot + 1) & mask;
+    }
   }
 }
 
@@ -612,6 +651,7 @@ __global__ __launch_bounds__(kBigThreads) void big_expand_kernel(RowArgs ra, con
                                                                  int colbits, uint64_t* __restrict__ keys,
                                                                  double* __restrict__ vals) {
   for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    if (off2[li + 1] == off2[li]) continue;  // a row of the in-LDS path
     const uint32_t r = list[li];
     const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
     const uint64_t p0 = ra.poff[e0];
@@ -648,8 +688,9 @@ __global__ __launch_bounds__(kBigThreads) void big_reduce_kernel(RowArgs ra, con
                                                                  double* __restrict__ out_vals) {
   __shared__ uint32_t wsum[kBigThreads / kWave + 1];
   for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
-    const uint32_t r = list[li];
     const uint64_t f = off2[li + 1] - off2[li];
+    if (f == 0) continue;  // a row of the in-LDS path
+    const uint32_t r = list[li];
     const uint64_t base = off2[li];
     const uint64_t row = row_of(ra, r);
     uint64_t run = 0;  // heads seen before this chunk
@@ -669,6 +710,211 @@ __global__ __launch_bounds__(kBigThreads) void big_reduce_kernel(RowArgs ra, con
       run += total;
     }
     if (!NUMERIC && threadIdx.x == 0) cnt[r] = run;
+  }
+}
+
+// Long rows of at most kMidMax products are computed in LDS, once: the row's
+// products are expanded keyed by (column, product index), put in key order by
+// a bitonic network, and each column's run is summed in product order, which
+// is ascending A' entry order, hence ascending contracted index (the keys are
+// distinct, so this is the order the stable global sort gives).  Each row's
+// output goes to a staging list at the row's product offset `moff` and its
+// count to cnt[r]; once the rows are placed, row_mid_copy moves it to C.
+constexpr int kMidThreads = 256;
+constexpr int kMidBits = 12;
+constexpr int kMidMax = 1 << kMidBits;
+constexpr int kMidWaveMax = 256;  // rows of at most this many products take one wave
+
+// Expands product p of a long row (A' entries [e0, e1), first product offset p0)
+// into its sort key (column << pbits | p) and value.
+__device__ __forceinline__ void mid_product(const RowArgs& ra, uint32_t e0, uint32_t e1, uint64_t p0, uint64_t row,
+                                            uint32_t p, int pbits, uint64_t& key, double& val) {
+  // last A' entry e in [e0, e1) with poff[e] <= p0 + p
+  uint32_t lo = e0, hi = e1 - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (ra.poff[mid] <= p0 + p) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint64_t j = ra.a_livs[lo] - ra.kp * row;
+  const uint32_t q = ra.bstart[lo] + (uint32_t)(p0 + p - ra.poff[lo]);
+  const uint64_t col = ra.b_livs[q] - ra.np * j;
+  key = (col << pbits) | p;
+  val = ra.a_vals[lo] * ra.b_vals[q];
+}
+
+__device__ __forceinline__ int mid_bits(uint64_t f) {
+  int pbits = 6;
+  while (((uint64_t)1 << pbits) < f) ++pbits;
+  return pbits;
+}
+
+// One wave per row of at most kMidWaveMax products (four rows per block).
+__global__ __launch_bounds__(kMidThreads) void row_midw_kernel(RowArgs ra, const uint32_t* __restrict__ list,
+                                                               uint32_t count, const uint64_t* __restrict__ f2,
+                                                               const uint64_t* __restrict__ moff,
+                                                               uint64_t* __restrict__ cnt,
+                                                               uint64_t* __restrict__ tmp_livs,
+                                                               double* __restrict__ tmp_vals) {
+  constexpr int kWaves = kMidThreads / kWave;
+  constexpr int kPer = kMidWaveMax / kWave;
+  __shared__ uint64_t skey_all[kWaves][kMidWaveMax];
+  __shared__ double sval_all[kWaves][kMidWaveMax];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  uint64_t* skey = skey_all[w];
+  double* sval = sval_all[w];
+  for (uint32_t li = blockIdx.x * kWaves + w; li < count; li += gridDim.x * kWaves) {
+    const uint64_t f = f2[li];
+    if (f > (uint64_t)kMidWaveMax) continue;  // uniform over the wave
+    const uint32_t r = list[li];
+    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+    const uint64_t p0 = ra.poff[e0];
+    const uint64_t row = row_of(ra, r);
+    const int pbits = mid_bits(f);
+    const uint32_t P = 1u << pbits;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t p = (uint32_t)(i * kWave + lane);
+      if (p < P) {
+        uint64_t key = ~0ull;  // padding sorts last
+        double v = 0.0;
+        if (p < f) mid_product(ra, e0, e1, p0, row, p, pbits, key, v);
+        skey[p] = key;
+        sval[p] = v;
+      }
+    }
+    wave_lds_sync();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+        for (int h = 0; h < kPer / 2; ++h) {
+          const uint32_t i = (uint32_t)(h * kWave + lane);
+          if (i < P / 2) {
+            const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+            const uint32_t hi = lo | j;
+            const uint64_t a = skey[lo], b = skey[hi];
+            if ((a > b) == ((lo & k) == 0)) {
+              skey[lo] = b;
+              skey[hi] = a;
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    const uint64_t base = moff[li];
+    uint64_t run = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t q = (uint32_t)(i * kWave + lane);
+      const uint64_t col = q < f ? skey[q] >> pbits : 0;
+      const bool head = q < f && (q == 0 || (skey[q - 1] >> pbits) != col);
+      const uint64_t hm = __ballot(head);
+      if (head) {
+        double acc = 0.0;
+        for (uint32_t t = q; t < (uint32_t)f && (skey[t] >> pbits) == col; ++t) acc += sval[skey[t] & (P - 1)];
+        const uint64_t o = base + run + (uint64_t)__popcll(hm & lanemask_lt());
+        tmp_livs[o] = col + ra.np * row;
+        tmp_vals[o] = acc;
+      }
+      run += (uint64_t)__popcll(hm);
+    }
+    if (lane == 0) cnt[r] = run;
+    wave_lds_sync();  // every run is summed before the next row is expanded
+  }
+}
+
+// One block per row of more than fmin and at most MAXP products.
+template <int MAXP>
+__global__ __launch_bounds__(kMidThreads) void row_mid_kernel(RowArgs ra, const uint32_t* __restrict__ list,
+                                                              uint32_t count, const uint64_t* __restrict__ f2,
+                                                              uint64_t fmin, const uint64_t* __restrict__ moff,
+                                                              uint64_t* __restrict__ cnt,
+                                                              uint64_t* __restrict__ tmp_livs,
+                                                              double* __restrict__ tmp_vals) {
+  __shared__ uint64_t skey[MAXP];
+  __shared__ double sval[MAXP];
+  __shared__ uint32_t wsum[kMidThreads / kWave + 1];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    const uint64_t f = f2[li];
+    if (f <= fmin || f > (uint64_t)MAXP) continue;  // uniform over the block
+    const uint32_t r = list[li];
+    const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
+    const uint64_t p0 = ra.poff[e0];
+    const uint64_t row = row_of(ra, r);
+    const int pbits = mid_bits(f);
+    const uint32_t P = 1u << pbits;
+    for (uint32_t p = tid; p < P; p += kMidThreads) {
+      uint64_t key = ~0ull;
+      double v = 0.0;
+      if (p < f) mid_product(ra, e0, e1, p0, row, p, pbits, key, v);
+      skey[p] = key;
+      sval[p] = v;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = tid; i < P / 2; i += kMidThreads) {
+          const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+          const uint32_t hi = lo | j;
+          const uint64_t a = skey[lo], b = skey[hi];
+          if ((a > b) == ((lo & k) == 0)) {
+            skey[lo] = b;
+            skey[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const uint64_t base = moff[li];
+    uint64_t run = 0;
+    for (uint32_t c0 = 0; c0 < (uint32_t)f; c0 += kMidThreads) {
+      const uint32_t q = c0 + tid;
+      const uint64_t col = q < f ? skey[q] >> pbits : 0;
+      const bool head = q < f && (q == 0 || (skey[q - 1] >> pbits) != col);
+      uint32_t total;
+      const uint32_t ex = block_exclusive_scan<uint32_t>(head ? 1u : 0u, wsum, total);
+      if (head) {
+        double acc = 0.0;
+        for (uint32_t t = q; t < (uint32_t)f && (skey[t] >> pbits) == col; ++t) acc += sval[skey[t] & (P - 1)];
+        tmp_livs[base + run + ex] = col + ra.np * row;
+        tmp_vals[base + run + ex] = acc;
+      }
+      run += total;
+    }
+    if (tid == 0) cnt[r] = run;
+    __syncthreads();  // every run is summed before the next row is expanded
+  }
+}
+
+// Moves each staged long row to its place in C (one wave per row).
+__global__ void row_mid_copy_kernel(const uint32_t* __restrict__ list, uint32_t count,
+                                    const uint64_t* __restrict__ moff, const uint64_t* __restrict__ coff,
+                                    const uint64_t* __restrict__ tmp_livs, const double* __restrict__ tmp_vals,
+                                    uint64_t* __restrict__ out_livs, double* __restrict__ out_vals) {
+  const int lane = lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t li = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; li < count; li += waves) {
+    const uint64_t src = moff[li];
+    if (moff[li + 1] == src) continue;  // a row of the global path
+    const uint32_t r = list[li];
+    const uint64_t dst = coff[r], n = coff[r + 1] - dst;
+    for (uint64_t q = lane; q < n; q += kWave) {
+      out_livs[dst + q] = tmp_livs[src + q];
+      out_vals[dst + q] = tmp_vals[src + q];
+    }
+  }
+}
+
+// Product counts of the long rows of the global path (g2) and of the in-LDS
+// path (m2), each zero for the other path's rows.
+__global__ void long_split_kernel(const uint64_t* __restrict__ f2, int64_t n, uint64_t fmax, uint64_t* __restrict__ g2,
+                                  uint64_t* __restrict__ m2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t f = f2[i];
+    g2[i] = f > fmax ? f : 0;
+    m2[i] = f > fmax ? 0 : f;
   }
 }
 
@@ -748,20 +994,18 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
                  bptr);
       ra.bptr = bptr;
     } else {
-      Segments brows = segment_livs(ctx, s, B->livs, nb, ndiv);
-      ra.brow_id = brows.ids;
-      ra.brow_start = brows.starts;
-      ra.nzr_b = brows.count;
-      // buckets of 2^shift row ids, at most nnz_B of them
-      const uint64_t kmax = kp ? kp - 1 : 0;
-      int shift = 0;
-      while (shift < 63 && (kmax >> shift) + 1 > (uint64_t)std::max<int64_t>(nb, 1)) ++shift;
-      const uint64_t nbk = (kmax >> shift) + 1;
-      uint32_t* bkt = s.get<uint32_t>(nbk + 1);
-      LCO_LAUNCH(ctx, "bucket_ptr", bucket_ptr_kernel, grid_for(ctx, nb + 1, 256), 256, 0, brows.ids, brows.count,
-                 nb, shift, nbk, bkt);
-      ra.bkt = bkt;
-      ra.bshift = shift;
+      // doubly compressed B': a hash table of its non-empty rows, at most two thirds full
+      int logcap = 6;
+      while (((uint64_t)1 << logcap) <= (uint64_t)nb + (uint64_t)nb / 2) ++logcap;
+      const uint64_t cap = (uint64_t)1 << logcap;
+      ulonglong2* tab = s.get<ulonglong2>(cap);
+      LCO_LAUNCH(ctx, "dc_clear", dc_clear_kernel, grid_for(ctx, (int64_t)cap, 256), 256, 0, tab, cap);
+      if (nb)
+        LCO_LAUNCH(ctx, "dc_table", dc_table_kernel, grid_for(ctx, nb, 256), 256, 0, B->livs, nb, ndiv, tab,
+                   64 - logcap, cap - 1);
+      ra.dc_tab = tab;
+      ra.dc_shift = 64 - logcap;
+      ra.dc_mask = cap - 1;
     }
     // one block of words: long-row count; some row is tiny; a copy; of the one-wave kernel
     uint64_t* n2_dev = s.get<uint64_t>(4);
@@ -804,16 +1048,34 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   const bool tiny = h[2] != 0, copy = h[3] != 0, wave = h[4] != 0;
   const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);  // 64 rows per wave and sweep
   const int copy_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + 3) / 4, (uint64_t)ctx->num_cus * 8));
-  uint64_t f2_total = 0;
+  uint64_t f2_total = 0, mid_total = 0;
   uint64_t* off2 = nullptr;
+  uint64_t* moff = nullptr;
+  // long rows of at most kMidMax products are computed in LDS (their keys pack
+  // the column and the product index into 63 bits); the rest take the global sort
+  const int colbits = bits_for(np - 1);
+  const bool mid = colbits + kMidBits <= 63;
   if (n2) {
-    // the long-row path locates products through the entries' product offsets
+    // the long-row paths locate products through the entries' product offsets
     scan_u32_u64(ctx, len, poff, na, poff + na);
     ra.poff = poff;
     off2 = s.get<uint64_t>(n2 + 1);
-    scan_u64(ctx, f2, off2, (int64_t)n2, off2 + n2);
-    const uint64_t* rb[1] = {off2 + n2};
-    f2_total = readback(ctx, rb, 1)[0];
+    moff = s.get<uint64_t>(n2 + 1);
+    if (mid) {
+      uint64_t* g2 = s.get<uint64_t>(n2);
+      uint64_t* m2 = s.get<uint64_t>(n2);
+      LCO_LAUNCH(ctx, "long_split", long_split_kernel, grid_for(ctx, (int64_t)n2, 256), 256, 0, (const uint64_t*)f2,
+                 (int64_t)n2, (uint64_t)kMidMax, g2, m2);
+      scan_u64(ctx, g2, off2, (int64_t)n2, off2 + n2);
+      scan_u64(ctx, m2, moff, (int64_t)n2, moff + n2);
+    } else {
+      scan_u64(ctx, f2, off2, (int64_t)n2, off2 + n2);
+      memset_async(ctx, moff + n2, 0, sizeof(uint64_t));
+    }
+    const uint64_t* rb[2] = {off2 + n2, moff + n2};
+    const uint64_t* h2 = readback(ctx, rb, 2);
+    f2_total = h2[0];
+    mid_total = h2[1];
   }
   // per-row output counts
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
@@ -849,13 +1111,28 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   if (copy)
     LCO_LAUNCH(ctx, "row_copy_sym", row_copy_kernel<false>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
                (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
-  // long rows: expand, sort by (row rank, column), count distinct
+  // long rows of the in-LDS path: computed now, staged, moved once placed
+  uint64_t* mid_livs = nullptr;
+  double* mid_vals = nullptr;
+  const int mid_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(n2, (uint64_t)ctx->num_cus * 8));
+  if (mid_total) {
+    mid_livs = s.get<uint64_t>(mid_total);
+    mid_vals = s.get<double>(mid_total);
+    const int midw_grid =
+        (int)std::max<uint64_t>(1, std::min<uint64_t>((n2 + 3) / 4, (uint64_t)ctx->num_cus * 8));
+    LCO_LAUNCH(ctx, "row_mid", row_midw_kernel, midw_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
+               (const uint64_t*)f2, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
+    LCO_LAUNCH(ctx, "row_mid", row_mid_kernel<1024>, mid_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
+               (const uint64_t*)f2, (uint64_t)kMidWaveMax, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
+    LCO_LAUNCH(ctx, "row_mid", row_mid_kernel<kMidMax>, mid_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
+               (const uint64_t*)f2, (uint64_t)1024, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
+  }
+  // other long rows: expand, sort by (row rank, column), count distinct
   uint64_t* keys = nullptr;
   double* pvals = nullptr;
   uint64_t colmask = 0;
   const int big_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(n2, (uint64_t)ctx->num_cus * 8));
-  if (n2) {
-    const int colbits = bits_for(np - 1);
+  if (f2_total) {
     const int qbits = bits_for(n2 - 1);
     if (colbits + qbits > 64) fail(LCO_E_UNSUPPORTED, "contract: long-row sort key exceeds 64 bits");
     colmask = colbits == 64 ? ~0ull : ((1ull << colbits) - 1);
@@ -886,7 +1163,11 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     if (copy)
       LCO_LAUNCH(ctx, "row_copy_num", row_copy_kernel<true>, copy_grid, 256, 0, ra, (uint32_t)nzr,
                  (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
-    if (n2)
+    if (mid_total)
+      LCO_LAUNCH(ctx, "row_mid_copy", row_mid_copy_kernel, mid_grid, 256, 0, (const uint32_t*)list2, (uint32_t)n2,
+                 (const uint64_t*)moff, (const uint64_t*)coff, (const uint64_t*)mid_livs, (const double*)mid_vals,
+                 C->livs, C->vals);
+    if (f2_total)
       LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
                  off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,
                  (const uint64_t*)coff, C->livs, C->vals);

@@ -55,6 +55,16 @@ struct Arena {
   size_t fixed_cap = 0;
 };
 
+// ------------------------------------------------------------------ selector
+// Hyper-sparsity up to which the doubly-compressed, no-accumulator and
+// index-cell algorithms give way to CSC/CSR, and the index-sparse x
+// index-sparse cell's algorithm: SOP (the paper's table) or the doubly
+// compressed accumulator algorithms.
+struct Selector {
+  double cross[3] = {LCO_MI355X_DC_CROSSOVER, LCO_MI355X_NA_CROSSOVER, LCO_MI355X_INDEX_CROSSOVER};
+  bool index_dc = LCO_MI355X_INDEX_ALGORITHM != LCO_ALG_SOP;
+};
+
 }  // namespace lco
 
 struct lco_ctx_s {
@@ -76,8 +86,8 @@ struct lco_ctx_s {
                                      // batched those in the persistent engine
   // batched-engine autotuner: (size bucket, selected branch) -> (branch, 64-row chunks per work item)
   std::map<int, std::pair<int, int>> tune;
-  // selector crossovers: doubly compressed, no accumulator, outer product
-  double cross[3] = {3.0, 3.0, 3.0};
+  // the selector's settings (default: those measured on MI355X)
+  lco::Selector sel;
 };
 
 namespace lco {
@@ -212,11 +222,10 @@ struct ContractDetail {
   // of its right operand (entrywise modes counted on the left only)
   uint64_t em, ek, en;
 };
-// `cross`: hyper-sparsity up to which the doubly-compressed, no-accumulator and
-// outer-product algorithms give way to CSC/CSR (NULL: never, the paper's table)
+// `sel`: the selector's crossovers and index-cell algorithm (NULL: the paper's table as is)
 ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
                              const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags,
-                             const double* cross = nullptr);
+                             const Selector* sel = nullptr);
 // Addition of two tensors over the same labelled modes: each operand is brought
 // into the output's mode order (output mode r is operand mode perm[r]).
 struct AddDetail {

@@ -183,7 +183,7 @@ bool is_identity(const int* p, int n) {
 
 ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t na, int ob, const uint64_t* db,
                              const int* lb, int64_t nb, int oc, const int* lc, uint32_t flags,
-                             const double* cross) {
+                             const Selector* sel) {
   check_dims(oa, da, "contract operand a");
   check_dims(ob, db, "contract operand b");
   if (oc < 0 || oc > LCO_MAX_ORDER) fail(LCO_E_ARG, "contract: output order out of range");
@@ -350,10 +350,14 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
       if (c1 < c0) algo = cell[1];
       else if (c0 == c1) algo = (pub.n > pub.m) ? cell[0] : cell[1];
     }
-    if (cross) {
+    if (sel) {
       // Measured crossovers: the cell's specialised algorithm gives way to the
       // singly compressed accumulator one while the operand is only mildly
-      // hyper-sparse (the cell and its orientation stay the paper's).
+      // hyper-sparse (the cell and its orientation stay the paper's).  The
+      // index-sparse cell's SOP may give way to the doubly compressed
+      // accumulator algorithms above that, oriented like the singly
+      // compressed ones (fewest rearrangements, then n > m).
+      const double* cross = sel->cross;
       auto ratio = [](uint64_t dim, int64_t nz) { return nz > 0 ? (long double)dim / (long double)nz : 0.0L; };
       const long double s_dc = algo == LCO_ALG_DCSC ? ratio(pub.k, na) : ratio(pub.k, nb);
       const long double s_na = algo == LCO_ALG_CSCNA ? ratio(pub.m, na) : ratio(pub.n, nb);
@@ -363,9 +367,11 @@ ContractDetail plan_contract(int oa, const uint64_t* da, const int* la, int64_t 
         algo = algo == LCO_ALG_DCSC ? LCO_ALG_CSC : LCO_ALG_CSR;
       else if ((algo == LCO_ALG_CSCNA || algo == LCO_ALG_CSRNA) && s_na <= cross[1])
         algo = algo == LCO_ALG_CSCNA ? LCO_ALG_CSC : LCO_ALG_CSR;
-      else if (algo == LCO_ALG_SOP && s_op <= cross[2]) {
+      else if (algo == LCO_ALG_SOP && (s_op <= cross[2] || sel->index_dc)) {
         const int c0 = best(0).cost, c1 = best(1).cost;
-        algo = c0 < c1 || (c0 == c1 && pub.n > pub.m) ? LCO_ALG_CSC : LCO_ALG_CSR;
+        const bool by_col = c0 < c1 || (c0 == c1 && pub.n > pub.m);
+        if (s_op <= cross[2]) algo = by_col ? LCO_ALG_CSC : LCO_ALG_CSR;
+        else algo = by_col ? LCO_ALG_DCSC : LCO_ALG_DCSR;
       }
     }
   }

@@ -27,11 +27,9 @@ struct RowArgs {
   FastDiv kdiv;          // k': row of A' = LIV / k'
   uint64_t kp = 1, np = 1;
   const uint32_t* bptr = nullptr;        // singly compressed B': k'+1 row starts
-  const uint64_t* brow_id = nullptr;     // doubly compressed B': non-empty row ids
-  const uint32_t* brow_start = nullptr;  //   and their starts (plus terminal)
-  const uint64_t* nzr_b = nullptr;       //   device count of non-empty rows
-  const uint32_t* bkt = nullptr;         //   first of those rows in each bucket of 2^bshift ids (plus terminal)
-  int bshift = 0;
+  const ulonglong2* dc_tab = nullptr;    // doubly compressed B': hash table of its non-empty rows,
+  uint64_t dc_mask = 0;                  //   slots {row id, start | length << 32}, dc_mask + 1 of them,
+  int dc_shift = 64;                     //   home slot dc_home(id, dc_shift), linear probing
   const uint32_t* row_start = nullptr;   // non-empty rows of A': starts (plus terminal)
   const uint64_t* row_id = nullptr;      //   and ids (nullptr: row r of the list is row r of A')
   const uint64_t* nzr_a = nullptr;       //   device count
@@ -39,6 +37,11 @@ struct RowArgs {
   const uint64_t* poff = nullptr;        // exclusive prefix of products per A' entry (nnz_a + 1)
   const uint32_t* bstart = nullptr;      // first B' entry of the row each A' entry selects
 };
+
+// Doubly compressed B' table: the id of an empty slot (row ids are below k' <= 2^64 - 1)
+// and a row id's home slot (Fibonacci hashing: the top bits of id * 2^64/phi).
+constexpr uint64_t kDcEmpty = ~0ull;
+__device__ __forceinline__ uint64_t dc_home(uint64_t id, int shift) { return (id * 0x9E3779B97F4A7C15ull) >> shift; }
 
 // Row of A' at position r of the row list.
 __device__ __forceinline__ uint64_t row_of(const RowArgs& ra, uint64_t r) { return ra.row_id ? ra.row_id[r] : r; }

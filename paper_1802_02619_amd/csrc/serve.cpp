@@ -259,10 +259,11 @@ lco_status lco_server_submit(lco_server s, const lco_contract_desc* d, int64_t* 
     if (d->a->ctx->device != s->device || d->b->ctx->device != s->device)
       fail(LCO_E_ARG, "lco_server_submit: operand lives on another device");
     if (d->c_order < 0 || d->c_order > LCO_MAX_ORDER) fail(LCO_E_ARG, "lco_server_submit: bad output order");
-    // argument errors surface here, before the request is queued
+    // argument errors surface here, before the request is queued; the algorithm
+    // is the one the workers' contexts will select
     const ContractDetail plan = plan_contract(d->a->order, d->a->dims, d->a_labels, d->a->nnz, d->b->order,
                                               d->b->dims, d->b_labels, d->b->nnz, d->c_order, d->c_labels,
-                                              d->flags);
+                                              d->flags, &s->ctxs[0]->sel);
     Request* r = new Request;
     r->a = d->a;
     r->b = d->b;

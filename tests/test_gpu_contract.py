@@ -20,6 +20,15 @@ FORCED = ["CSC", "CSR", "DCSC", "DCSR", "CSCNA", "CSRNA", "SOP"]
 TOL = 1e-12
 
 
+@pytest.fixture(scope="module")
+def paper_ctx(lco_lib):
+    """A context whose selector is the paper's table as is."""
+    c = lco_lib.lco_ctx_create(0)
+    lco_lib.lco_ctx_use_paper_selector(c)
+    yield c
+    c.destroy()
+
+
 def to_np(t):
     d, livs, vals = t.to_numpy()
     return d, livs, vals
@@ -203,7 +212,7 @@ def test_random_fp64_every_algorithm(lco_lib, gpu_ctx, oracle_mod, seed):
 
 
 def test_long_rows_global_path(lco_lib, gpu_ctx, oracle_mod):
-    """Rows with more than 64 products go through the global sort path."""
+    """Rows with more than 64 products (about 3000 here: the in-LDS sort of up to 4096)."""
     rng = np.random.default_rng(9)
     ca, va = L.random_sparse(rng, [60, 300], 6000)
     cb, vb = L.random_sparse(rng, [300, 200], 9000)
@@ -211,6 +220,57 @@ def test_long_rows_global_path(lco_lib, gpu_ctx, oracle_mod):
     gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [300, 200], cb, vb)
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [0, 2], exact=True)
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], [2, 0], exact=True)
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_long_rows_every_bin(lco_lib, gpu_ctx, oracle_mod, wide):
+    """Long rows in every bin of the long-row paths: in-LDS sorts of up to 256,
+    1024 and 4096 products, and the global sort above that (rows of about 4500
+    and 12000 products), beside rows of more than 64 entries with few or no
+    products.  Row 0 of B has 2500 entries: a doubly compressed B' finds its end
+    by a galloping search across many windows of 64 entries.  With 2^52 or more columns the (column, product) keys no longer
+    fit 63 bits and every long row takes the global sort."""
+    rng = np.random.default_rng(123)
+    m, k = 240, 2000
+    dims_b = [k, 1 << 26, 1 << 27] if wide else [k, 3000]
+    ncols = int(np.prod(dims_b[1:], dtype=np.float64)) if not wide else None
+    b_rows = []
+    for j in range(k):
+        if j % 10 == 9:
+            continue  # empty rows of B
+        ln = 2500 if j == 0 else int(rng.integers(1, 61))  # row 0: a doubly compressed row over 39 windows
+        if wide:
+            cols = np.unique(rng.integers(0, 1 << 20, ln)) * np.uint64(1 << 33) + np.uint64(j % 7)
+        else:
+            cols = rng.choice(ncols, ln, replace=False)
+        b_rows += [(j, int(c)) for c in cols]
+    nb = np.array(b_rows, dtype=np.uint64)
+    if wide:  # column c -> coordinates (c mod 2^26, c div 2^26)
+        cb = np.stack([nb[:, 0], nb[:, 1] % np.uint64(1 << 26), nb[:, 1] // np.uint64(1 << 26)], axis=1)
+    else:
+        cb = nb
+    vb = rng.integers(-3, 4, len(cb)).astype(np.float64)
+    vb[vb == 0] = 0.5
+    empty = np.array([j for j in range(k) if j % 10 == 9])
+    a_rows = []
+    for i in range(m):
+        t = [2, 5, 20, 60, 150, 400, 90][i % 7]
+        if i % 7 == 6:  # many entries, most of them selecting empty rows of B
+            full = np.setdiff1d(np.arange(k), empty)
+            cols = np.concatenate([rng.choice(empty, t - 5, replace=False), rng.choice(full, 5, replace=False)])
+        else:
+            cols = rng.choice(k, t, replace=False)
+        a_rows += [(i, int(c)) for c in cols]
+    ca = np.array(a_rows, dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, dims_b, cb, vb)
+    lb = [1, 2] if not wide else [1, 2, 3]
+    lc = [0, 2] if not wide else [0, 2, 3]
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, lb, lc, exact=True,
+            algos=("auto", "CSR", "DCSR", "CSRNA", "CSC", "DCSC"))
+    for t in (ga, gb):
+        t.destroy()
 
 
 def test_row_classes_mixed(lco_lib, gpu_ctx, oracle_mod):
@@ -269,14 +329,14 @@ def test_dense_rows_with_empty_rows(lco_lib, gpu_ctx, oracle_mod):
 
 
 @pytest.mark.parametrize("lc", [[0, 2], [2, 0]])
-def test_many_entry_rows_and_row_buckets(lco_lib, gpu_ctx, oracle_mod, lc):
+def test_many_entry_rows_and_row_table(lco_lib, gpu_ctx, oracle_mod, lc):
     """Rows of more than 64 entries (up to 700; their product counts are summed
     by a whole wave), some of which select only empty rows of the other operand
     and so have no products, in 300 rows (a ragged last wave).  The contracted
     index has 2^20 values and few non-empty rows, so a doubly compressed operand
-    is located through buckets of row ids: clustered rows, rows at both ends of
-    the range, and absent rows looked up inside occupied buckets.  B has a
-    column of 150 entries, a many-entry row of the column-wise orientation."""
+    is located through its hash table of row ids: clustered rows (long probe
+    runs), rows at both ends of the range, and absent rows.  B has a column of
+    150 entries, a many-entry row of the column-wise orientation."""
     rng = np.random.default_rng(77)
     m, k, n = 300, 1 << 20, 500
     brows = np.unique(np.concatenate([np.arange(200), [k - 1, k - 2, k - 5000], rng.integers(0, k, 300)]))
@@ -311,7 +371,7 @@ def test_clustered_rows_long_pointer_runs(lco_lib, gpu_ctx, oracle_mod, lc):
     """Rows clustered at both ends of their ranges leave runs of thousands of
     empty rows between them, which whole waves write: B's rows are the first and
     last 300 of 2^22 (about 4.2 million empty row pointers of a singly
-    compressed B', 1022 empty buckets in the index of a doubly compressed one),
+    compressed B'; a doubly compressed one finds them in its hash table),
     and A's rows are the first and last 150 of 4096 with 2400 entries (its row
     starts are taken over all 4096 rows)."""
     rng = np.random.default_rng(91)
@@ -380,49 +440,68 @@ def test_tiny_rows_staged_and_direct(lco_lib, gpu_ctx, oracle_mod, b_len):
 
 
 def test_selector_crossovers(lco_lib, gpu_ctx, oracle_mod):
-    """With the crossovers measured on MI355X, a column-sparsity of 8 takes CSC
-    instead of DCSC and an index-sparsity of 20 takes CSC or CSR instead of SOP,
-    with bit-identical results; a column-sparsity of 64 keeps DCSC; the paper's
-    table returns with the defaults; bad values are rejected."""
+    """A new context selects with the values measured on MI355X; the paper's
+    table is one call away.  Against the paper's table: a column-sparsity of 4
+    takes CSC instead of DCSC, a column-sparsity of 64 keeps DCSC, an
+    index-sparsity of 20 takes CSC or CSR instead of SOP, and one of 64 takes
+    DCSC or DCSR instead of SOP (or SOP again when the index cell is set to it).
+    Results are bit-identical throughout; bad values are rejected."""
     rng = np.random.default_rng(90)
     ctx2 = lco_lib.lco_ctx_create(0)
     try:
-        assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.PAPER_CROSSOVERS
+        assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.MI355X_CROSSOVERS
+        assert lco_lib.lco_ctx_get_index_algorithm(ctx2) == lco_lib.MI355X_INDEX_ALGORITHM == "DCSC"
         cases = []
-        # a_ijk b_ljk: A is N x N^2 with N^2 / nnz = 8 (A column-sparse, B row-sparse)
-        ca, va = L.random_sparse(rng, [64, 64, 64], 512)
-        cb, vb = L.random_sparse(rng, [64, 64, 64], 512)
-        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], True))
+        # a_ijk b_ljk: A is N x N^2 with N^2 / nnz = 4 (A column-sparse, B row-sparse)
+        ca, va = L.random_sparse(rng, [64, 64, 64], 1024)
+        cb, vb = L.random_sparse(rng, [64, 64, 64], 1024)
+        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, ("CSC", "CSR")))
         # the same with N^2 / nnz = 64: DCSC stays
         ca, va = L.random_sparse(rng, [64, 64, 64], 64)
         cb, vb = L.random_sparse(rng, [64, 64, 64], 64)
-        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], False))
-        # square N^2 x N^2 operands with index-sparsity 20
-        ca, va = L.random_sparse(rng, [4096, 64, 64], 205)
-        cb, vb = L.random_sparse(rng, [4096, 64, 64], 205)
-        cases.append(([4096, 64, 64], ca, va, [4096, 64, 64], cb, vb, [0, 1, 2], [3, 1, 2], [0, 3], True))
-        for da, ca, va, db, cb, vb, la, lb, lc, moves in cases:
+        cases.append(([64, 64, 64], ca, va, [64, 64, 64], cb, vb, None))
+        # square N^2 x N^2 operands with index-sparsity 20, then 64
+        for nnz, to in ((205, ("CSC", "CSR")), (64, ("DCSC", "DCSR"))):
+            ca, va = L.random_sparse(rng, [4096, 64, 64], nnz)
+            cb, vb = L.random_sparse(rng, [4096, 64, 64], nnz)
+            cases.append(([4096, 64, 64], ca, va, [4096, 64, 64], cb, vb, to))
+        la, lb, lc = [0, 1, 2], [3, 1, 2], [0, 3]
+        for da, ca, va, db, cb, vb, to in cases:
             ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, da, ca, va)
             gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, db, cb, vb)
             ref = oracle_mod.contract(oa, la, ob, lb, lc)
-            lco_lib.lco_ctx_set_crossovers(ctx2, *lco_lib.PAPER_CROSSOVERS)
+            lco_lib.lco_ctx_use_paper_selector(ctx2)
+            assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.PAPER_CROSSOVERS
             paper = lco_lib.lco_plan_info(ctx2, ga, la, gb, lb, lc).as_dict()
             got_p = lco_lib.lco_contract(ctx2, ga, la, gb, lb, lc)
-            lco_lib.lco_ctx_set_crossovers(ctx2, *lco_lib.MI355X_CROSSOVERS)
+            lco_lib.lco_ctx_use_mi355x_selector(ctx2)
             tuned = lco_lib.lco_plan_info(ctx2, ga, la, gb, lb, lc).as_dict()
             got_t = lco_lib.lco_contract(ctx2, ga, la, gb, lb, lc)
-            print("crossovers", paper["algo_name"], "->", tuned["algo_name"], flush=True)
-            assert (paper["algo_name"] != tuned["algo_name"]) == moves
-            assert tuned["algo_name"] in (("CSC", "CSR") if moves else (paper["algo_name"],))
-            check(got_p, ref, exact=True)
-            check(got_t, ref, exact=True)
-            for t in (got_p, got_t, ga, gb):
+            print("selector", paper["algo_name"], "->", tuned["algo_name"], flush=True)
+            if to is None:
+                assert tuned["algo_name"] == paper["algo_name"]
+            else:
+                assert paper["algo_name"] != tuned["algo_name"] and tuned["algo_name"] in to
+            outs = [got_p, got_t]
+            if paper["algo_name"] == "SOP" and to[0] == "DCSC":
+                # the measured crossovers with SOP in the index cell: SOP again
+                lco_lib.lco_ctx_set_index_algorithm(ctx2, "SOP")
+                assert lco_lib.lco_plan_info(ctx2, ga, la, gb, lb, lc).as_dict()["algo_name"] == "SOP"
+                outs.append(lco_lib.lco_contract(ctx2, ga, la, gb, lb, lc))
+                lco_lib.lco_ctx_set_index_algorithm(ctx2, "DCSR")
+                assert lco_lib.lco_ctx_get_index_algorithm(ctx2) == "DCSC"
+            for t in outs:
+                check(t, ref, exact=True)
+            for t in outs + [ga, gb]:
                 t.destroy()
-        for bad in [(2.0, 3.0, 3.0), (3.0, -1.0, 3.0), (3.0, 3.0, float("inf")), (float("nan"), 3.0, 3.0)]:
-            with pytest.raises(lco_lib.LcoError) as e:
+        for bad in [(2.9, 3, 3), (3, 3, float("inf")), (3, float("nan"), 3)]:
+            with pytest.raises(lco_lib.LcoError):
                 lco_lib.lco_ctx_set_crossovers(ctx2, *bad)
-            assert e.value.code == 1
+        for bad in ("CSC", "CSRNA", "auto"):
+            with pytest.raises(lco_lib.LcoError):
+                lco_lib.lco_ctx_set_index_algorithm(ctx2, bad)
         assert lco_lib.lco_ctx_get_crossovers(ctx2) == lco_lib.MI355X_CROSSOVERS
+        assert lco_lib.lco_ctx_get_index_algorithm(ctx2) == "DCSC"
     finally:
         ctx2.destroy()
 
@@ -443,8 +522,10 @@ def test_rowsparse_times_colsparse_uses_no_accumulator(lco_lib, gpu_ctx, oracle_
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
 
 
-def test_colsparse_times_rowsparse_uses_doubly_compressed(lco_lib, gpu_ctx, oracle_mod):
-    """a_ijk b_ljk (Section 5.2.3): A column-sparse, B row-sparse -> DCSC/DCSR."""
+def test_colsparse_times_rowsparse_uses_doubly_compressed(lco_lib, gpu_ctx, paper_ctx, oracle_mod):
+    """a_ijk b_ljk (Section 5.2.3): A column-sparse, B row-sparse -> DCSC/DCSR in the paper's
+    table (a column-sparsity of 5.5, below the crossover measured on MI355X, where a new context
+    takes CSC)."""
     rng = np.random.default_rng(22)
     d = [128, 128, 128]
     ca, va = L.random_sparse(rng, d, 3000)
@@ -452,15 +533,16 @@ def test_colsparse_times_rowsparse_uses_doubly_compressed(lco_lib, gpu_ctx, orac
     ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, d, ca, va)
     gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, d, cb, vb)
     la, lb, lc = [0, 1, 2], [3, 1, 2], [0, 3]
-    p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
+    p = lco_lib.lco_plan_info(paper_ctx, ga, la, gb, lb, lc)
     assert (p.a_class, p.b_class) == (lco_lib.LCO_COL_SPARSE, lco_lib.LCO_ROW_SPARSE)
     assert lco_lib.ALGOS[p.algo] in ("DCSC", "DCSR")
+    assert lco_lib.ALGOS[lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc).algo] in ("CSC", "CSR")
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
 
 
 @pytest.mark.parametrize("lc", [[0, 1, 4, 5], [0, 4, 1, 5]])
 @pytest.mark.parametrize("bits,draws", [(6, 3000), (10, 60000)])
-def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws, lc):
+def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, paper_ctx, oracle_mod, bits, draws, lc):
     """Scaled-down hyper-sparse Kronecker pair contracted over (3,4)x(1,2): index-sparse x
     index-sparse -> SOP, with the second operand rearranged; the output modes in order, or
     interleaved (a general output-LIV key)."""
@@ -473,8 +555,8 @@ def test_kronecker_index_sparse_sop(lco_lib, gpu_ctx, oracle_mod, bits, draws, l
     oa = oracle_mod.create(dims, ca, va, sum_duplicates=True)
     ob = oracle_mod.create(dims, cb, vb, sum_duplicates=True)
     la, lb = [0, 1, 2, 3], [2, 3, 4, 5]
-    p = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
     if bits == 10:
+        p = lco_lib.lco_plan_info(paper_ctx, ga, la, gb, lb, lc)
         assert lco_lib.ALGOS[p.algo] == "SOP" and p.permute_b == 1
     run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, la, gb, ob, lb, lc, exact=True)
 
@@ -585,7 +667,8 @@ def test_3d_fd_config_full_size(lco_lib, gpu_ctx, oracle_mod):
 @pytest.mark.slow
 def test_hypersparse_kronecker_full_size(lco_lib, gpu_ctx, oracle_mod):
     """Order-4 Kronecker pair, 2^16 per mode, 2^24 draws each (seeds 1, 2), contracted over (3,4)x(1,2)
-    by SOP; sampled output rows against the oracle."""
+    by DCSC (the selector measured on MI355X) and by SOP (the paper's table), bit-identical; sampled
+    output rows against the oracle."""
     bits, draws = 16, 1 << 24
     ca, va = L.kronecker_hypersparse(bits, draws, seed=1)
     cb, vb = L.kronecker_hypersparse(bits, draws, seed=2)
@@ -595,9 +678,15 @@ def test_hypersparse_kronecker_full_size(lco_lib, gpu_ctx, oracle_mod):
     gb = gpu_create(lco_lib, gpu_ctx, dims, cb, vb, flags)
     la, lb, lc = [0, 1, 2, 3], [2, 3, 4, 5], [0, 1, 4, 5]
     plan = lco_lib.lco_plan_info(gpu_ctx, ga, la, gb, lb, lc)
-    assert lco_lib.ALGOS[plan.algo] == "SOP"
+    assert lco_lib.ALGOS[plan.algo] == "DCSC" and plan.permute_a + plan.permute_b + plan.permute_c == 0
     r = lco_lib.lco_contract(gpu_ctx, ga, la, gb, lb, lc)
     _, livs, vals = to_np(r)
+    # the paper's table takes SOP here: the same bits
+    sop = lco_lib.lco_contract(gpu_ctx, ga, la, gb, lb, lc, lco_lib.ALGO_IDS["SOP"])
+    _, livs_s, vals_s = to_np(sop)
+    sop.destroy()
+    assert np.array_equal(livs, livs_s) and np.array_equal(vals.view(np.uint64), vals_s.view(np.uint64))
+    del livs_s, vals_s
     assert np.all(livs[1:] > livs[:-1])
     # sampled rows: output entries whose (mode 0, mode 1) pair lies in a random sample
     oa = oracle_mod.create(dims, ca, va, sum_duplicates=True)

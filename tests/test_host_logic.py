@@ -247,6 +247,7 @@ def test_orientation_rule_prefers_fewer_rearrangements(lib):
 def test_crossover_constants_match_header(lib):
     hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lco.h")).read()
     got = tuple(float(re.search(r"#define LCO_MI355X_%s_CROSSOVER ([0-9.]+)" % k, hdr).group(1))
-                for k in ("DC", "NA", "SOP"))
+                for k in ("DC", "NA", "INDEX"))
     assert got == lib.MI355X_CROSSOVERS
+    assert re.search(r"#define LCO_MI355X_INDEX_ALGORITHM LCO_ALG_(\w+)", hdr).group(1) == lib.MI355X_INDEX_ALGORITHM
     assert lib.PAPER_CROSSOVERS == (3.0, 3.0, 3.0)
