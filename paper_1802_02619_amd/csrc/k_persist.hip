@@ -13,13 +13,15 @@
 //   3  each instance's scan of its chunk counts (one item per instance),
 //   4  the scan over instances: every instance's place in the output pool (one item),
 //   5  the numeric product, written to the pool (groups of 64-row chunks).
-// Items are taken from eight queues, one per XCD: queue q holds the q-th
-// eighth of every phase's items in instance order, so the waves of one XCD
+// Items are taken from 64 queues, eight per XCD: the eight queues of XCD x
+// share the x-th eighth of every phase's items in instance order, interleaved
+// (queue j takes every eighth item from the j-th on), so the waves of one XCD
 // work on neighbouring chunks of the same instances (rows that gather the same
-// rows of B' share that XCD's L2).  A wave takes items of phase p from its own
-// queue, then from the other queues, and moves on to phase p + 1 only when
-// every queue has handed out all of phase p; it then waits until every item of
-// phase p is complete.  A wave waits only for items that running waves have
+// rows of B' share that XCD's L2) while the queue heads, one atomic per item
+// taken, are spread over 64 addresses.  A wave takes items of phase p from a
+// queue of its own XCD, then from any queue with items left, and moves on to
+// phase p + 1 only when every queue has handed out all of phase p; it then
+// waits until every item of phase p is complete.  A wave waits only for items that running waves have
 // already taken, so the grid never deadlocks, whatever part of it is resident
 // and whatever else runs on the device; every wait is also bounded and reports
 // through the device error word when it gives up.
@@ -41,7 +43,7 @@ namespace {
 constexpr int kPhases = 6;
 constexpr int64_t kSetupTile = 8192;  // entries per item of phases 0 and 1
 constexpr int kCtlStride = 32;         // control words sit 256 bytes apart
-// Work queues: kSubQueues per XCD, each holding a contiguous range of a
+// Work queues: kSubQueues per XCD, interleaved over the XCD's range of a
 // phase's items (so that the queue heads, one atomic per item taken, are
 // spread over many addresses).
 constexpr uint32_t kSubQueues = 8;

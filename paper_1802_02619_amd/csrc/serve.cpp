@@ -78,6 +78,7 @@ struct lco_server_s {
   bool stop = false;
   std::vector<hipStream_t> streams;
   std::vector<lco_ctx> ctxs;
+  std::vector<std::vector<hipEvent_t>> events;  // per worker: completion events, grown on demand
   std::vector<std::thread> threads;
 };
 
@@ -117,12 +118,31 @@ bool take_batch(lco_server s, std::vector<Request*>& batch) {
 
 void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
   lco_ctx ctx = s->ctxs[w];
+  hipStream_t stream = s->streams[w];
   const int n = (int)batch.size();
   std::vector<lco_tensor> outs(n, nullptr);
   std::vector<lco_status> st(n, LCO_OK);
+  // Each request completes on an event of its own: its result is handed back
+  // once its own work is done, not when the rest of its batch is.  Requests
+  // of one batched call share the call's event (one launch computes them all).
+  std::vector<hipEvent_t>& ev = s->events[w];
+  while ((int)ev.size() < n) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) break;
+    ev.push_back(e);
+  }
+  std::vector<int> done_at(n, -1);  // index of the event that completes request i (-1: synchronise the stream)
+  int nev = 0;
+  auto mark = [&](int first, int last) {
+    if (nev < (int)ev.size() && hipEventRecord(ev[nev], stream) == hipSuccess) {
+      for (int i = first; i < last; ++i) done_at[i] = nev;
+      ++nev;
+    }
+  };
   auto alone = [&](int i) {
     Request* r = batch[i];
     st[i] = lco_contract(ctx, r->a, r->la.data(), r->b, r->lb.data(), r->c_order, r->lc.data(), r->flags, &outs[i]);
+    mark(i, i + 1);
   };
   if (s->cfg.plain || n == 1) {
     // a batch of one takes the per-call path, which is the faster one for a single product
@@ -133,32 +153,49 @@ void run_batch(lco_server s, int w, std::vector<Request*>& batch) {
       Request* r = batch[i];
       d[i] = {r->a, r->la.data(), r->b, r->lb.data(), r->c_order, r->lc.data(), r->flags};
     }
-    if (lco_contract_batch(ctx, n, d.data(), outs.data()) != LCO_OK) {
+    if (lco_contract_batch(ctx, n, d.data(), outs.data()) == LCO_OK) {
+      mark(0, n);
+    } else {
       // isolate the failure: every request gets its own outcome
+      nev = 0;
+      for (int i = 0; i < n; ++i) done_at[i] = -1;
       for (int i = 0; i < n; ++i) alone(i);
     }
   }
-  (void)hipStreamSynchronize(s->streams[w]);
-  const Clock::time_point t_done = Clock::now();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (int i = 0; i < n; ++i) {
-      Request* r = batch[i];
-      if (r->heavy) s->heavy_running = false;
-      r->res.status = st[i];
-      r->res.out = st[i] == LCO_OK ? outs[i] : nullptr;
-      r->res.latency_ms = ms_between(r->arrival, t_done);
-      r->res.queue_ms = ms_between(r->arrival, r->start);
-      r->res.batch_size = n;
-      s->budget_left += r->charged;
-      s->done.push_back(r);
-      s->outstanding--;
+  // hand results back in completion order (the events complete in the order recorded)
+  int i = 0;
+  while (i < n) {
+    int j = i + 1;
+    if (done_at[i] >= 0) {
+      while (j < n && done_at[j] == done_at[i]) ++j;
+      (void)hipEventSynchronize(ev[done_at[i]]);
+    } else {
+      j = n;  // no event: the rest complete together
+      (void)hipStreamSynchronize(stream);
     }
-    // a finished batch frees budget (and possibly the running solo request):
-    // another worker may now take what this one does not
-    if (!s->pending.empty()) wake_one(s);
+    const Clock::time_point t_done = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (int q = i; q < j; ++q) {
+        Request* r = batch[q];
+        if (r->heavy) s->heavy_running = false;
+        r->res.status = st[q];
+        r->res.out = st[q] == LCO_OK ? outs[q] : nullptr;
+        r->res.latency_ms = ms_between(r->arrival, t_done);
+        r->res.queue_ms = ms_between(r->arrival, r->start);
+        r->res.batch_size = n;
+        s->budget_left += r->charged;
+        s->done.push_back(r);
+        s->outstanding--;
+      }
+      // finished requests free budget (and possibly the running solo request):
+      // another worker may now take what this one does not
+      if (!s->pending.empty()) wake_one(s);
+    }
+    s->cv_done.notify_all();
+    i = j;
   }
-  s->cv_done.notify_all();
+  (void)hipStreamSynchronize(stream);  // nothing of this batch is still in flight when the worker moves on
 }
 
 void worker_main(lco_server s, int w) {
@@ -199,6 +236,8 @@ void release(lco_server s) {
   }
   for (Request* r : s->pending) delete r;
   for (lco_ctx c : s->ctxs) lco_ctx_destroy(c);
+  for (auto& v : s->events)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   delete s;
 }
@@ -238,6 +277,7 @@ lco_status lco_server_create(int device, const lco_server_config* cfg, lco_serve
       if (r != LCO_OK) fail(r, "lco_server_create: context creation failed");
       s->ctxs.push_back(c);
     }
+    s->events.resize(cfg->workers);
     s->woken.assign(cfg->workers, 0);
     for (int w = 0; w < cfg->workers; ++w) s->cv_worker.emplace_back(new std::condition_variable);
     for (int w = 0; w < cfg->workers; ++w) s->threads.emplace_back(worker_main, s, w);
