@@ -80,12 +80,16 @@ typedef void (*lco_free_fn)(void* user, void* ptr, size_t bytes, void* stream);
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  If alloc/free are NULL the library
- * uses stream-ordered hipMallocAsync/hipFreeAsync.  *out receives the handle. */
+ * allocates with hipMalloc and keeps the blocks its tensors and scratch
+ * release for reuse in the order of the context's stream (at most 32 GiB
+ * cached; lco_ctx_destroy returns them).  Tensors of a context are destroyed
+ * before it.  *out receives the handle. */
 lco_status lco_ctx_create(int device, void* hip_stream, lco_alloc_fn alloc, lco_free_fn free_fn, void* user,
                           lco_ctx* out);
 /* Destroy a context (waits for its stream first). */
 lco_status lco_ctx_destroy(lco_ctx ctx);
-/* Redirect subsequent work of the context to another stream of the same device. */
+/* Redirect subsequent work of the context to another stream of the same device
+ * (waits for the old stream first). */
 lco_status lco_ctx_set_stream(lco_ctx ctx, void* hip_stream);
 /* Block until all work enqueued by the context has finished. */
 lco_status lco_ctx_synchronize(lco_ctx ctx);
@@ -370,7 +374,7 @@ lco_status lco_batch_plan_destroy(lco_batch_plan p);
  *
  * A request server for contractions (continuous batching).  Requests are
  * submitted as they arrive; `workers` threads each own a HIP stream (default
- * priority) and a context allocating with stream-ordered hipMallocAsync.  A
+ * priority) and a context that keeps its released device blocks for reuse.  A
  * worker that becomes free takes every pending request that fits -- in arrival
  * order, up to `max_batch`, while the sum of their estimated device footprints
  * stays within `hbm_budget` bytes -- and runs them as one lco_contract_batch;

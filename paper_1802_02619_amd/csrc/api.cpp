@@ -100,26 +100,93 @@ LaunchScope::~LaunchScope() {
 }
 
 // ---------------------------------------------------------------- memory
+namespace {
+constexpr size_t kCacheCap = (size_t)32 << 30;  // bytes of released blocks a context keeps at most
+
+size_t block_size(size_t bytes) {
+  if (bytes < ((size_t)1 << 20)) {
+    size_t b = 4096;
+    while (b < bytes) b <<= 1;
+    return b;
+  }
+  const size_t g = (size_t)2 << 20;
+  return (bytes + g - 1) / g * g;
+}
+
+// Returns cached blocks to the device, largest first, until at most `keep`
+// bytes stay cached (the stream is drained first: a block may have been
+// released while work that uses it is still queued).
+void trim_blocks(lco_ctx ctx, size_t keep) {
+  BlockCache& c = ctx->blocks;
+  std::vector<void*> out;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    while (c.cached > keep && !c.free.empty()) {
+      auto it = std::prev(c.free.end());
+      c.cached -= it->first;
+      out.push_back(it->second);
+      c.size.erase(it->second);
+      c.free.erase(it);
+    }
+  }
+  if (out.empty()) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* p : out) (void)hipFree(p);
+}
+}  // namespace
+
 void* dev_alloc(lco_ctx ctx, size_t bytes) {
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
   if (ctx->alloc) {
     p = ctx->alloc(ctx->user, bytes, (void*)ctx->stream);
-  } else {
-    hipError_t e = hipMallocAsync(&p, bytes, ctx->stream);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
+    if (!p) fail(LCO_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+  }
+  const size_t want = block_size(bytes);
+  BlockCache& c = ctx->blocks;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free.lower_bound(want);
+    if (it != c.free.end() && it->first <= want + want / 4) {
+      p = it->second;
+      c.cached -= it->first;
+      c.free.erase(it);
+      return p;
     }
   }
-  if (!p) fail(LCO_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim_blocks(ctx, 0);  // give every cached block back and try once more
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(LCO_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.size[p] = want;
   return p;
 }
 
 void dev_free(lco_ctx ctx, void* p, size_t bytes) {
   if (!p) return;
-  if (ctx->free_fn) ctx->free_fn(ctx->user, p, bytes, (void*)ctx->stream);
-  else (void)hipFreeAsync(p, ctx->stream);
+  if (ctx->free_fn) {
+    ctx->free_fn(ctx->user, p, bytes, (void*)ctx->stream);
+    return;
+  }
+  BlockCache& c = ctx->blocks;
+  bool over = false;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.size.find(p);
+    if (it == c.size.end()) return;  // not a block of this context
+    c.free.emplace(it->second, p);
+    c.cached += it->second;
+    over = c.cached > kCacheCap;
+  }
+  if (over) trim_blocks(ctx, kCacheCap / 2);
 }
 
 Scratch::Scratch(lco_ctx ctx) : ctx_(ctx) {
@@ -417,6 +484,7 @@ lco_status lco_ctx_destroy(lco_ctx ctx) {
   ctx->arena.chunks.clear();
   if (ctx->dev_err) dev_free(ctx, ctx->dev_err, 256);
   (void)hipStreamSynchronize(ctx->stream);
+  trim_blocks(ctx, 0);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return LCO_OK;
@@ -425,6 +493,8 @@ lco_status lco_ctx_destroy(lco_ctx ctx) {
 
 lco_status lco_ctx_set_stream(lco_ctx ctx, void* hip_stream) {
   if (!ctx) return set_error_msg(LCO_E_ARG, "lco_ctx_set_stream: ctx is NULL");
+  // released blocks are reused in stream order: drain the old stream first
+  if ((hipStream_t)hip_stream != ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->stream = (hipStream_t)hip_stream;
   return LCO_OK;
 }

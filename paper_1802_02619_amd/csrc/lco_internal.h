@@ -5,7 +5,9 @@
 #include <stdint.h>
 
 #include <map>
+#include <mutex>
 #include <stdexcept>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -55,6 +57,21 @@ struct Arena {
   size_t fixed_cap = 0;
 };
 
+// ------------------------------------------------------------------ device blocks
+// Device memory a context allocated itself (no allocator callbacks) and has
+// released, kept for reuse.  Every block is used in the order of the
+// context's stream, so a released block can serve the next allocation on that
+// stream at once.  Requests are rounded up (powers of two below 1 MiB,
+// multiples of 2 MiB above); a request takes the smallest cached block of its
+// rounded size up to a quarter more.  Beyond kCacheCap bytes cached, the
+// largest blocks are returned to the device.
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free;       // cached blocks by size
+  std::unordered_map<void*, size_t> size;  // size of every block this cache allocated
+  size_t cached = 0;                       // bytes held in `free`
+};
+
 // ------------------------------------------------------------------ selector
 // Hyper-sparsity up to which the doubly-compressed, no-accumulator and
 // index-cell algorithms give way to CSC/CSR, and the index-sparse x
@@ -76,6 +93,7 @@ struct lco_ctx_s {
   int num_cus = 256;
   size_t max_lds = 65536;
   lco::Arena arena;
+  lco::BlockCache blocks;  // released device blocks (when the library allocates itself)
   int scratch_depth = 0;
   uint64_t* pinned = nullptr;  // host-pinned readback buffer (64 words, device-coherent)
   uint64_t* pinned_dev = nullptr;  // the same buffer as the device addresses it

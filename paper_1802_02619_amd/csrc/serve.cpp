@@ -1,7 +1,7 @@
 // Request server: continuous batching of contractions over worker streams.
 //
 // Each worker thread owns a HIP stream (default priority) and a context that
-// allocates with stream-ordered hipMallocAsync.  A free worker takes every
+// keeps its released device blocks for reuse.  A free worker takes every
 // pending request that fits the device-memory budget, in arrival order, and
 // runs them as one batched contraction (a batch of one as a plain call);
 // requests arriving meanwhile wait for the next free worker, so the batches of
@@ -262,12 +262,6 @@ lco_status lco_server_create(int device, const lco_server_config* cfg, lco_serve
     LCO_HIP(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) fail(LCO_E_ARG, "lco_server_create: no such device");
     LCO_HIP(hipSetDevice(device));
-    // keep freed blocks in the stream-ordered pool instead of returning them at every synchronisation
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-      uint64_t keep = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
     for (int w = 0; w < cfg->workers; ++w) {
       hipStream_t st;
       LCO_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
