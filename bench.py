@@ -531,7 +531,7 @@ def small_leg(lco, ctx, torch, np, L, reps: int):
                         "over (2,3)x(0,1)", "nnz_out": n_out, "reps": reps, **res}
 
 
-def hyper_leg(lco, ctx, torch, np, L, reps: int):
+def hyper_leg(lco, ctx, torch, np, L, reps: int, forced: bool = True):
     """The order-4 hyper-sparse Kronecker pair (2^16 per mode, 2^24 draws each, duplicates summed),
     contracted over (2,3)x(0,1): index-sparse x index-sparse, where the selector measured on MI355X takes
     DCSC (no rearrangement) and the paper's table SOP (B permuted (2,3,0,1)); both are timed."""
@@ -581,7 +581,7 @@ def hyper_leg(lco, ctx, torch, np, L, reps: int):
     # the same product through the other algorithms of the cell (SOP: the paper's table's choice)
     ref = lco.lco_contract(ctx, A, la, B, lb, lc)
     alt = {}
-    for name in [x for x in ("SOP", "DCSC", "DCSR") if x != plan["algo_name"]]:
+    for name in [x for x in ("SOP", "DCSC", "DCSR") if x != plan["algo_name"] and forced]:
         f = lco.ALGO_IDS[name]
         C = lco.lco_contract(ctx, A, la, B, lb, lc, f)
         C.destroy()
@@ -874,6 +874,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small-reps", type=int, default=1000, help="repetitions of the 32x32 leg (0: skip)")
     ap.add_argument("--hyper-reps", type=int, default=5, help="repetitions of the hyper-sparse leg (0: skip)")
+    ap.add_argument("--hyper-selected-only", action="store_true",
+                    help="hyper-sparse leg: time the selected algorithm only (no forced alternatives)")
     ap.add_argument("--app-n", type=int, default=2047, help="image side of the combinatorial Laplacian leg")
     ap.add_argument("--app-reps", type=int, default=5, help="repetitions of the Laplacian leg (0: skip)")
     ap.add_argument("--rp-n", type=int, default=2896, help="side of the Laplacian in the permutation-table leg")
@@ -935,7 +937,8 @@ def main():
         print(json.dumps({"rp_table": rp_leg(lco, ctx, torch, np, L, args.rp_n, max(1, args.rp_reps))}), flush=True)
         return
     if args.hyper_only:
-        print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps))}), flush=True)
+        print(json.dumps({"hyper_sparse": hyper_leg(lco, ctx, torch, np, L, max(1, args.hyper_reps),
+                                                    not args.hyper_selected_only)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_leg(lco, ctx, torch, np, L, args.serve_seconds, args.serve_workers,
@@ -1020,6 +1023,12 @@ def main():
     torch.cuda.synchronize()
     perm_ms = statistics.median(a.elapsed_time(b) for a, b in zip(pe0, pe1))
     perm_gbps = 32.0 * nnz_in / (perm_ms * 1e-3) / 1e9
+    # what the radix passes themselves move: per pass a digit count (8 B read per entry) and a
+    # scatter (16 B read + 16 B written), by the model and by the committed counter summary
+    rp = lco.lco_plan_permute([SIDE] * 6, PERM, nnz_in).as_dict()
+    pass_bytes = rp["passes"] * 40.0 * nnz_in
+    cnt_tr, sct_tr = measured_traffic("rx_count"), measured_traffic("rx_scatter")
+    counter_bytes = rp["passes"] * (cnt_tr + sct_tr) if cnt_tr and sct_tr else None
 
     # ---- roofline of the dominant kernel, from its launches in the timed region
     sizes = {"n": nnz_in, "nnz_a": nnz_in, "nnz_b": nnz_in, "nnz_c": nnz_c, "k": SIDE**3, "rows": SIDE**3}
@@ -1057,7 +1066,10 @@ def main():
         },
         "copy_ceiling_GBps": copy_ceiling(torch),
         "permute": {"ms": perm_ms, "effective_GBps": perm_gbps, "frac_hbm_peak": perm_gbps / HBM_PEAK_GBPS,
-                    "bytes_algorithmic": 32 * nnz_in},
+                    "bytes_algorithmic": 32 * nnz_in, "key_bits": rp["key_bits"], "passes": rp["passes"],
+                    "pass_bytes_model": pass_bytes, "pass_GBps_model": pass_bytes / (perm_ms * 1e-3) / 1e9,
+                    "pass_bytes_counters": counter_bytes,
+                    "pass_GBps_counters": counter_bytes / (perm_ms * 1e-3) / 1e9 if counter_bytes else None},
         "roofline": roof,
         "kernels": kernels,
         "kernels_steps": prof_steps,
