@@ -127,11 +127,13 @@ lco_status lco_ctx_set_index_algorithm(lco_ctx ctx, int algo);
 lco_status lco_ctx_get_index_algorithm(lco_ctx ctx, int* algo);
 /* The selector measured on MI355X with the paper's R-TENSOR sweeps (the
  * benchmark's calibration leg): DCSC overtakes CSC above a column-sparsity of
- * about 8; CSCNA and CSC take the same time at every row-sparsity (the
- * accumulator is a per-row LDS table here, not a dense array of the row count),
- * so NA keeps the paper's 3; in the index-sparse cell DCSC is faster than SOP
- * at every index-sparsity measured and overtakes CSC above about 30. */
-#define LCO_MI355X_DC_CROSSOVER 8.0
+ * about 10 (the two are within a few percent between 6 and 25); CSCNA and CSC
+ * take the same time at every row-sparsity (the accumulator is a per-row LDS
+ * table here, not a dense array of the row count), so NA keeps the paper's 3;
+ * in the index-sparse cell DCSC beats SOP above an index-sparsity of about 19
+ * and CSC above about 30 (within a few percent of CSC from 5 to 100), and on
+ * the 2^16-per-mode Kronecker pair runs in 8.2 ms against SOP's 14.9 ms. */
+#define LCO_MI355X_DC_CROSSOVER 10.0
 #define LCO_MI355X_NA_CROSSOVER 3.0
 #define LCO_MI355X_INDEX_CROSSOVER 30.0
 #define LCO_MI355X_INDEX_ALGORITHM LCO_ALG_DCSC

@@ -379,7 +379,7 @@ def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_label
 # selector crossovers (doubly compressed, no accumulator, index cell): the paper's table as is, and
 # those measured on MI355X (LCO_MI355X_* in include/lco.h), a new context's default
 PAPER_CROSSOVERS = (3.0, 3.0, 3.0)
-MI355X_CROSSOVERS = (8.0, 3.0, 30.0)
+MI355X_CROSSOVERS = (10.0, 3.0, 30.0)
 MI355X_INDEX_ALGORITHM = "DCSC"
 
 
