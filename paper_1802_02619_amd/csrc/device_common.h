@@ -42,6 +42,20 @@ __device__ __forceinline__ T wave_inclusive_scan(T x) {
   return x;
 }
 
+// Inclusive running maximum over the wave (lane order), the same steps with
+// max in place of +; lanes a step does not reach see 0, so the values must
+// be unsigned.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+  uint32_t y;
+  y = dpp_move<kDppRowShr + 1, 0xf, true>(x); x = x > y ? x : y;
+  y = dpp_move<kDppRowShr + 2, 0xf, true>(x); x = x > y ? x : y;
+  y = dpp_move<kDppRowShr + 4, 0xf, true>(x); x = x > y ? x : y;
+  y = dpp_move<kDppRowShr + 8, 0xf, true>(x); x = x > y ? x : y;
+  y = dpp_move<kDppRowBcast15, 0xa, false>(x); x = x > y ? x : y;
+  y = dpp_move<kDppRowBcast31, 0xc, false>(x); x = x > y ? x : y;
+  return x;
+}
+
 __device__ __forceinline__ uint32_t lane_value(uint32_t x, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
 }

@@ -611,8 +611,8 @@ __global__ __launch_bounds__(256) void row_tiny_kernel(RowArgs ra, uint32_t nzr,
 // A row with one A' entry (and more than kTinyProducts products) has as
 // products that entry's B' row scaled, already ascending in column and without
 // repeats: each output is 0.0 + a*b.  Symbolic pass: one thread per row writes
-// the count.  Numeric pass: one wave per row (rows strided over the waves of
-// the grid) copies the row with coalesced loads and stores.
+// the count.  Numeric pass: a wave takes 64 consecutive rows and copies each
+// of their copy rows with coalesced loads and stores.
 template <bool NUMERIC>
 __global__ __launch_bounds__(256) void row_copy_kernel(RowArgs ra, uint32_t nzr, const uint8_t* __restrict__ shape,
                                                        uint64_t* __restrict__ cnt, const uint64_t* __restrict__ coff,
@@ -623,19 +623,37 @@ __global__ __launch_bounds__(256) void row_copy_kernel(RowArgs ra, uint32_t nzr,
       if (shape[r] == kShapeCopy) cnt[r] = ra.elen[ra.row_start[r]];
     return;
   }
+  // Each wave takes 64 consecutive rows: one coalesced load of their shapes,
+  // and every copy row's metadata loaded by its own lane at once; the wave then
+  // copies the chunk's copy rows one after another.
   const int lane = lane_id();
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
-  for (uint32_t r = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; r < nzr; r += waves) {
-    if (shape[r] != kShapeCopy) continue;
-    const uint32_t e0 = ra.row_start[r];
-    const uint64_t row = row_of(ra, r);
-    const uint32_t len = ra.elen[e0], bs = ra.bstart[e0];
-    const uint64_t jn = (ra.a_livs[e0] - ra.kp * row) * ra.np;
-    const double a = ra.a_vals[e0];
-    const uint64_t base = coff[r];
-    for (uint32_t q = lane; q < len; q += kWave) {
-      out_livs[base + q] = (ra.b_livs[bs + q] - jn) + ra.np * row;
-      out_vals[base + q] = 0.0 + a * ra.b_vals[bs + q];
+  for (uint64_t r0 = (uint64_t)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; r0 < nzr;
+       r0 += (uint64_t)waves * kWave) {
+    const uint32_t r = (uint32_t)(r0 + lane);
+    const bool mine = r0 + lane < nzr && shape[r] == kShapeCopy;
+    uint32_t len = 0, bs = 0;
+    uint64_t jn = 0, base = 0, rowc = 0;
+    double a = 0.0;
+    if (mine) {
+      const uint32_t e0 = ra.row_start[r];
+      const uint64_t row = row_of(ra, r);
+      len = ra.elen[e0];
+      bs = ra.bstart[e0];
+      jn = (ra.a_livs[e0] - ra.kp * row) * ra.np;
+      a = ra.a_vals[e0];
+      base = coff[r];
+      rowc = ra.np * row;
+    }
+    for (uint64_t m = __ballot(mine); m; m &= m - 1) {
+      const int src = __builtin_ctzll(m);
+      const uint32_t l = readlane_u32(len, src), b = readlane_u32(bs, src);
+      const uint64_t j = readlane_u64(jn, src), o = readlane_u64(base, src), rc = readlane_u64(rowc, src);
+      const double av = __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(a), src));
+      for (uint32_t q = lane; q < l; q += kWave) {
+        out_livs[o + q] = (ra.b_livs[b + q] - j) + rc;
+        out_vals[o + q] = 0.0 + av * ra.b_vals[b + q];
+      }
     }
   }
 }
@@ -725,22 +743,14 @@ constexpr int kMidBits = 12;
 constexpr int kMidMax = 1 << kMidBits;
 constexpr int kMidWaveMax = 256;  // rows of at most this many products take one wave
 
-// Expands product p of a long row (A' entries [e0, e1), first product offset p0)
-// into its sort key (column << pbits | p) and value.
-__device__ __forceinline__ void mid_product(const RowArgs& ra, uint32_t e0, uint32_t e1, uint64_t p0, uint64_t row,
-                                            uint32_t p, int pbits, uint64_t& key, double& val) {
-  // last A' entry e in [e0, e1) with poff[e] <= p0 + p
-  uint32_t lo = e0, hi = e1 - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (ra.poff[mid] <= p0 + p) lo = mid;
-    else hi = mid - 1;
-  }
-  const uint64_t j = ra.a_livs[lo] - ra.kp * row;
-  const uint32_t q = ra.bstart[lo] + (uint32_t)(p0 + p - ra.poff[lo]);
+// Product p of a long row from its A' entry e (absolute index).
+__device__ __forceinline__ void mid_product_of(const RowArgs& ra, uint32_t e, uint64_t p0, uint64_t row, uint32_t p,
+                                               int pbits, uint64_t& key, double& val) {
+  const uint64_t j = ra.a_livs[e] - ra.kp * row;
+  const uint32_t q = ra.bstart[e] + (uint32_t)(p0 + p - ra.poff[e]);
   const uint64_t col = ra.b_livs[q] - ra.np * j;
   key = (col << pbits) | p;
-  val = ra.a_vals[lo] * ra.b_vals[q];
+  val = ra.a_vals[e] * ra.b_vals[q];
 }
 
 __device__ __forceinline__ int mid_bits(uint64_t f) {
@@ -751,7 +761,8 @@ __device__ __forceinline__ int mid_bits(uint64_t f) {
 
 // One wave per row of at most kMidWaveMax products (four rows per block).
 __global__ __launch_bounds__(kMidThreads) void row_midw_kernel(RowArgs ra, const uint32_t* __restrict__ list,
-                                                               uint32_t count, const uint64_t* __restrict__ f2,
+                                                               const uint32_t* __restrict__ bin, uint32_t count,
+                                                               const uint64_t* __restrict__ f2,
                                                                const uint64_t* __restrict__ moff,
                                                                uint64_t* __restrict__ cnt,
                                                                uint64_t* __restrict__ tmp_livs,
@@ -763,22 +774,54 @@ __global__ __launch_bounds__(kMidThreads) void row_midw_kernel(RowArgs ra, const
   const int lane = lane_id(), w = threadIdx.x / kWave;
   uint64_t* skey = skey_all[w];
   double* sval = sval_all[w];
-  for (uint32_t li = blockIdx.x * kWaves + w; li < count; li += gridDim.x * kWaves) {
+  for (uint32_t k = blockIdx.x * kWaves + w; k < count; k += gridDim.x * kWaves) {
+    const uint32_t li = bin[k];
     const uint64_t f = f2[li];
-    if (f > (uint64_t)kMidWaveMax) continue;  // uniform over the wave
     const uint32_t r = list[li];
     const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
     const uint64_t p0 = ra.poff[e0];
     const uint64_t row = row_of(ra, r);
     const int pbits = mid_bits(f);
     const uint32_t P = 1u << pbits;
+    // Each product's A' entry: every entry with products marks its first
+    // product's position, and a running maximum over the positions (entries
+    // come in product order) hands every position its entry.  The marks use
+    // the value area, which the expansion fills afterwards.
+    uint32_t* ent = reinterpret_cast<uint32_t*>(sval);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) ent[i * kWave + lane] = 0;
+    wave_lds_sync();
+    for (uint32_t e = lane; e < e1 - e0; e += kWave) {
+      const uint64_t a = ra.poff[e0 + e] - p0, b = ra.poff[e0 + e + 1] - p0;
+      if (b > a) ent[a] = e;
+    }
+    wave_lds_sync();
+    {
+      uint32_t top = 0, seg[kPer];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {  // this lane's positions kPer * lane + i
+        const uint32_t x = ent[kPer * lane + i];
+        top = x > top ? x : top;
+        seg[i] = top;
+      }
+      const uint32_t incl = wave_inclusive_max(top);
+      uint32_t before = (uint32_t)__shfl_up((int)incl, 1, kWave);
+      if (lane == 0) before = 0;
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) ent[kPer * lane + i] = seg[i] > before ? seg[i] : before;
+    }
+    wave_lds_sync();
+    uint32_t mine[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) mine[i] = ent[i * kWave + lane];
+    wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const uint32_t p = (uint32_t)(i * kWave + lane);
       if (p < P) {
         uint64_t key = ~0ull;  // padding sorts last
         double v = 0.0;
-        if (p < f) mid_product(ra, e0, e1, p0, row, p, pbits, key, v);
+        if (p < f) mid_product_of(ra, e0 + mine[i], p0, row, p, pbits, key, v);
         skey[p] = key;
         sval[p] = v;
       }
@@ -827,8 +870,9 @@ __global__ __launch_bounds__(kMidThreads) void row_midw_kernel(RowArgs ra, const
 // One block per row of more than fmin and at most MAXP products.
 template <int MAXP>
 __global__ __launch_bounds__(kMidThreads) void row_mid_kernel(RowArgs ra, const uint32_t* __restrict__ list,
-                                                              uint32_t count, const uint64_t* __restrict__ f2,
-                                                              uint64_t fmin, const uint64_t* __restrict__ moff,
+                                                              const uint32_t* __restrict__ bin, uint32_t count,
+                                                              const uint64_t* __restrict__ f2,
+                                                              const uint64_t* __restrict__ moff,
                                                               uint64_t* __restrict__ cnt,
                                                               uint64_t* __restrict__ tmp_livs,
                                                               double* __restrict__ tmp_vals) {
@@ -836,36 +880,90 @@ __global__ __launch_bounds__(kMidThreads) void row_mid_kernel(RowArgs ra, const 
   __shared__ double sval[MAXP];
   __shared__ uint32_t wsum[kMidThreads / kWave + 1];
   const uint32_t tid = threadIdx.x;
-  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+  for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const uint32_t li = bin[k];
     const uint64_t f = f2[li];
-    if (f <= fmin || f > (uint64_t)MAXP) continue;  // uniform over the block
     const uint32_t r = list[li];
     const uint32_t e0 = ra.row_start[r], e1 = ra.row_start[r + 1];
     const uint64_t p0 = ra.poff[e0];
     const uint64_t row = row_of(ra, r);
     const int pbits = mid_bits(f);
     const uint32_t P = 1u << pbits;
-    for (uint32_t p = tid; p < P; p += kMidThreads) {
-      uint64_t key = ~0ull;
-      double v = 0.0;
-      if (p < f) mid_product(ra, e0, e1, p0, row, p, pbits, key, v);
-      skey[p] = key;
-      sval[p] = v;
+    // each product's A' entry, as in the one-wave kernel: marks, then a running
+    // maximum over the positions (thread i takes positions i*S .. i*S + S - 1)
+    constexpr int kMaxPer = MAXP / kMidThreads;
+    uint32_t* ent = reinterpret_cast<uint32_t*>(sval);
+    for (uint32_t p = tid; p < P; p += kMidThreads) ent[p] = 0;
+    __syncthreads();
+    for (uint32_t e = tid; e < e1 - e0; e += kMidThreads) {
+      const uint64_t a = ra.poff[e0 + e] - p0, b = ra.poff[e0 + e + 1] - p0;
+      if (b > a) ent[a] = e;
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tid; i < P / 2; i += kMidThreads) {
-          const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-          const uint32_t hi = lo | j;
-          const uint64_t a = skey[lo], b = skey[hi];
-          if ((a > b) == ((lo & k) == 0)) {
-            skey[lo] = b;
-            skey[hi] = a;
-          }
-        }
-        __syncthreads();
+    {
+      const uint32_t S = P / kMidThreads;
+      uint32_t run = 0;
+      for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t x = ent[tid * S + i];
+        run = x > run ? x : run;
       }
+      const uint32_t incl = wave_inclusive_max(run);
+      const int lane = lane_id(), wv = (int)(tid / kWave);
+      if (lane == kWave - 1) wsum[wv] = incl;
+      uint32_t before = (uint32_t)__shfl_up((int)incl, 1, kWave);
+      if (lane == 0) before = 0;
+      __syncthreads();
+      for (int q = 0; q < wv; ++q) before = wsum[q] > before ? wsum[q] : before;
+      run = before;
+      for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t x = ent[tid * S + i];
+        run = x > run ? x : run;
+        ent[tid * S + i] = run;
+      }
+    }
+    __syncthreads();
+    uint32_t mine[kMaxPer];
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+      const uint32_t p = tid + (uint32_t)i * kMidThreads;
+      mine[i] = p < P ? ent[p] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+      const uint32_t p = tid + (uint32_t)i * kMidThreads;
+      if (p < P) {
+        uint64_t key = ~0ull;
+        double v = 0.0;
+        if (p < f) mid_product_of(ra, e0 + mine[i], p0, row, p, pbits, key, v);
+        skey[p] = key;
+        sval[p] = v;
+      }
+    }
+    __syncthreads();
+    // Wave w owns pairs w*P/8 .. (w+1)*P/8 - 1, i.e. elements w*P/4 .. (w+1)*P/4 - 1
+    // while j <= P/8: those stages need only the wave's own order; the few
+    // with larger j are fenced by block barriers.
+    {
+      const uint32_t per_wave = P / 8, lane = (uint32_t)lane_id(), wv = tid / kWave;
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          const bool wide = j > per_wave;
+          if (wide) __syncthreads();
+          for (uint32_t i = wv * per_wave + lane; i < (wv + 1) * per_wave; i += kWave) {
+            const uint32_t lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+            const uint32_t hi = lo | j;
+            const uint64_t a = skey[lo], b = skey[hi];
+            if ((a > b) == ((lo & k) == 0)) {
+              skey[lo] = b;
+              skey[hi] = a;
+            }
+          }
+          if (wide) __syncthreads();
+          else wave_lds_sync();
+        }
+      }
+      __syncthreads();
     }
     const uint64_t base = moff[li];
     uint64_t run = 0;
@@ -888,16 +986,19 @@ __global__ __launch_bounds__(kMidThreads) void row_mid_kernel(RowArgs ra, const 
   }
 }
 
-// Moves each staged long row to its place in C (one wave per row).
-__global__ void row_mid_copy_kernel(const uint32_t* __restrict__ list, uint32_t count,
-                                    const uint64_t* __restrict__ moff, const uint64_t* __restrict__ coff,
-                                    const uint64_t* __restrict__ tmp_livs, const double* __restrict__ tmp_vals,
-                                    uint64_t* __restrict__ out_livs, double* __restrict__ out_vals) {
+// Moves each staged long row to its place in C (one wave per row; the rows
+// are those of the bin lists, `n` apart, with counts c0, c1, c2).
+__global__ void row_mid_copy_kernel(const uint32_t* __restrict__ list, const uint32_t* __restrict__ bins, uint32_t n,
+                                    uint32_t c0, uint32_t c1, uint32_t c2, const uint64_t* __restrict__ moff,
+                                    const uint64_t* __restrict__ coff, const uint64_t* __restrict__ tmp_livs,
+                                    const double* __restrict__ tmp_vals, uint64_t* __restrict__ out_livs,
+                                    double* __restrict__ out_vals) {
   const int lane = lane_id();
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
-  for (uint32_t li = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; li < count; li += waves) {
+  const uint32_t total = c0 + c1 + c2;
+  for (uint32_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < total; k += waves) {
+    const uint32_t li = k < c0 ? bins[k] : k < c0 + c1 ? bins[n + (k - c0)] : bins[2 * (uint64_t)n + (k - c0 - c1)];
     const uint64_t src = moff[li];
-    if (moff[li + 1] == src) continue;  // a row of the global path
     const uint32_t r = list[li];
     const uint64_t dst = coff[r], n = coff[r + 1] - dst;
     for (uint64_t q = lane; q < n; q += kWave) {
@@ -908,13 +1009,37 @@ __global__ void row_mid_copy_kernel(const uint32_t* __restrict__ list, uint32_t 
 }
 
 // Product counts of the long rows of the global path (g2) and of the in-LDS
-// path (m2), each zero for the other path's rows.
-__global__ void long_split_kernel(const uint64_t* __restrict__ f2, int64_t n, uint64_t fmax, uint64_t* __restrict__ g2,
-                                  uint64_t* __restrict__ m2) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t f = f2[i];
-    g2[i] = f > fmax ? f : 0;
-    m2[i] = f > fmax ? 0 : f;
+// path (m2), each zero for the other path's rows; the in-LDS rows are also
+// listed by size bin (at most kMidWaveMax, 1024 and kMidMax products: bin b's
+// list positions at bins + b * n, its count in bin_cnt[b], cleared before).
+// Whole waves step together (one list reservation per wave and bin).
+constexpr int kMidBins = 3;
+__device__ __forceinline__ int mid_bin(uint64_t f) {
+  return f <= (uint64_t)kMidWaveMax ? 0 : f <= 1024 ? 1 : f <= (uint64_t)kMidMax ? 2 : -1;
+}
+__global__ void long_split_kernel(const uint64_t* __restrict__ f2, int64_t n, uint64_t* __restrict__ g2,
+                                  uint64_t* __restrict__ m2, uint32_t* __restrict__ bins,
+                                  unsigned long long* __restrict__ bin_cnt) {
+  const int lane = lane_id();
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < n;
+       i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + lane;
+    int b = -1;
+    if (i < n) {
+      const uint64_t f = f2[i];
+      b = mid_bin(f);
+      g2[i] = b < 0 ? f : 0;
+      m2[i] = b < 0 ? 0 : f;
+    }
+#pragma unroll
+    for (int q = 0; q < kMidBins; ++q) {
+      const uint64_t m = __ballot(b == q);
+      if (!m) continue;
+      unsigned long long base = 0;
+      if (lane == __builtin_ctzll(m)) base = atomicAdd(&bin_cnt[q], (unsigned long long)__popcll(m));
+      base = __shfl(base, __builtin_ctzll(m), kWave);
+      if (b == q) bins[(int64_t)q * n + (int64_t)(base + __popcll(m & lanemask_lt()))] = (uint32_t)i;
+    }
   }
 }
 
@@ -1047,10 +1172,13 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   const uint64_t nzr = h[0], n2 = h[1];
   const bool tiny = h[2] != 0, copy = h[3] != 0, wave = h[4] != 0;
   const int tiny_grid = grid_for(ctx, (int64_t)nzr, 256);  // 64 rows per wave and sweep
-  const int copy_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nzr + 3) / 4, (uint64_t)ctx->num_cus * 8));
+  const int copy_grid = tiny_grid;  // 64 rows per wave and sweep as well
   uint64_t f2_total = 0, mid_total = 0;
   uint64_t* off2 = nullptr;
   uint64_t* moff = nullptr;
+  uint64_t* bin_cnt = nullptr;
+  uint32_t* bins = nullptr;
+  uint64_t nbin[kMidBins] = {0, 0, 0};
   // long rows of at most kMidMax products are computed in LDS (their keys pack
   // the column and the product index into 63 bits); the rest take the global sort
   const int colbits = bits_for(np - 1);
@@ -1061,21 +1189,25 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     ra.poff = poff;
     off2 = s.get<uint64_t>(n2 + 1);
     moff = s.get<uint64_t>(n2 + 1);
+    bin_cnt = s.get<uint64_t>(kMidBins);
+    memset_async(ctx, bin_cnt, 0, kMidBins * sizeof(uint64_t));
     if (mid) {
       uint64_t* g2 = s.get<uint64_t>(n2);
       uint64_t* m2 = s.get<uint64_t>(n2);
+      bins = s.get<uint32_t>((size_t)kMidBins * n2);
       LCO_LAUNCH(ctx, "long_split", long_split_kernel, grid_for(ctx, (int64_t)n2, 256), 256, 0, (const uint64_t*)f2,
-                 (int64_t)n2, (uint64_t)kMidMax, g2, m2);
+                 (int64_t)n2, g2, m2, bins, (unsigned long long*)bin_cnt);
       scan_u64(ctx, g2, off2, (int64_t)n2, off2 + n2);
       scan_u64(ctx, m2, moff, (int64_t)n2, moff + n2);
     } else {
       scan_u64(ctx, f2, off2, (int64_t)n2, off2 + n2);
       memset_async(ctx, moff + n2, 0, sizeof(uint64_t));
     }
-    const uint64_t* rb[2] = {off2 + n2, moff + n2};
-    const uint64_t* h2 = readback(ctx, rb, 2);
+    const uint64_t* rb[5] = {off2 + n2, moff + n2, bin_cnt, bin_cnt + 1, bin_cnt + 2};
+    const uint64_t* h2 = readback(ctx, rb, 5);
     f2_total = h2[0];
     mid_total = h2[1];
+    for (int b = 0; b < kMidBins; ++b) nbin[b] = h2[2 + b];
   }
   // per-row output counts
   uint64_t* cnt = s.get<uint64_t>(nzr + 1);
@@ -1114,18 +1246,22 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   // long rows of the in-LDS path: computed now, staged, moved once placed
   uint64_t* mid_livs = nullptr;
   double* mid_vals = nullptr;
-  const int mid_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(n2, (uint64_t)ctx->num_cus * 8));
+  auto cap_grid = [&](uint64_t want) { return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)ctx->num_cus * 8)); };
   if (mid_total) {
     mid_livs = s.get<uint64_t>(mid_total);
     mid_vals = s.get<double>(mid_total);
-    const int midw_grid =
-        (int)std::max<uint64_t>(1, std::min<uint64_t>((n2 + 3) / 4, (uint64_t)ctx->num_cus * 8));
-    LCO_LAUNCH(ctx, "row_mid", row_midw_kernel, midw_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
-               (const uint64_t*)f2, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
-    LCO_LAUNCH(ctx, "row_mid", row_mid_kernel<1024>, mid_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
-               (const uint64_t*)f2, (uint64_t)kMidWaveMax, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
-    LCO_LAUNCH(ctx, "row_mid", row_mid_kernel<kMidMax>, mid_grid, kMidThreads, 0, ra, list2, (uint32_t)n2,
-               (const uint64_t*)f2, (uint64_t)1024, (const uint64_t*)moff, cnt, mid_livs, mid_vals);
+    if (nbin[0])
+      LCO_LAUNCH(ctx, "row_mid_wave", row_midw_kernel, cap_grid((nbin[0] + 3) / 4), kMidThreads, 0, ra, list2,
+                 (const uint32_t*)bins, (uint32_t)nbin[0], (const uint64_t*)f2, (const uint64_t*)moff, cnt, mid_livs,
+                 mid_vals);
+    if (nbin[1])
+      LCO_LAUNCH(ctx, "row_mid_1024", row_mid_kernel<1024>, cap_grid(nbin[1]), kMidThreads, 0, ra, list2,
+                 (const uint32_t*)(bins + n2), (uint32_t)nbin[1], (const uint64_t*)f2, (const uint64_t*)moff, cnt,
+                 mid_livs, mid_vals);
+    if (nbin[2])
+      LCO_LAUNCH(ctx, "row_mid_4096", row_mid_kernel<kMidMax>, cap_grid(nbin[2]), kMidThreads, 0, ra, list2,
+                 (const uint32_t*)(bins + 2 * n2), (uint32_t)nbin[2], (const uint64_t*)f2, (const uint64_t*)moff, cnt,
+                 mid_livs, mid_vals);
   }
   // other long rows: expand, sort by (row rank, column), count distinct
   uint64_t* keys = nullptr;
@@ -1164,9 +1300,10 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
       LCO_LAUNCH(ctx, "row_copy_num", row_copy_kernel<true>, copy_grid, 256, 0, ra, (uint32_t)nzr,
                  (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
     if (mid_total)
-      LCO_LAUNCH(ctx, "row_mid_copy", row_mid_copy_kernel, mid_grid, 256, 0, (const uint32_t*)list2, (uint32_t)n2,
-                 (const uint64_t*)moff, (const uint64_t*)coff, (const uint64_t*)mid_livs, (const double*)mid_vals,
-                 C->livs, C->vals);
+      LCO_LAUNCH(ctx, "row_mid_copy", row_mid_copy_kernel, cap_grid((nbin[0] + nbin[1] + nbin[2] + 3) / 4), 256, 0,
+                 (const uint32_t*)list2, (const uint32_t*)bins, (uint32_t)n2, (uint32_t)nbin[0], (uint32_t)nbin[1],
+                 (uint32_t)nbin[2], (const uint64_t*)moff, (const uint64_t*)coff, (const uint64_t*)mid_livs,
+                 (const double*)mid_vals, C->livs, C->vals);
     if (f2_total)
       LCO_LAUNCH(ctx, "big_reduce_num", big_reduce_kernel<true>, big_grid, kBigThreads, 0, ra, list2, (uint32_t)n2,
                  off2, (const uint64_t*)keys, (const double*)pvals, colmask, (uint64_t*)nullptr,

@@ -88,15 +88,6 @@ constexpr int kSopWaves = kSopThreads / kWave;
 constexpr int kSopQuarter = kSopTile / kSopWaves;  // positions scanned by one wave
 static_assert(kSopWaves == 4, "the running maximum is combined over four quarters");
 
-__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t t = __shfl_up(x, o, kWave);
-    if (lane >= o) x = t > x ? t : x;
-  }
-  return x;
-}
 
 __global__ __launch_bounds__(kSopThreads) void sop_expand_kernel(SopArgs sa, uint64_t f, uint64_t* __restrict__ keys,
                                                                  double* __restrict__ vals) {
