@@ -201,10 +201,15 @@ def lco_version() -> str:
 
 # ------------------------------------------------------------------ context
 class Context:
-    """A library context on one device and stream, allocating through torch."""
+    """A library context on one device and stream.  With allocator="torch" (the default) device memory
+    comes from torch's caching allocator and livs()/vals() are torch views; with allocator="library"
+    the library allocates itself (hipMalloc, with released blocks reused in stream order) and tensors
+    are read with to_numpy()."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, allocator: str = "torch"):
         import torch
+        if allocator not in ("torch", "library"):
+            raise ValueError("allocator must be 'torch' or 'library'")
         L = load_library()
         self._torch = torch
         self.device = int(device)
@@ -213,6 +218,12 @@ class Context:
             stream = torch.cuda.current_stream(self._dev)
         self.stream = stream
         self._allocs = {}
+        if allocator == "library":
+            h = ctypes.c_void_p()
+            _check(L.lco_ctx_create(self.device, ctypes.c_void_p(stream.cuda_stream), ctypes.cast(None, _ALLOC_FN),
+                                    ctypes.cast(None, _FREE_FN), None, ctypes.byref(h)))
+            self.handle = h
+            return
 
         def _alloc(user, nbytes, strm):
             try:
@@ -237,13 +248,19 @@ class Context:
     def synchronize(self):
         _check(load_library().lco_ctx_synchronize(self.handle))
 
+    def set_stream(self, stream):
+        """Move the context's later work to another torch stream of its device (waits for the old one)."""
+        _check(load_library().lco_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def destroy(self):
         if self.handle:
             _check(load_library().lco_ctx_destroy(self.handle))
             self.handle = None
 
     def view(self, ptr: int, nbytes: int, dtype):
-        """torch view of `nbytes` at device pointer `ptr` inside one of this context's allocations."""
+        """torch view of `nbytes` at device pointer `ptr` inside one of this context's allocations
+        (torch-allocating contexts only)."""
         t = self._allocs.get(ptr)
         if t is not None:
             return t[:nbytes].view(dtype)
@@ -251,11 +268,12 @@ class Context:
             if start <= ptr and ptr + nbytes <= start + buf.numel():
                 off = ptr - start
                 return buf[off:off + nbytes].view(dtype)
-        raise KeyError("pointer is not inside a library allocation")
+        raise KeyError("pointer is not inside a torch allocation of this context (library-allocating contexts: "
+                       "read tensors with to_numpy())")
 
 
-def lco_ctx_create(device: int = 0, stream=None) -> Context:
-    return Context(device, stream)
+def lco_ctx_create(device: int = 0, stream=None, allocator: str = "torch") -> Context:
+    return Context(device, stream, allocator)
 
 
 def lco_ctx_destroy(ctx: Context):
