@@ -367,6 +367,34 @@ def test_many_entry_rows_and_row_table(lco_lib, gpu_ctx, oracle_mod, lc):
 
 
 @pytest.mark.parametrize("lc", [[0, 2], [2, 0]])
+def test_doubly_compressed_ids_near_2e57(lco_lib, gpu_ctx, oracle_mod, lc):
+    """A contracted index of 2^57 values: no row pointer array fits, so only the doubly compressed
+    (and outer-product) algorithms run. The hash table of B's rows holds ids at both ends of the
+    range (0, 1, 2^57 - 1, 2^57 - 2), ids one apart and 2^40 apart, and ids that no entry of A
+    selects; A selects absent ids as well."""
+    rng = np.random.default_rng(57)
+    m, k, n = 70, 1 << 57, 90
+    ids = [0, 1, 2, k - 1, k - 2, k - 3] + [(1 << 40) * i for i in range(1, 40)] + \
+          [int(x) for x in rng.integers(0, k, 200, dtype=np.int64)]
+    ids = sorted(set(ids))
+    cb = np.array(sorted({(j, int(c)) for j in ids for c in rng.choice(n, 1 + j % 5, replace=False)}), dtype=np.uint64)
+    vb = rng.uniform(-1, 1, len(cb))
+    absent = sorted(set(int(x) for x in rng.integers(0, k, 300, dtype=np.int64)) - set(ids))
+    ca = np.array(sorted({(i, int(c)) for i in range(m)
+                          for c in list(rng.choice(ids, 4 + i % 9, replace=False)) + list(rng.choice(absent, 3, replace=False))}),
+                  dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [m, k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, [k, n], cb, vb)
+    p = lco_lib.lco_plan_info(gpu_ctx, ga, [0, 1], gb, [1, 2], lc)
+    assert lco_lib.ALGOS[p.algo] in ("DCSC", "DCSR")
+    run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, [1, 2], lc, exact=True,
+            algos=("auto", "DCSC", "DCSR", "SOP"))
+    for t in (ga, gb):
+        t.destroy()
+
+
+@pytest.mark.parametrize("lc", [[0, 2], [2, 0]])
 def test_clustered_rows_long_pointer_runs(lco_lib, gpu_ctx, oracle_mod, lc):
     """Rows clustered at both ends of their ranges leave runs of thousands of
     empty rows between them, which whole waves write: B's rows are the first and
