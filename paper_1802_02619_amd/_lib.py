@@ -453,22 +453,50 @@ class ContractDesc(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+def _handle_value(h) -> int:
+    return (h.value or 0) if isinstance(h, ctypes.c_void_p) else int(h)
+
+
+def _desc_array(items):
+    """lco_contract_desc records of `items` (a, a_labels, b, b_labels, c_labels[, flags]) as a numpy
+    array laid out like ContractDesc, and the label arrays it points to (one per distinct list)."""
+    import numpy as np
+    n = len(items)
+    dt = np.dtype({"names": [f for f, _ in ContractDesc._fields_],
+                   "formats": ["u8", "u8", "u8", "u8", "i4", "u8", "u4"],
+                   "offsets": [getattr(ContractDesc, f).offset for f, _ in ContractDesc._fields_],
+                   "itemsize": ctypes.sizeof(ContractDesc)})
+    rec = np.zeros(max(1, n), dtype=dt)
+    labels = {}
+
+    def lab(x):
+        k = tuple(x)
+        a = labels.get(k)
+        if a is None:
+            a = labels[k] = _i32arr(k)
+        return ctypes.addressof(a)
+
+    if n:
+        rec["a"][:n] = [_handle_value(it[0].handle) for it in items]
+        rec["a_labels"][:n] = [lab(it[1]) for it in items]
+        rec["b"][:n] = [_handle_value(it[2].handle) for it in items]
+        rec["b_labels"][:n] = [lab(it[3]) for it in items]
+        rec["c_order"][:n] = [len(it[4]) for it in items]
+        rec["c_labels"][:n] = [lab(it[4]) for it in items]
+        rec["flags"][:n] = [int(it[5]) if len(it) > 5 else 0 for it in items]
+    return rec, labels
+
+
 def lco_contract_batch(ctx: Context, items):
     """Batched products; `items` is a list of (a, a_labels, b, b_labels, c_labels[, flags]).
     Returns the list of result tensors (bit-identical to lco_contract on each item)."""
     L = load_library()
     n = len(items)
-    keep = []
-    descs = (ContractDesc * max(1, n))()
-    for i, it in enumerate(items):
-        a, la, b, lb, lc = it[:5]
-        flags = it[5] if len(it) > 5 else 0
-        arrs = (_i32arr(la), _i32arr(lb), _i32arr(lc))
-        keep.append(arrs)
-        descs[i] = ContractDesc(a.handle, arrs[0], b.handle, arrs[1], len(lc), arrs[2], int(flags))
+    rec, labels = _desc_array(items)
     outs = (ctypes.c_void_p * max(1, n))()
-    _check(L.lco_contract_batch(ctx.handle, n, descs, outs))
-    return [Tensor(ctx, ctypes.c_void_p(outs[i])) for i in range(n)]
+    _check(L.lco_contract_batch(ctx.handle, n, ctypes.cast(rec.ctypes.data, ctypes.POINTER(ContractDesc)), outs))
+    del labels  # the label arrays live until the call has returned
+    return [Tensor(ctx, h) for h in outs[:n]]  # plain integer handles
 
 
 class _Borrowed(Tensor):
@@ -479,15 +507,8 @@ class _Borrowed(Tensor):
 
 
 def _descs(items):
-    keep = []
-    descs = (ContractDesc * max(1, len(items)))()
-    for i, it in enumerate(items):
-        a, la, b, lb, lc = it[:5]
-        flags = it[5] if len(it) > 5 else 0
-        arrs = (_i32arr(la), _i32arr(lb), _i32arr(lc))
-        keep.append(arrs)
-        descs[i] = ContractDesc(a.handle, arrs[0], b.handle, arrs[1], len(lc), arrs[2], int(flags))
-    return descs, keep
+    rec, labels = _desc_array(items)
+    return ctypes.cast(rec.ctypes.data, ctypes.POINTER(ContractDesc)), (rec, labels)
 
 
 class BatchPlan:

@@ -465,10 +465,12 @@ __device__ __forceinline__ bool wait_phase(const PArgs& g, int p, int lane) {
   return ok != 0;
 }
 
-// The sizing launch is held to 8 waves per SIMD (64 VGPRs), the launches with
-// the numeric phase to 6 (80 VGPRs), the fastest bounds measured.
+// Waves per SIMD, the fastest bounds measured on the 4096-instance FD batch:
+// the sizing launch 7 (72 VGPRs; at 8 it spills 27 VGPRs), the numeric launch
+// 6 (80), and the launch of every phase 5 (96 VGPRs: at 6 it spills 32 and
+// takes 13 % longer).
 template <bool NARROW, int MODE, int BRANCH>
-__global__ __launch_bounds__(kRowThreads, MODE == kModeSize ? 8 : 6) void bt_persist_kernel(
+__global__ __launch_bounds__(kRowThreads, MODE == kModeSize ? 7 : (MODE == kModeAll ? 5 : 6)) void bt_persist_kernel(
     const PArgs* __restrict__ gp) {
   // the arguments are read from device memory where they are used (scalar
   // loads), rather than held in registers for the whole kernel
