@@ -446,7 +446,10 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
       if (NUMERIC) m_off = coff[r];
     }
     uint32_t my_cnt = 0;
-    int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+    // The window [w0, w0 + 64) of A' entries (entry indexes are 32-bit here, so
+    // the window tests are scalar compares); none is loaded before the first row.
+    bool have = false;
+    uint32_t w0 = 0;
     // window lane l: entry w0 + l's product count, B' row start, value, and
     // j * n' (the LIV of its B' row's first position, j = its contracted index)
     uint32_t x_len = 0, x_bs = 0;
@@ -457,13 +460,16 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
     // current row is reduced, so that their latency overlaps its LDS work.
     uint64_t todo = __ballot(lane < rows && m_sh <= kShapeSearch);
     RowProduct<NUMERIC> next;
+    int t_next = 0;
     auto stage = [&](int i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
-      if ((int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
+      t_next = (int)(e1 - e0);  // at most 64 for the rows of this kernel
+      if (!have || e0 - w0 > (uint32_t)(kWave - t_next)) {
+        have = true;
         w0 = e0;
-        const int64_t e = w0 + lane;
-        if (e < ra.nnz_a) {
+        const uint64_t e = (uint64_t)w0 + (uint32_t)lane;
+        if (e < (uint64_t)ra.nnz_a) {
           x_len = ra.elen[e];
           x_bs = ra.bstart[e];
           uint64_t j;
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
           if (NUMERIC) x_av = ra.a_vals[e];
         }
       }
-      window_products<NUMERIC>(ra.b_livs, ra.b_vals, e0, (int)(e1 - e0), sh, lane, w0, x_len, x_bs, x_jn, x_av,
+      window_products<NUMERIC>(ra.b_livs, ra.b_vals, e0, t_next, sh, lane, (int64_t)w0, x_len, x_bs, x_jn, x_av,
                                next);
     };
     if (todo) stage(__builtin_ctzll(todo));
@@ -483,16 +489,20 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
       const int ent = next.ent;
       const uint64_t col = next.col();
       const double v = next.val();
-      const int t = (int)(readlane_u32(m_s1, i) - readlane_u32(m_s0, i));
+      const int t = t_next;
       if (todo) stage(__builtin_ctzll(todo));
       RowOut o;
       const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, lane, s_lds[w], o);
       if (!NUMERIC) {
         if (lane == i) my_cnt = d;
       } else if (o.own) {
-        const uint64_t pos = readlane_u64(m_off, i) + o.rank;
-        out_livs[pos] = o.col + ra.np * readlane_u64(m_id, i);
-        out_vals[pos] = o.val;
+        // the row's output range starts at a wave-uniform address; the rank
+        // (below 64) is the per-lane offset
+        const uint64_t r_off = readlane_u64(m_off, i);
+        const uint32_t boff = o.rank * 8u;
+        *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(out_livs + r_off) + boff) =
+            o.col + ra.np * readlane_u64(m_id, i);
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(out_vals + r_off) + boff) = o.val;
       }
     }
     if (!NUMERIC && lane < rows) cnt[r0 + lane] = my_cnt;

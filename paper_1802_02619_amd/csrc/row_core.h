@@ -312,18 +312,29 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
     if constexpr (NUMERIC) {
       // Probe until the slot is empty (this lane inserts the column) or holds
       // the column; at most 64 columns in 128 slots, so a free slot always
-      // exists.  Only lanes still probing take part in a probe.
+      // exists and every probe sequence ends.  Only lanes still probing take
+      // part in a probe.  Lanes with one column probe the same slots in
+      // lockstep, so exactly one of them inserts it.
       if (valid) {
-        const uint64_t key = table ? (((uint64_t)lane << 32) | (uint32_t)col) : col;
-        const uint64_t cmp = table ? 0xFFFFFFFFull : ~0ull;  // the bits that hold the column
-        for (int probe = 0; probe < kHashSlots; ++probe) {
-          const uint64_t p =
-              atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
-          isnew = p == kEmpty;
-          owner = isnew ? (uint32_t)lane : (uint32_t)(p >> 32);
-          if (isnew || ((p ^ col) & cmp) == 0) break;
-          slot = (slot + 1) & (kHashSlots - 1);
+        uint64_t p;
+        if (table) {
+          // key: the owner lane above the 32-bit column (never kEmpty)
+          const uint32_t c32 = (uint32_t)col;
+          const uint64_t key = ((uint64_t)lane << 32) | c32;
+          while (true) {
+            p = atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (p == kEmpty || (uint32_t)p == c32) break;
+            slot = (slot + 1) & (kHashSlots - 1);
+          }
+        } else {
+          while (true) {
+            p = atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)col);
+            if (p == kEmpty || p == col) break;
+            slot = (slot + 1) & (kHashSlots - 1);
+          }
         }
+        isnew = p == kEmpty;
+        owner = isnew ? (uint32_t)lane : (uint32_t)(p >> 32);
       }
     } else {
       // The same probing, but a lane that is done moves to its spare slot (past
