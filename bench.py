@@ -881,7 +881,7 @@ def main():
     ap.add_argument("--rp-n", type=int, default=2896, help="side of the Laplacian in the permutation-table leg")
     ap.add_argument("--rp-reps", type=int, default=3, help="repetitions per permutation in that leg (0: skip)")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances in the batched leg (0: skip)")
-    ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the replayed request trace (0: skip the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=3)

@@ -168,22 +168,26 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
       if (NUMERIC) m_off = coff[r];
     }
     uint32_t my_cnt = 0;
-    int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+    // entry window [w0, w0 + 64) of instance w_inst (none before the first row;
+    // entry indexes are 32-bit, so the tests are scalar compares)
+    uint32_t w0 = 0;
     uint32_t w_inst = 0xFFFFFFFFu;
     uint32_t x_len = 0, x_bs = 0;
     uint64_t x_jn = 0;
     double x_av = 0.0;
     uint64_t todo = __ballot(lane < rows && m_sh != kShapeSkip);
     RowProduct<NUMERIC> next;
+    int t_next = 0;
     auto stage = [&](int i) {
       const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
       const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
       const uint32_t xi = readlane_u32(m_in, i);
       const BInst& x = in[xi];
-      if (xi != w_inst || (int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
+      t_next = (int)(e1 - e0);  // at most 64 for the rows of this kernel
+      if (xi != w_inst || e0 - w0 > (uint32_t)(kWave - t_next)) {
         w0 = e0;
         w_inst = xi;
-        const int64_t g = w0 + lane;
+        const int64_t g = (int64_t)w0 + lane;
         if (g < x.eoff + x.nnz_a) {
           x_len = (uint32_t)(poff[g + 1] - poff[g]);
           x_bs = bstart[g];
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
           if (NUMERIC) x_av = x.a_vals[g - x.eoff];
         }
       }
-      window_products<NUMERIC>(x.b_livs, x.b_vals, e0, (int)(e1 - e0), sh, lane, w0, x_len, x_bs, x_jn, x_av,
+      window_products<NUMERIC>(x.b_livs, x.b_vals, e0, t_next, sh, lane, (int64_t)w0, x_len, x_bs, x_jn, x_av,
                                next);
     };
     if (todo) stage(__builtin_ctzll(todo));
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
       const int ent = next.ent;
       const uint64_t col = next.col();
       const double v = next.val();
-      const int t = (int)(readlane_u32(m_s1, i) - readlane_u32(m_s0, i));
+      const int t = t_next;
       const uint64_t np = in[readlane_u32(m_in, i)].np;
       if (todo) stage(__builtin_ctzll(todo));
       RowOut o;
@@ -213,9 +217,12 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void bt_chunk_kernel(
       if (!NUMERIC) {
         if (lane == i) my_cnt = d;
       } else if (o.own) {
-        const uint64_t pos = readlane_u64(m_off, i) + o.rank;
-        out_livs[pos] = o.col + np * readlane_u64(m_id, i);
-        out_vals[pos] = o.val;
+        // scalar row base, 32-bit lane offset (the rank is below 64)
+        const uint64_t r_off = readlane_u64(m_off, i);
+        const uint32_t boff = o.rank * 8u;
+        *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(out_livs + r_off) + boff) =
+            o.col + np * readlane_u64(m_id, i);
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(out_vals + r_off) + boff) = o.val;
       }
     }
     if (!NUMERIC && lane < rows) cnt[r0 + lane] = my_cnt;

@@ -280,18 +280,24 @@ __device__ __forceinline__ void p_chunk(const PArgs& g, const PInst& x, int inst
     m_sh = sh;
   }
   uint32_t my_cnt = 0;
-  int64_t w0 = -(int64_t)kWave - 1;  // no window yet
+  // entry window [w0, w0 + 64) (none before the first row; entry indexes are
+  // 32-bit, so the tests are scalar compares)
+  bool have = false;
+  uint32_t w0 = 0;
   uint32_t x_len = 0, x_bs = 0;
   uint64_t x_jn = 0;
   double x_av = 0.0;
   uint64_t todo = __ballot(lane < rows && m_sh <= kShapeSearch);
   RowProduct<NUMERIC> next;
+  int t_next = 0;
   auto stage = [&](int i) {
     const uint8_t sh = (uint8_t)readlane_u32(m_sh, i);
     const uint32_t e0 = readlane_u32(m_s0, i), e1 = readlane_u32(m_s1, i);
-    if ((int64_t)e0 < w0 || (int64_t)e1 > w0 + kWave) {
+    t_next = (int)(e1 - e0);  // at most 64 for the rows of this engine
+    if (!have || e0 - w0 > (uint32_t)(kWave - t_next)) {
+      have = true;
       w0 = e0;
-      const int64_t e = w0 + lane;
+      const int64_t e = (int64_t)w0 + lane;
       if (e < x.nnz_a) {
         x_len = elen[e];
         x_bs = bst[e];
@@ -301,7 +307,8 @@ __device__ __forceinline__ void p_chunk(const PArgs& g, const PInst& x, int inst
         if (NUMERIC) x_av = x.a_vals[e];
       }
     }
-    window_products<NUMERIC>(x.b_livs, x.b_vals, e0, (int)(e1 - e0), sh, lane, w0, x_len, x_bs, x_jn, x_av, next);
+    window_products<NUMERIC>(x.b_livs, x.b_vals, e0, t_next, sh, lane, (int64_t)w0, x_len, x_bs, x_jn, x_av,
+                             next);
   };
   if (todo) stage(__builtin_ctzll(todo));
   const bool narrow = NARROW || x.np < (1ull << 32);
@@ -312,16 +319,19 @@ __device__ __forceinline__ void p_chunk(const PArgs& g, const PInst& x, int inst
     const int ent = next.ent;
     const uint64_t col = next.col();
     const double v = next.val();
-    const int t = (int)(readlane_u32(m_s1, i) - readlane_u32(m_s0, i));
+    const int t = t_next;
     if (todo) stage(__builtin_ctzll(todo));
     RowOut o;
     const uint32_t d = row_reduce<ACC, NUMERIC>(valid, ent, col, v, t, narrow, lane, L, o);
     if (!NUMERIC) {
       if (lane == i) my_cnt = d;
     } else if (o.own) {
-      const uint64_t pos = readlane_u64(m_off, i) + o.rank;
-      g.out_livs[pos] = o.col + x.np * (r0 + (uint64_t)i);
-      g.out_vals[pos] = o.val;
+      // scalar row base, 32-bit lane offset (the rank is below 64)
+      const uint64_t r_off = readlane_u64(m_off, i);
+      const uint32_t boff = o.rank * 8u;
+      *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(g.out_livs + r_off) + boff) =
+          o.col + x.np * (r0 + (uint64_t)i);
+      *reinterpret_cast<double*>(reinterpret_cast<char*>(g.out_vals + r_off) + boff) = o.val;
     }
   }
   if (!NUMERIC) {
