@@ -119,9 +119,7 @@ __device__ __forceinline__ bool small_row(uint64_t f, uint32_t t) {
 }
 
 // LDS of one wave of the one-wave-per-row kernels.  The hash table has
-// kHashSlots slots; in the symbolic pass, one spare slot per lane follows
-// them, which a lane that has finished probing keeps probing while other lanes
-// still search.
+// kHashSlots slots.
 // Numeric: a row with at most kTabEntries entries and 32-bit columns sums
 // through the table tab[entry][owner number], which is all +0.0 between rows;
 // other accumulator rows use the lane masks and staged values that share its
@@ -132,8 +130,8 @@ struct RowLds;
 template <>
 struct alignas(16) RowLds<false> {
   union {
-    uint64_t hash[kHashSlots + kWave];    // columns
-    uint32_t hash32[kHashSlots + kWave];  // 32-bit columns
+    uint64_t hash[kHashSlots];    // columns
+    uint32_t hash32[kHashSlots];  // 32-bit columns
   };
 };
 template <>
@@ -337,32 +335,31 @@ __device__ __forceinline__ uint32_t row_reduce(bool valid, int ent, uint64_t col
         owner = isnew ? (uint32_t)lane : (uint32_t)(p >> 32);
       }
     } else {
-      // The same probing, but a lane that is done moves to its spare slot (past
-      // the table), and the wave leaves the loop together once no lane is still
-      // probing: fewer scalar instructions than a divergent loop.
-      const uint32_t spare = kHashSlots + lane;
-      uint32_t at = valid ? slot : spare;
-      if (key32) {
-        const uint32_t c32 = (uint32_t)col;
-        for (int probe = 0; probe <= kHashSlots; ++probe) {
-          const uint32_t p = atomicCAS(&L.hash32[at], 0xFFFFFFFFu, c32);
-          const bool live = at < kHashSlots;
-          const bool fresh = live && p == 0xFFFFFFFFu;
-          const bool hit = fresh || (live && p == c32);
-          isnew = isnew || fresh;
-          at = hit ? spare : live ? ((at + 1) & (kHashSlots - 1)) : at;
-          if (!__any(at < kHashSlots)) break;
-        }
-      } else {
-        for (int probe = 0; probe <= kHashSlots; ++probe) {
-          const uint64_t p =
-              atomicCAS((unsigned long long*)&L.hash[at], (unsigned long long)kEmpty, (unsigned long long)col);
-          const bool live = at < kHashSlots;
-          const bool fresh = live && p == kEmpty;
-          const bool hit = fresh || (live && p == col);
-          isnew = isnew || fresh;
-          at = hit ? spare : live ? ((at + 1) & (kHashSlots - 1)) : at;
-          if (!__any(at < kHashSlots)) break;
+      // The same probing as the numeric pass, with only the column stored
+      // (32-bit columns in 32-bit slots).
+      if (valid) {
+        if (key32) {
+          const uint32_t c32 = (uint32_t)col;
+          while (true) {
+            const uint32_t p = atomicCAS(&L.hash32[slot], 0xFFFFFFFFu, c32);
+            if (p == 0xFFFFFFFFu) {
+              isnew = true;
+              break;
+            }
+            if (p == c32) break;
+            slot = (slot + 1) & (kHashSlots - 1);
+          }
+        } else {
+          while (true) {
+            const uint64_t p =
+                atomicCAS((unsigned long long*)&L.hash[slot], (unsigned long long)kEmpty, (unsigned long long)col);
+            if (p == kEmpty) {
+              isnew = true;
+              break;
+            }
+            if (p == col) break;
+            slot = (slot + 1) & (kHashSlots - 1);
+          }
         }
       }
     }
