@@ -273,6 +273,69 @@ def test_long_rows_every_bin(lco_lib, gpu_ctx, oracle_mod, wide):
         t.destroy()
 
 
+def _colliding_columns(n_cols, wide, slot, count, rng):
+    """`count` distinct columns below n_cols that the row passes' LDS hash sends to
+    one home slot: Fibonacci hashing of the column (32-bit product for columns
+    below 2^32, 64-bit otherwise), top 7 bits."""
+    out = np.zeros(0, dtype=np.uint64)
+    while len(out) < count:
+        c = np.unique(rng.integers(0, n_cols, 1 << 16, dtype=np.uint64))
+        if wide:
+            h = (c * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(57)
+        else:
+            h = ((c * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(25)
+        out = np.union1d(out, c[h == np.uint64(slot)])
+    return rng.permutation(out)[:count]
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_row_hash_collisions(lco_lib, gpu_ctx, oracle_mod, wide):
+    """Rows whose columns all share one home slot of the row passes' 128-slot LDS
+    hash (and rows that mix two neighbouring home slots), so that probe runs
+    reach 64 slots: table rows of 2 and 7 entries (up to 64 distinct columns),
+    rows of 16 entries, search-shaped rows, and entries that repeat each other's
+    columns (lanes holding one column probe in lockstep and exactly one inserts
+    it).  Exact against the oracle under CSR, DCSR, CSRNA and the automatic
+    choice; with 2^40 columns the hash is the 64-bit one and no row is a table
+    row."""
+    rng = np.random.default_rng(2024 + int(wide))
+    n_cols = (1 << 40) if wide else (1 << 20)
+    s5 = _colliding_columns(n_cols, wide, 5, 64, rng)
+    s6 = _colliding_columns(n_cols, wide, 6, 32, rng)
+    b_rows = {
+        0: s5[0:32], 1: s5[16:48], 2: s5[32:64], 3: np.concatenate([s6[0:16], s5[0:16]]),
+    }
+    for j in range(4, 12):  # rows of 8, overlapping by half
+        b_rows[j] = s5[4 * (j - 4):4 * (j - 4) + 8]
+    for j in range(12, 28):  # rows of 4
+        b_rows[j] = np.concatenate([s5[2 * (j - 12):2 * (j - 12) + 2], s6[2 * (j - 12) % 32:2 * (j - 12) % 32 + 2]])
+    both = np.concatenate([s5, s6])
+    for j, ln in zip(range(28, 33), (20, 3, 17, 1, 23)):  # uneven rows: the search shape
+        b_rows[j] = rng.choice(both, ln, replace=False)
+    k = 40
+    cb = np.array([(j, int(c)) for j in sorted(b_rows) for c in np.sort(b_rows[j])], dtype=np.uint64)
+    vb = rng.uniform(-1, 1, len(cb))
+    a_sets = [[0, 1], [0, 2], [1, 3], [2, 3], list(range(4, 11)), list(range(12, 28)), list(range(28, 33)),
+              [0], [3, 30], list(range(4, 12)) + [0]]
+    ca = np.array([(i, j) for i, js in enumerate(a_sets) for j in js], dtype=np.uint64)
+    va = rng.uniform(-1, 1, len(ca))
+    if wide:  # column c -> coordinates (c mod 2^20, c div 2^20)
+        dims_b = [k, 1 << 20, 1 << 20]
+        cbc = np.stack([cb[:, 0], cb[:, 1] % np.uint64(1 << 20), cb[:, 1] // np.uint64(1 << 20)], axis=1)
+        lb, lc = [1, 2, 3], [0, 2, 3]
+    else:
+        dims_b = [k, n_cols]
+        cbc = cb
+        lb, lc = [1, 2], [0, 2]
+    ga, oa = pair(lco_lib, gpu_ctx, oracle_mod, [len(a_sets), k], ca, va)
+    gb, ob = pair(lco_lib, gpu_ctx, oracle_mod, dims_b, cbc, vb)
+    ref = run_all(lco_lib, gpu_ctx, oracle_mod, ga, oa, [0, 1], gb, ob, lb, lc, exact=True,
+                  algos=("auto", "CSR", "DCSR", "CSRNA"))
+    assert ref.nnz == sum(len(np.unique(np.concatenate([b_rows[j] for j in js]))) for js in a_sets)
+    for t in (ga, gb):
+        t.destroy()
+
+
 def test_row_classes_mixed(lco_lib, gpu_ctx, oracle_mod):
     """Every row class of the row engine in one product: single-entry rows whose
     B' row is short or long (more than 64 products: the scaled-copy class),
