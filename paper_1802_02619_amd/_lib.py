@@ -195,6 +195,21 @@ def _i32arr(xs):
     return (ctypes.c_int * max(1, len(xs)))(*xs)
 
 
+# Label and permutation lists repeat from call to call: their int arrays are
+# kept (the library only reads them during a call), bounded in number.
+_LABEL_ARRAYS = {}
+
+
+def _labels(xs):
+    k = tuple(xs)
+    a = _LABEL_ARRAYS.get(k)
+    if a is None:
+        if len(_LABEL_ARRAYS) >= 4096:
+            _LABEL_ARRAYS.clear()
+        a = _LABEL_ARRAYS[k] = _i32arr(k)
+    return a
+
+
 def lco_version() -> str:
     return load_library().lco_version().decode()
 
@@ -369,7 +384,7 @@ def lco_read(t: Tensor):
 def lco_permute(ctx: Context, t: Tensor, perm) -> Tensor:
     L = load_library()
     h = ctypes.c_void_p()
-    _check(L.lco_permute(ctx.handle, t.handle, _i32arr(perm), ctypes.byref(h)))
+    _check(L.lco_permute(ctx.handle, t.handle, _labels(perm), ctypes.byref(h)))
     return Tensor(ctx, h)
 
 
@@ -389,8 +404,8 @@ def lco_permute_noalloc(ctx: Context, t: Tensor, perm, out_livs, out_vals):
 def lco_contract(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, flags: int = 0) -> Tensor:
     L = load_library()
     h = ctypes.c_void_p()
-    _check(L.lco_contract(ctx.handle, a.handle, _i32arr(a_labels), b.handle, _i32arr(b_labels), len(c_labels),
-                          _i32arr(c_labels), int(flags), ctypes.byref(h)))
+    _check(L.lco_contract(ctx.handle, a.handle, _labels(a_labels), b.handle, _labels(b_labels), len(c_labels),
+                          _labels(c_labels), int(flags), ctypes.byref(h)))
     return Tensor(ctx, h)
 
 
@@ -441,8 +456,8 @@ def lco_add(ctx: Context, a: Tensor, a_labels, b: Tensor, b_labels, c_labels, al
     """c = alpha*a + beta*b over the same labelled modes (output mode order: c_labels)."""
     L = load_library()
     h = ctypes.c_void_p()
-    _check(L.lco_add(ctx.handle, float(alpha), a.handle, _i32arr(a_labels), float(beta), b.handle,
-                     _i32arr(b_labels), _i32arr(c_labels), ctypes.byref(h)))
+    _check(L.lco_add(ctx.handle, float(alpha), a.handle, _labels(a_labels), float(beta), b.handle,
+                     _labels(b_labels), _labels(c_labels), ctypes.byref(h)))
     return Tensor(ctx, h)
 
 
