@@ -337,7 +337,9 @@ __global__ __launch_bounds__(kClassifyThreads) void row_classify_kernel(
 // the rows of A' (heads, a block scan, compaction), the row pointers of B',
 // each A' entry's product count and B' row start, and the row classes.  The
 // kernel writes its counters itself: words[0] rows of A', [1] long rows, [2..4]
-// some row is tiny / a copy / of the one-wave kernel.
+// some row is tiny / a copy / of the one-wave kernel.  It also clears the
+// per-row output counts cnt[0..nnz_A] (at least as many as there are rows), so
+// that the symbolic pass can follow without the row count on the host.
 constexpr int kSetupThreads = 1024;
 constexpr int64_t kClassMinEntries = 65536;  // A' entries from which the tiny and copy classes are used
 constexpr int64_t kSetupMaxEntries = 16384;
@@ -347,12 +349,13 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
     RowArgs ra, FastDiv ndiv, bool classes, uint32_t* __restrict__ row_start, uint64_t* __restrict__ row_id,
     uint64_t* __restrict__ words, uint32_t* __restrict__ bptr, uint32_t* __restrict__ elen,
     uint32_t* __restrict__ bstart, uint32_t* __restrict__ list2, uint64_t* __restrict__ f2,
-    uint8_t* __restrict__ shape) {
+    uint8_t* __restrict__ shape, uint64_t* __restrict__ cnt) {
   __shared__ uint32_t wsum[kSetupThreads / kWave + 1];
   __shared__ uint32_t s_cnt[4];  // long rows, tiny, copy, wave
   const int64_t na = ra.nnz_a, nb = ra.nnz_b;
   const int tid = threadIdx.x;
   if (tid < 4) s_cnt[tid] = 0;
+  for (int64_t i = tid; i <= na; i += kSetupThreads) cnt[i] = 0;
   // row pointers of B'
   for (int64_t e = tid; e <= nb; e += kSetupThreads) {
     const uint64_t lo = e == 0 ? 0 : fd_div(ndiv, ra.b_livs[e - 1]) + 1;
@@ -416,7 +419,8 @@ __global__ __launch_bounds__(kSetupThreads) void row_setup_small_kernel(
 // (rows are consecutive, so their entries are too).  The symbolic pass is held
 // to 8 waves per SIMD (64 VGPRs) and the numeric pass to 6 (80 VGPRs), the
 // fastest bounds measured.  NARROW: columns below 2^32 (n' < 2^32), fixed at
-// compile time so that the width is no per-row branch.
+// compile time so that the width is no per-row branch.  With `nzr_dev` the
+// row count is the smaller of `nzr` (an upper bound) and *nzr_dev.
 constexpr int kChunkRows = kWave;
 
 template <bool ACC, bool NUMERIC, bool NARROW>
@@ -425,8 +429,10 @@ __global__ __launch_bounds__(kRowThreads, NUMERIC ? 6 : 8) void row_chunk_kernel
                                                                 uint64_t* __restrict__ cnt,
                                                                 const uint64_t* __restrict__ coff,
                                                                 uint64_t* __restrict__ out_livs,
-                                                                double* __restrict__ out_vals) {
+                                                                double* __restrict__ out_vals,
+                                                                const uint64_t* __restrict__ nzr_dev) {
   __shared__ RowLds<NUMERIC> s_lds[kRowWaves];
+  if (nzr_dev && *nzr_dev < (uint64_t)nzr) nzr = (uint32_t)*nzr_dev;
   const int w = threadIdx.x / kWave, lane = lane_id();
   constexpr bool narrow = NARROW;  // columns below 2^32 (n' < 2^32)
   const uint64_t nchunks = ((uint64_t)nzr + chunk_rows - 1) / chunk_rows;
@@ -1105,7 +1111,40 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
   uint8_t* shape = s.get<uint8_t>(rows_cap);
   ra.bstart = bstart;
   ra.elen = len;
+  const bool narrow = np < (1ull << 32);
+  // rows per chunk: up to 64, but enough chunks for every resident wave (32 per compute unit)
+  auto chunk_rows_for = [&](uint64_t rows) {
+    const uint64_t resident = (uint64_t)ctx->num_cus * 32;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(kChunkRows, rows / resident));
+  };
+  auto small_grid_for = [&](uint64_t rows, int chunk) {
+    const uint64_t nchunks = (rows + chunk - 1) / chunk;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((nchunks + kRowWaves - 1) / kRowWaves,
+                                                         (uint64_t)ctx->num_cus * 16));
+  };
+#define LCO_ROW_SMALL_N(GRID, NUM, NARROW, ...)                                                                  \
+  do {                                                                                                           \
+    if (acc)                                                                                                     \
+      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<true, NUM, NARROW>), GRID,       \
+                 kRowThreads, 0, __VA_ARGS__);                                                                   \
+    else                                                                                                         \
+      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM, NARROW>), GRID,      \
+                 kRowThreads, 0, __VA_ARGS__);                                                                   \
+  } while (0)
+#define LCO_ROW_SMALL(GRID, NUM, ...)                          \
+  do {                                                         \
+    if (narrow) LCO_ROW_SMALL_N(GRID, NUM, true, __VA_ARGS__); \
+    else LCO_ROW_SMALL_N(GRID, NUM, false, __VA_ARGS__);       \
+  } while (0)
   const uint64_t* h;
+  // Small products: the symbolic pass of the one-wave rows and the scan of the
+  // row counts follow the setup over at most nnz_A rows (the row count stays on
+  // the device), so that one host synchronisation serves the setup and the
+  // output size when there are no long rows.
+  uint64_t* cnt = nullptr;
+  uint64_t* coff = nullptr;
+  bool counted = false;
+  uint64_t counted_total = 0;
   if (small) {
     // rows of A', row pointers of B', entry lengths and row classes in one launch
     uint32_t* row_start = s.get<uint32_t>(na + 1);
@@ -1116,10 +1155,19 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     ra.row_id = row_id;
     ra.nzr_a = words;
     ra.bptr = bptr;
+    cnt = s.get<uint64_t>(na + 1);
+    coff = s.get<uint64_t>(na + 1);
     LCO_LAUNCH(ctx, "row_setup_small", row_setup_small_kernel, 1, kSetupThreads, 0, ra, ndiv, classes, row_start,
-               row_id, words, bptr, len, bstart, list2, f2, shape);
-    const uint64_t* rb1[5] = {words, words + 1, words + 2, words + 3, words + 4};
-    h = readback(ctx, rb1, 5);
+               row_id, words, bptr, len, bstart, list2, f2, shape, cnt);
+    const int spec_chunk = chunk_rows_for((uint64_t)na);
+    LCO_ROW_SMALL(small_grid_for((uint64_t)na, spec_chunk), false, ra, (uint32_t)na, spec_chunk,
+                  (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr,
+                  (const uint64_t*)words);
+    scan_u64(ctx, cnt, coff, na, coff + na);
+    const uint64_t* rb1[6] = {words, words + 1, words + 2, words + 3, words + 4, coff + na};
+    h = readback(ctx, rb1, 6);
+    counted = true;
+    counted_total = h[5];
   } else {
     // compressed B'
     if (dense) {
@@ -1219,34 +1267,17 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
     mid_total = h2[1];
     for (int b = 0; b < kMidBins; ++b) nbin[b] = h2[2 + b];
   }
-  // per-row output counts
-  uint64_t* cnt = s.get<uint64_t>(nzr + 1);
-  uint64_t* coff = s.get<uint64_t>(nzr + 1);
-  if (!wave) memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));  // else the one-wave kernel writes every count
-  // rows per chunk: up to 64, but enough chunks for every resident wave (32 per compute unit)
-  const uint64_t resident = (uint64_t)ctx->num_cus * 32;
-  const int chunk_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>(kChunkRows, nzr / resident));
-  const uint64_t nchunks = (nzr + chunk_rows - 1) / chunk_rows;
-  const int small_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((nchunks + kRowWaves - 1) / kRowWaves,
-                                                                       (uint64_t)ctx->num_cus * 16));
-  const bool narrow = np < (1ull << 32);
-#define LCO_ROW_SMALL_N(NUM, NARROW, ...)                                                                        \
-  do {                                                                                                           \
-    if (acc)                                                                                                     \
-      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<true, NUM, NARROW>), small_grid, \
-                 kRowThreads, 0, __VA_ARGS__);                                                                   \
-    else                                                                                                         \
-      LCO_LAUNCH(ctx, NUM ? "row_small_num" : "row_small_sym", (row_chunk_kernel<false, NUM, NARROW>),           \
-                 small_grid, kRowThreads, 0, __VA_ARGS__);                                                       \
-  } while (0)
-#define LCO_ROW_SMALL(NUM, ...)                      \
-  do {                                               \
-    if (narrow) LCO_ROW_SMALL_N(NUM, true, __VA_ARGS__); \
-    else LCO_ROW_SMALL_N(NUM, false, __VA_ARGS__);   \
-  } while (0)
-  if (wave)
-    LCO_ROW_SMALL(false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt, (const uint64_t*)nullptr,
-                  (uint64_t*)nullptr, (double*)nullptr);
+  // per-row output counts (already cleared and, for the one-wave rows, written on small products)
+  if (!counted) {
+    cnt = s.get<uint64_t>(nzr + 1);
+    coff = s.get<uint64_t>(nzr + 1);
+    if (!wave) memset_async(ctx, cnt, 0, (nzr + 1) * sizeof(uint64_t));  // else the one-wave kernel writes every count
+  }
+  const int chunk_rows = chunk_rows_for(nzr);
+  const int small_grid = small_grid_for(nzr, chunk_rows);
+  if (wave && !counted)
+    LCO_ROW_SMALL(small_grid, false, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, cnt,
+                  (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr, (const uint64_t*)nullptr);
   if (tiny)
     LCO_LAUNCH(ctx, "row_tiny_sym", row_tiny_kernel<false>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
                (const uint8_t*)shape, cnt, (const uint64_t*)nullptr, (uint64_t*)nullptr, (double*)nullptr);
@@ -1294,15 +1325,18 @@ lco_tensor row_engine(lco_ctx ctx, const lco_tensor_s* A, const lco_tensor_s* B,
                off2, (const uint64_t*)keys, (const double*)pvals, colmask, cnt, (const uint64_t*)nullptr,
                (uint64_t*)nullptr, (double*)nullptr);
   }
-  scan_u64(ctx, cnt, coff, nzr, coff + nzr);
-  const uint64_t* rb2[1] = {coff + nzr};
-  const uint64_t nnz_c = readback(ctx, rb2, 1)[0];
+  uint64_t nnz_c = counted_total;
+  if (!counted || n2 || tiny || copy) {  // counts written after the first scan: scan again
+    scan_u64(ctx, cnt, coff, nzr, coff + nzr);
+    const uint64_t* rb2[1] = {coff + nzr};
+    nnz_c = readback(ctx, rb2, 1)[0];
+  }
   if (nnz_c > UINT32_MAX) fail(LCO_E_UNSUPPORTED, "contract: more than 2^32-1 output entries");
   lco_tensor C = new_tensor(ctx, out_order, out_dims, (int64_t)nnz_c);
   try {
     if (wave)
-      LCO_ROW_SMALL(true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr,
-                    (const uint64_t*)coff, C->livs, C->vals);
+      LCO_ROW_SMALL(small_grid, true, ra, (uint32_t)nzr, chunk_rows, (const uint8_t*)shape, (uint64_t*)nullptr,
+                    (const uint64_t*)coff, C->livs, C->vals, (const uint64_t*)nullptr);
     if (tiny)
       LCO_LAUNCH(ctx, "row_tiny_num", row_tiny_kernel<true>, tiny_grid, 256, 0, ra, (uint32_t)nzr,
                  (const uint8_t*)shape, (uint64_t*)nullptr, (const uint64_t*)coff, C->livs, C->vals);
