@@ -91,7 +91,9 @@ lco_status lco_ctx_destroy(lco_ctx ctx);
 /* Redirect subsequent work of the context to another stream of the same device
  * (waits for the old stream first). */
 lco_status lco_ctx_set_stream(lco_ctx ctx, void* hip_stream);
-/* Block until all work enqueued by the context has finished. */
+/* Block until all work enqueued by the context has finished: the host spins
+ * for up to 20 ms, then waits in a stream synchronisation.  Reports an error
+ * that a kernel recorded (LCO_E_HIP otherwise). */
 lco_status lco_ctx_synchronize(lco_ctx ctx);
 
 /* Crossovers of the selector.  The paper's table (Section 5.2) picks a cell

@@ -240,10 +240,17 @@ class Context:
             self.handle = h
             return
 
+        self._stream_handle = int(stream.cuda_stream)
+
         def _alloc(user, nbytes, strm):
             try:
-                with torch.cuda.stream(self.stream):
+                # torch's allocator ties a block to the current stream: allocate on the context's stream
+                # (entering a stream context only when another stream is current)
+                if torch.cuda.current_stream(self._dev).cuda_stream == self._stream_handle:
                     t = torch.empty(int(nbytes), dtype=torch.uint8, device=self._dev)
+                else:
+                    with torch.cuda.stream(self.stream):
+                        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self._dev)
                 p = t.data_ptr()
                 self._allocs[p] = t
                 return p
@@ -267,6 +274,7 @@ class Context:
         """Move the context's later work to another torch stream of its device (waits for the old one)."""
         _check(load_library().lco_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
         self.stream = stream
+        self._stream_handle = int(stream.cuda_stream)
 
     def destroy(self):
         if self.handle:
