@@ -251,3 +251,22 @@ def test_crossover_constants_match_header(lib):
     assert got == lib.MI355X_CROSSOVERS
     assert re.search(r"#define LCO_MI355X_INDEX_ALGORITHM LCO_ALG_(\w+)", hdr).group(1) == lib.MI355X_INDEX_ALGORITHM
     assert lib.PAPER_CROSSOVERS == (3.0, 3.0, 3.0)
+
+
+def test_binding_label_arrays_are_kept_and_bounded():
+    """The binding keeps one int array per distinct label list: equal lists (as list,
+    tuple or numpy array) share it, distinct lists get their own with the right
+    contents, and the store is emptied once it holds 4096 lists."""
+    from paper_1802_02619_amd import _lib
+    _lib._LABEL_ARRAYS.clear()
+    a = _lib._labels([0, 1, 2, 3])
+    assert list(a) == [0, 1, 2, 3]
+    assert _lib._labels((0, 1, 2, 3)) is a
+    assert _lib._labels(np.array([0, 1, 2, 3], dtype=np.int64)) is a
+    b = _lib._labels([3, 2, 1, 0])
+    assert b is not a and list(b) == [3, 2, 1, 0] and list(a) == [0, 1, 2, 3]
+    assert len(_lib._labels([])) == 1  # an empty list passes a valid one-element array
+    for i in range(5000):
+        assert list(_lib._labels([i, i + 1])) == [i, i + 1]
+    assert len(_lib._LABEL_ARRAYS) <= 4096
+    _lib._LABEL_ARRAYS.clear()
